@@ -1,0 +1,125 @@
+"""Benchmark of the MPS lattice Boltzmann step on one MI355X.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload porous64]
+
+A step is one full D3Q19 MPS-LBM step (moments, 1/rho, variational
+products, BGK sums, streaming, open faces, bounce-back, all roundings) on
+the synthetic workload, inputs resident in HBM.  Prints one JSON line.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MPS-LBM steps/s & equiv. MLUPS at fixed chi vs plain FP64 path; MFMA util"
+
+# MI355X published peaks
+PEAK = {"hbm_gbs": 8000.0, "fp64_tflops": 78.6, "fp32_tflops": 157.3, "bf16_tflops": 2500.0}
+
+
+def make_case(name):
+    import workloads as WL
+    if name == "porous64":
+        # 64^3 random spheres (radius 4-8, 30 % solid), pressure-driven in x,
+        # chi = 64, FP32 (the structured porous medium configuration)
+        return WL.case_porous(n=6, chi=64, tau=0.6, tol=1e-8, precision="fp32")
+    if name == "porous32":
+        return WL.case_porous(n=5, chi=32, tau=0.6, tol=1e-8, precision="fp32")
+    if name == "channel16":
+        return WL.case_channel()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(case, budget_s=30.0):
+    """Time the CPU oracle (FP64 MPS path, same schedule) on a bounded
+    sample: initialisation excluded, as many whole steps as fit the budget
+    (at least one)."""
+    import numpy as np  # noqa: F401
+    from oracle.mps_lbm import MPSLBM
+    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
+    m = MPSLBM(case)
+    t0 = time.perf_counter()
+    k = 0
+    while True:
+        m.step()
+        k += 1
+        if time.perf_counter() - t0 > budget_s or k >= 3:
+            break
+    dt = (time.perf_counter() - t0) / k
+    return {"value": 1.0 / dt, "unit": "steps/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": f"{k} step(s) of the CPU FP64 MPS oracle on {case.name} "
+                      f"(chi={case.chi}), initialisation excluded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="porous64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--fp64-steps", type=int, default=3)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU only (N=1); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2512_07615_amd import mps_lbm as L
+
+    case = make_case(args.workload)
+    stream = torch.cuda.Stream()
+    sim = L.Simulation(case, hip_stream=stream.cuda_stream)
+    for _ in range(args.warmup):
+        sim.step(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        sim.step(1)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    obs = sim.observables()
+    sps = 1000.0 / ms
+    N3 = case.N ** 3
+    out = {
+        "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32" if case.precision == "fp32" else "f64", "data": "synthetic",
+        "config": {"workload": case.name, "n": case.n, "chi": case.chi, "tau": case.tau,
+                   "tol": case.tol, "geometry": case.meta,
+                   "equiv_mlups": N3 * sps / 1e6, "max_bond": obs.max_bond,
+                   "mask_bond": obs.mask_bond, "mask_trunc_err": obs.mask_trunc_err,
+                   "roundings_per_step": obs.roundings, "products_per_step": obs.products,
+                   "compression": obs.compression},
+    }
+    sim.close()
+    if args.fp64_steps > 0 and case.precision != "fp64":
+        sim64 = L.Simulation(case, precision="fp64", hip_stream=stream.cuda_stream)
+        sim64.step(1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.fp64_steps):
+            sim64.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms64 = e0.elapsed_time(e1) / args.fp64_steps
+        out["config"]["fp64_steps_per_s"] = 1000.0 / ms64
+        out["config"]["speedup_vs_fp64_path"] = ms64 / ms
+        sim64.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(case)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

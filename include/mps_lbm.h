@@ -1,0 +1,165 @@
+/*
+ * mps_lbm.h - C ABI of the MI355X (gfx950) matrix-product-state lattice
+ * Boltzmann library.
+ *
+ * The library advances a D3Q19 BGK lattice Boltzmann simulation whose 19
+ * particle distribution functions are each held as a matrix product state
+ * (MPS) over scale-ordered grid bits (paper: "Tensor Network Lattice
+ * Boltzmann Method for Data-Compressed Fluid Simulations", Sections 2-3).
+ * All state lives in device memory owned by the handle; every computation
+ * of a step runs in the library's HIP kernels on the handle's stream.
+ *
+ * Conventions for every entry point:
+ *  - Dense fields are C-order FP64 arrays indexed [x][y][z] (x slowest),
+ *    side N = 2^n; vector fields are [3][N][N][N]; population arrays are
+ *    [19][N][N][N] in the D3Q19 order: rest, +x,-x, +y,-y, +z,-z, then the
+ *    twelve edges as opposite pairs (+x+y,-x-y), (+x-y,-x+y), (+x+z,-x-z),
+ *    (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z).
+ *  - Host buffers are owned by the caller; the library copies inputs during
+ *    the call and writes only into the output buffer it is given.
+ *  - Return value 0 is success; negative values are the MPS_LBM_E* codes
+ *    below.  On error nothing is written to outputs and
+ *    mps_lbm_last_error() returns a message (thread-local).  No C++
+ *    exception crosses this interface.
+ *  - A handle must not be used from two threads at once.
+ */
+#ifndef MPS_LBM_H
+#define MPS_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MPS_LBM_OK 0
+#define MPS_LBM_EINVAL (-1)       /* bad argument or configuration        */
+#define MPS_LBM_ENOMEM (-2)       /* device allocation failed             */
+#define MPS_LBM_EHIP (-3)         /* a HIP runtime call failed            */
+#define MPS_LBM_ENUMERIC (-4)     /* NaN/Inf or SVD non-convergence       */
+#define MPS_LBM_EUNSUPPORTED (-5) /* valid but not implemented            */
+
+#define MPS_LBM_D3Q19 19
+
+/* arithmetic of the step (storage and contractions); the R-factor SVDs,
+   rank selection and 1/rho coefficients are FP64 under every policy */
+#define MPS_LBM_FP64 0
+#define MPS_LBM_FP32 1
+
+/* inverse density: second-order Taylor expansion about the mean density
+   rho_0 (Section 3.2), or k Newton-Schulz steps from 1/rho_0 (k steps equal
+   the Taylor expansion of order 2^k - 1) */
+#define MPS_LBM_INV_TAYLOR2 0
+#define MPS_LBM_INV_NEWTON 1
+
+/* face boundary types for non-periodic axes (Section 3.2.1) */
+#define MPS_LBM_BC_NONE 0
+#define MPS_LBM_BC_VELOCITY 1 /* bounce-back with wall velocity u_b, rho_b = rho_0 */
+#define MPS_LBM_BC_PRESSURE 2 /* anti-bounce-back with density rho_b, u_b = local u */
+
+/* what mps_lbm_to_dense writes */
+#define MPS_LBM_POPS 0 /* [19][N][N][N] populations                       */
+#define MPS_LBM_RHO 1  /* [N][N][N]     rho = sum_i f_i                     */
+#define MPS_LBM_J 2    /* [3][N][N][N]  j = sum_i c_i f_i                   */
+#define MPS_LBM_VEL 3  /* [3][N][N][N]  u = j / rho (0 where rho = 0)       */
+
+#define MPS_LBM_MAX_SITES 10 /* n <= 10 (N <= 1024)                        */
+
+typedef struct mps_lbm mps_lbm_t; /* opaque handle; owns all device state */
+
+typedef struct {
+  int n;            /* N = 2^n cells per axis, 2 <= n <= MPS_LBM_MAX_SITES */
+  int lattice;      /* MPS_LBM_D3Q19                                      */
+  int chi_max;      /* bond dimension cap of every population MPS, >= 1    */
+  int chi_mask_max; /* cap of the obstacle-mask MPS; <= 0 means no cap     */
+  double tol;       /* relative Frobenius truncation tolerance of a rounding */
+  double tol_mask;  /* truncation tolerance of the mask decomposition      */
+  double tau;       /* BGK relaxation time, > 1/2                          */
+  double g[3];      /* body acceleration; force density F = rho g          */
+  int inv_rho_mode; /* MPS_LBM_INV_TAYLOR2 | MPS_LBM_INV_NEWTON            */
+  int inv_rho_iters;/* Newton-Schulz steps (>= 1) when mode is NEWTON      */
+  int precision;    /* MPS_LBM_FP64 | MPS_LBM_FP32                         */
+  int sweeps;       /* variational-product sweeps 1->n->1 (the paper: 2)   */
+  int axis_open[3]; /* 0 = periodic (cyclic shift), 1 = open (non-cyclic)  */
+  int face_bc[6];   /* faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi            */
+  double face_val[6][3]; /* velocity faces: u_b; pressure faces: {rho_b,0,0} */
+  unsigned long long seed; /* reserved for randomized sketches            */
+} mps_lbm_config;
+
+typedef struct {
+  long long step;          /* steps taken since init                       */
+  double mass;             /* <1, rho> = sum_i <1, f_i>                     */
+  double momentum[3];      /* sum_i c_i <1, f_i>                            */
+  double rho0;             /* mean fluid density used by the last step      */
+  double n_fluid;          /* N^3 - <1, m_O>                                */
+  int max_bond;            /* largest bond over the 19 populations          */
+  int bonds[19][MPS_LBM_MAX_SITES]; /* bond dims r_1..r_{n-1} per population */
+  double nvps;             /* sum over populations of the core entries in use */
+  double compression;      /* 19 N^3 / nvps                                 */
+  double max_discarded;    /* largest relative discarded weight of a rounding
+                              in the last step                              */
+  int mask_bond;           /* largest bond of the obstacle-mask MPS          */
+  double mask_trunc_err;   /* ||m - m~|| / ||m|| of the mask decomposition   */
+  long long roundings;     /* roundings in the last step                    */
+  long long products;      /* variational products in the last step         */
+  int svd_failures;        /* Jacobi SVDs that hit the sweep limit (total)   */
+  int nonfinite;           /* 1 if a NaN/Inf was seen in the state           */
+} mps_lbm_obs;
+
+/* Fill *cfg with defaults: D3Q19, FP64, TAYLOR2, 2 sweeps, tol 1e-10,
+   tol_mask 1e-12, tau 0.8, periodic, no force, chi_max 16. */
+void mps_lbm_default_config(mps_lbm_config* cfg);
+
+/*
+ * Create a simulation.  Initial populations are the equilibrium
+ * f_i = (1 - m_O) w_i rho (1 + 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u)
+ * of the given rho [N][N][N] and u [3][N][N][N] (equilibrium equation),
+ * or, when f is non-NULL, the given populations [19][N][N][N] (rho and u
+ * are then ignored and may be NULL).  solid [N][N][N] (1 = solid) defines
+ * the obstacle mask m_O (Section 3.2.1, objects equation); NULL = none.
+ * Each field is decomposed into an MPS by successive truncated SVDs
+ * (Section 2.1, svd-comp equation) on the device.  hip_stream is the
+ * hipStream_t every later call of this handle runs on (NULL = default).
+ * Errors: EINVAL (n out of range, chi_max < 1, tau <= 1/2, unknown lattice,
+ * precision, BC or inverse mode, missing fields), ENOMEM, EHIP.
+ */
+int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho,
+                            const double* u, const double* f,
+                            const uint8_t* solid, void* hip_stream,
+                            mps_lbm_t** out);
+
+/*
+ * Advance nsteps lattice Boltzmann steps (Section 3.2): moments,
+ * 1/rho approximation, equilibrium by variational Hadamard products
+ * (Section 2.3), BGK relaxation, streaming by shift MPOs (Section 2.5),
+ * open-face boundary terms and masked bounce-back, every sum followed by
+ * rounding to chi_max.  Runs asynchronously on the handle's stream with
+ * no host synchronisation.  Errors: EINVAL (NULL handle, nsteps < 0), EHIP.
+ */
+int mps_lbm_step(mps_lbm_t* h, int nsteps);
+
+/*
+ * Contract the state to a dense host array (synchronises the stream).
+ * what = MPS_LBM_POPS | RHO | J | VEL; out_len is the number of doubles
+ * available at out.  Errors: EINVAL (bad what, out_len too small), EHIP.
+ */
+int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len);
+
+/* Scalar observables (synchronises the stream). */
+int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
+
+/* Release every device buffer of the handle; NULL is ignored. */
+void mps_lbm_destroy(mps_lbm_t* h);
+
+/* Message of the last error on this thread ("" if none). */
+const char* mps_lbm_last_error(void);
+
+/* Library version string. */
+const char* mps_lbm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPS_LBM_H */

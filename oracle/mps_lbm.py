@@ -64,13 +64,16 @@ class MPSLBM:
         self.cnt = Counters()
         n = self.n
         self.one = M.ones(n)
-        chi_mask = case.chi_mask if case.chi_mask is not None else 1 << 30
+        # the mask rank is capped at the flow bond dimension chi (products with
+        # the mask run at the candidate's bonds, and chi_mask <= chi keeps every
+        # operand within the same capacity)
+        chi_mask = min(case.chi_mask if case.chi_mask else 1 << 30, self.chi)
         if case.solid is not None:
             self.mask = M.from_dense(case.solid.astype(np.float64), n, chi_mask,
                                      case.tol_mask)
             self.n_fluid = float(self.N ** 3) - M.inner_ones(self.mask)
             fluid_mps = M.round_mps(M.add(self.one, M.scale(self.mask, -1.0)),
-                                    1 << 30, case.tol_mask)
+                                    self.chi, case.tol_mask)
         else:
             self.mask = None
             self.n_fluid = float(self.N ** 3)

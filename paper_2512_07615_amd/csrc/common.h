@@ -1,0 +1,92 @@
+// Shared device/host definitions of the MPS-LBM library (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include <stdexcept>
+#include <string>
+
+namespace mpslbm {
+
+constexpr int MAXN = 10;     // maximum number of sites (N <= 1024)
+constexpr int PHYS = 8;      // physical dimension of a site (x, y, z bits)
+constexpr int WG = 256;      // threads per workgroup for the batched kernels
+constexpr int MAXB = 64;     // maximum batch of a single launch
+
+// Error carried through the host code as an exception (never crosses the ABI).
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_OK(expr)                                                              \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess)                                                         \
+      throw ::mpslbm::Error(-3, std::string(#expr) + ": " + hipGetErrorString(_e)); \
+  } while (0)
+
+// Device-resident descriptor of one MPS.  Core k (0-based) is stored packed,
+// row-major with shape (r[k], 8, r[k+1]) at data + off[k]; the space reserved
+// for it is cap[k] * 8 * cap[k+1] elements.  Ranks are updated on the device
+// by the truncation kernels, so the host never needs to read them in a step.
+template <typename T>
+struct MpsDev {
+  T* data;
+  long off[MAXN];
+  int cap[MAXN + 1];
+  int r[MAXN + 1];
+  int n;
+  int pad;
+};
+
+template <typename T>
+struct MpsList {
+  MpsDev<T>* p[MAXB];
+};
+
+// Coefficient a * rho0^p where rho0 is a device scalar (p in {-2..1}).
+struct Coef {
+  double a;
+  int p;
+};
+
+__host__ __device__ inline double coef_value(Coef c, const double* rho0) {
+  if (c.p == 0) return c.a;
+  double r = rho0[0];
+  switch (c.p) {
+    case 1: return c.a * r;
+    case -1: return c.a / r;
+    case -2: return c.a / (r * r);
+    default: return c.a;
+  }
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum for a 256-thread workgroup; `red` has >= 4 entries.
+__device__ inline double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+inline int ceil_div(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace mpslbm

@@ -1,0 +1,1058 @@
+// Host orchestration of the MPS-LBM operations on one GPU.
+//
+// Every operation is a short sequence of batched kernel launches on the
+// engine's stream.  Bond dimensions live in device memory (MpsDev::r), so
+// launches are sized by the host-known capacities and an operation never
+// waits for the device.  MPS objects come from a pool of capacity-sized
+// buffers and are referred to by pool index on the host.
+#pragma once
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "linalg.h"
+#include "mpsops.h"
+
+namespace mpslbm {
+
+// D3Q19 velocity set (rest, 6 axis, 12 edge velocities as opposite pairs)
+static const int kC[19][3] = {
+    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},   {0, 0, -1},
+    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
+    {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+static const int kOpp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
+static inline double kW(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+
+template <typename T>
+struct Mps {
+  MpsDev<T>* dev = nullptr;
+  T* data = nullptr;
+  int n = 0;
+  int cap[MAXN + 1];
+  long off[MAXN];
+  long total = 0;
+};
+
+template <typename T>
+__device__ inline int max_bond(const MpsDev<T>* m) {
+  int b = 1;
+  for (int k = 1; k < m->n; ++k) b = m->r[k] > b ? m->r[k] : b;
+  return b;
+}
+
+// Product factor order: the factor with the larger maximum bond is the
+// candidate (the "first factor" of the variational product); ties keep the
+// written order.
+template <typename T>
+__device__ inline void prod_order(MpsDev<T>* x, MpsDev<T>* y, MpsDev<T>** B, MpsDev<T>** C) {
+  if (max_bond(y) > max_bond(x)) {
+    *B = y;
+    *C = x;
+  } else {
+    *B = x;
+    *C = y;
+  }
+}
+
+// ============================================================================
+// QR problem functors
+// left unfolding of core k: m = 8 r_k, s = r_{k+1}
+template <typename T>
+struct FnQrLeft {
+  MpsList<T> L; int k; T* qout; long qslot; double* rout; long rslot;
+  __device__ QrProb<T> get(int i) const {
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q;
+    q.A = core_ptr(m, k);
+    q.m = PHYS * m->r[k];
+    q.s = m->r[k + 1];
+    q.sAm = q.s; q.sAk = 1;
+    q.p = 0; q.valid = 1;
+    q.Q = qout + i * qslot;
+    q.R = rout + i * rslot;
+    return q;
+  }
+};
+// transpose of the right unfolding of core k: m = 8 r_{k+1}, s = r_k
+template <typename T>
+struct FnQrRightT {
+  MpsList<T> L; int k; T* qout; long qslot; double* rout; long rslot;
+  __device__ QrProb<T> get(int i) const {
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q;
+    q.A = core_ptr(m, k);
+    q.m = PHYS * m->r[k + 1];
+    q.s = m->r[k];
+    q.sAm = 1; q.sAk = q.m;
+    q.p = 0; q.valid = 1;
+    q.Q = qout + i * qslot;
+    q.R = rout + i * rslot;
+    return q;
+  }
+};
+// dense matrix problems (initial decomposition): A_i = base + i*stride, m x s row-major
+template <typename T>
+struct FnQrDense {
+  const T* A; long astride; int m, s; T* qout; long qslot; double* rout; long rslot;
+  __device__ QrProb<T> get(int i) const {
+    QrProb<T> q;
+    q.A = A + i * astride;
+    q.m = m; q.s = s; q.sAm = s; q.sAk = 1;
+    q.p = 0; q.valid = 1;
+    q.Q = qout + i * qslot;
+    q.R = rout + i * rslot;
+    return q;
+  }
+};
+
+template <typename T>
+__global__ void k_qr_copy_sq(const QrProb<T>* qp, const double* src, double* dst, long sq) {
+  QrProb<T> q = qp[blockIdx.y];
+  if (!q.valid || q.m <= q.s) return;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < q.s * q.s; e += gridDim.x * blockDim.x)
+    dst[blockIdx.y * sq + e] = src[blockIdx.y * sq + e];
+}
+
+// rank updates after a QR of a core: left form r_{k+1} = p, right form r_k = p
+template <typename T>
+__global__ void k_set_rank_from_qr(MpsList<T> L, const QrProb<T>* qp, int bond, int cnt) {
+  int i = threadIdx.x;
+  if (i < cnt) L.p[i]->r[bond] = qp[i].p;
+}
+
+// ============================================================================
+// GEMM functors of the rounding sweep
+// tmp = R (p x s) * core_{k+1} (s x 8 r_{k+2})
+template <typename T>
+struct FnRTimesCore {
+  MpsList<T> L; const QrProb<T>* qp; T* tmp; long slot; int k;
+  __device__ GemmDesc<double, T, T> get(int i) const {
+    GemmDesc<double, T, T> d = gemm_empty<double, T, T>();
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q = qp[i];
+    int s = q.s, p = q.p, rr = m->r[k + 2];
+    d.A = q.R; d.B = core_ptr(m, k + 1); d.C = tmp + i * slot;
+    d.M = p; d.N = PHYS * rr; d.K = s;
+    d.sAm = s; d.sAk = 1; d.sBk = PHYS * rr; d.sBn = 1; d.sCm = PHYS * rr; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+// tmp = core_{k-1} ((r_{k-1} 8) x s) * X (s x r), X = US (rounding) or R'^T (canonicalisation)
+template <typename T>
+struct FnCoreTimesUS {
+  MpsList<T> L; const QrProb<T>* qp; const double* US; long sus; T* tmp; long slot; int k;
+  __device__ GemmDesc<T, double, T> get(int i) const {
+    GemmDesc<T, double, T> d = gemm_empty<T, double, T>();
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q = qp[i];
+    int s = q.s, r = m->r[k], rl = m->r[k - 1];
+    d.A = core_ptr(m, k - 1); d.B = US + i * sus; d.C = tmp + i * slot;
+    d.M = rl * PHYS; d.N = r; d.K = s;
+    d.sAm = s; d.sAk = 1; d.sBk = r; d.sBn = 1; d.sCm = r; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+struct FnCoreTimesRt {
+  MpsList<T> L; const QrProb<T>* qp; T* tmp; long slot; int k;
+  __device__ GemmDesc<T, double, T> get(int i) const {
+    GemmDesc<T, double, T> d = gemm_empty<T, double, T>();
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q = qp[i];
+    int s = q.s, p = q.p, rl = m->r[k - 1];
+    d.A = core_ptr(m, k - 1); d.B = q.R; d.C = tmp + i * slot;
+    d.M = rl * PHYS; d.N = p; d.K = s;
+    d.sAm = s; d.sAk = 1; d.sBk = 1; d.sBn = s; d.sCm = p; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+// core_k = Wk^T (r x p) * Q'^T (p x 8 r_{k+1})
+template <typename T>
+struct FnWtQt {
+  MpsList<T> L; const QrProb<T>* qp; const double* Wk; long swk; int k;
+  __device__ GemmDesc<double, T, T> get(int i) const {
+    GemmDesc<double, T, T> d = gemm_empty<double, T, T>();
+    MpsDev<T>* m = L.p[i];
+    QrProb<T> q = qp[i];
+    int r = m->r[k], p = q.p, mm = q.m;
+    d.A = Wk + i * swk; d.B = q.Q; d.C = core_ptr(m, k);
+    d.M = r; d.N = mm; d.K = p;
+    d.sAm = 1; d.sAk = r; d.sBk = 1; d.sBn = p; d.sCm = mm; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+
+// SVD problem of the truncation step: L = R'^T (rows s, cols p) is R' read
+// column-major; delta2 and the rank slot come from the MPS of entry i.
+template <typename T>
+struct FnSvdTrunc {
+  MpsList<T> L; const QrProb<T>* qp; int k; double* W; long sw; double* US; double* Wk;
+  long sus; const double* delta2; double* disc; int chi; int* fail; double* spectra;
+  long sstride;
+  __device__ SvdProb get(int i) const {
+    QrProb<T> q = qp[i];
+    SvdProb p;
+    p.L = q.R; p.W = W + i * sw;
+    p.rows = q.s; p.cols = q.p; p.valid = 1;
+    p.delta2 = delta2[i]; p.chi = chi;
+    p.rank_out = &L.p[i]->r[k];
+    p.US = US + i * sus; p.Wk = Wk + i * sus;
+    p.sv = spectra ? spectra + i * sstride : nullptr;
+    p.disc = disc + i * (MAXN + 1) + k;
+    p.fail = fail;
+    return p;
+  }
+};
+
+__global__ void k_round_finish(const double* disc, const double* norm2, double* stats, int cnt) {
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < cnt; ++i) {
+    double s = 0.0;
+    for (int k = 0; k <= MAXN; ++k) s += disc[i * (MAXN + 1) + k];
+    double ratio = norm2[i] > 0.0 ? s / norm2[i] : 0.0;
+    if (ratio > stats[0]) stats[0] = ratio;
+  }
+}
+
+// store the transposed Q' (m x p) as core k (p x m)
+template <typename T>
+__global__ void k_store_core_T(MpsList<T> L, const QrProb<T>* qp, int k) {
+  int i = blockIdx.y;
+  QrProb<T> q = qp[i];
+  T* o = core_ptr(L.p[i], k);
+  long tot = (long)q.m * q.p;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    int j = (int)(e / q.m), r = (int)(e % q.m);
+    o[e] = q.Q[(long)r * q.p + j];
+  }
+}
+
+// ============================================================================
+// Variational product functors (Section 2.3).  Environments:
+//  Lenv[k] (rD_k, rB_k, rC_k): sites 0..k-1 contracted;  Renv[k]: sites k..n-1.
+// Local optimum at site p:  A_p = sum L[a,b,c] B[b,s,b'] C[c,s,c'] R[a',b',c']
+//  G1: T1[a][c][s][b'] = sum_b L[a][b][c] B[b][s][b']       (batched over a)
+//  G2: T2[a][s][b'][c'] = sum_c T1[a][c][s][b'] C[c][s][c']  (batched over a, s)
+//  G3: A[a][s][a'] = sum_{b'c'} T2[a][s][b'c'] R[a'][b'c']
+// Left environment after the centre moves right (reuses T2 of site p):
+//  G3L: Lenv[p+1][a'][b'c'] = sum_{a s} A[a][s][a'] T2[a][s][b'c']
+// Right environment after the centre moves left:
+//  H1: U1[a'][c'][b s] = sum_{b'} R[a'][b'][c'] B[b][s][b']  (batched over a')
+//  H2: U2[s][a'][b][c] = sum_{c'} U1[a'][c'][b s] C[c][s][c'] (batched over s, a')
+//  H3: Renv[p][a][b c] = sum_{s a'} A[a][s][a'] U2[s][a'][b c]
+template <typename T>
+struct ProdCtx {
+  MpsList<T> D, X, Y;
+  T* envL; T* envR; long envcap;
+  T* T1; T* T2; long tcap; int nsl;
+  __device__ void get(int i, MpsDev<T>** d, MpsDev<T>** b, MpsDev<T>** c) const {
+    *d = D.p[i];
+    prod_order(X.p[i], Y.p[i], b, c);
+  }
+  __device__ T* L(int i, int k) const { return envL + ((long)i * nsl + k) * envcap; }
+  __device__ T* R(int i, int k) const { return envR + ((long)i * nsl + k) * envcap; }
+};
+
+template <typename T, typename Tacc>
+struct FnG1 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a = D->r[p], b = B->r[p], cc = C->r[p], b2 = B->r[p + 1];
+    g.A = c.L(i, p); g.B = core_ptr(B, p); g.C = c.T1 + i * c.tcap;
+    g.M = cc; g.N = PHYS * b2; g.K = b; g.nb1 = a; g.nb2 = 1;
+    g.sAm = 1; g.sAk = cc; g.bA1 = (long)b * cc;
+    g.sBk = PHYS * b2; g.sBn = 1;
+    g.sCm = PHYS * b2; g.sCn = 1; g.bC1 = (long)cc * PHYS * b2;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnG2 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a = D->r[p], cc = C->r[p], b2 = B->r[p + 1], c2 = C->r[p + 1];
+    g.A = c.T1 + i * c.tcap; g.B = core_ptr(C, p); g.C = c.T2 + i * c.tcap;
+    g.M = b2; g.N = c2; g.K = cc; g.nb1 = PHYS; g.nb2 = a;
+    g.sAm = 1; g.sAk = PHYS * b2; g.bA1 = b2; g.bA2 = (long)cc * PHYS * b2;
+    g.sBk = PHYS * c2; g.sBn = 1; g.bB1 = c2; g.bB2 = 0;
+    g.sCm = c2; g.sCn = 1; g.bC1 = (long)b2 * c2; g.bC2 = (long)PHYS * b2 * c2;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnG3 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a = D->r[p], a2 = D->r[p + 1], b2 = B->r[p + 1], c2 = C->r[p + 1];
+    g.A = c.T2 + i * c.tcap; g.B = c.R(i, p + 1); g.C = core_ptr(D, p);
+    g.M = PHYS * a; g.N = a2; g.K = b2 * c2;
+    g.sAm = (long)b2 * c2; g.sAk = 1; g.sBk = 1; g.sBn = (long)b2 * c2;
+    g.sCm = a2; g.sCn = 1;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnG3L {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a = D->r[p], a2 = D->r[p + 1], b2 = B->r[p + 1], c2 = C->r[p + 1];
+    g.A = core_ptr(D, p); g.B = c.T2 + i * c.tcap; g.C = c.L(i, p + 1);
+    g.M = a2; g.N = b2 * c2; g.K = PHYS * a;
+    g.sAm = 1; g.sAk = a2; g.sBk = (long)b2 * c2; g.sBn = 1;
+    g.sCm = (long)b2 * c2; g.sCn = 1;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnH1 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a2 = D->r[p + 1], b = B->r[p], b2 = B->r[p + 1], c2 = C->r[p + 1];
+    g.A = c.R(i, p + 1); g.B = core_ptr(B, p); g.C = c.T1 + i * c.tcap;
+    g.M = c2; g.N = PHYS * b; g.K = b2; g.nb1 = a2; g.nb2 = 1;
+    g.sAm = 1; g.sAk = c2; g.bA1 = (long)b2 * c2;
+    g.sBk = 1; g.sBn = b2;
+    g.sCm = PHYS * b; g.sCn = 1; g.bC1 = (long)c2 * PHYS * b;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnH2 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a2 = D->r[p + 1], b = B->r[p], cc = C->r[p], c2 = C->r[p + 1];
+    g.A = c.T1 + i * c.tcap; g.B = core_ptr(C, p); g.C = c.T2 + i * c.tcap;
+    g.M = b; g.N = cc; g.K = c2; g.nb1 = PHYS; g.nb2 = a2;
+    g.sAm = PHYS; g.sAk = PHYS * b; g.bA1 = 1; g.bA2 = (long)c2 * PHYS * b;
+    g.sBk = 1; g.sBn = PHYS * c2; g.bB1 = c2; g.bB2 = 0;
+    g.sCm = cc; g.sCn = 1; g.bC1 = (long)a2 * b * cc; g.bC2 = (long)b * cc;
+    g.valid = 1;
+    return g;
+  }
+};
+template <typename T, typename Tacc>
+struct FnH3 {
+  ProdCtx<T> c; int p;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>*D, *B, *C;
+    c.get(i, &D, &B, &C);
+    int a = D->r[p], a2 = D->r[p + 1], b = B->r[p], cc = C->r[p];
+    g.A = core_ptr(D, p); g.B = c.T2 + i * c.tcap; g.C = c.R(i, p);
+    g.M = a; g.N = b * cc; g.K = PHYS * a2;
+    g.sAm = PHYS * a2; g.sAk = 1; g.sBk = (long)b * cc; g.sBn = 1;
+    g.sCm = (long)b * cc; g.sCn = 1;
+    g.valid = 1;
+    return g;
+  }
+};
+
+// D <- copy of the candidate factor; environment boundaries = 1
+template <typename T>
+__global__ void k_prod_init(ProdCtx<T> c, int n) {
+  int i = blockIdx.y, k = blockIdx.x;
+  MpsDev<T>*D, *B, *C;
+  c.get(i, &D, &B, &C);
+  if (k == 0 && threadIdx.x == 0) {
+    for (int j = 0; j <= n; ++j) D->r[j] = B->r[j];
+    c.L(i, 0)[0] = (T)1;
+    c.R(i, n)[0] = (T)1;
+  }
+  if (k >= n) return;
+  long tot = (long)B->r[k] * PHYS * B->r[k + 1];
+  const T* s = core_ptr(B, k);
+  T* o = core_ptr(D, k);
+  for (long e = threadIdx.x; e < tot; e += blockDim.x) o[e] = s[e];
+}
+
+// ============================================================================
+// dense-contraction functor: T_{k+1} (rows x 8 r_{k+1}) = T_k (rows x r_k) * core_k
+template <typename T>
+struct FnContract {
+  MpsList<T> L; const T* in; T* out; long slot; long rows; int k;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    MpsDev<T>* m = L.p[i];
+    int rl = m->r[k], rr = m->r[k + 1];
+    g.A = in + i * slot; g.B = core_ptr(m, k); g.C = out + i * slot;
+    g.M = (int)rows; g.N = PHYS * rr; g.K = rl;
+    g.sAm = rl; g.sAk = 1; g.sBk = PHYS * rr; g.sBn = 1; g.sCm = PHYS * rr; g.sCn = 1;
+    g.valid = 1;
+    return g;
+  }
+};
+
+// initial decomposition functors (shapes host-known)
+template <typename T>
+struct FnDense {
+  const T* A; long sa; const T* B; long sb; T* C; long sc;
+  int M, N, K; long sAm, sAk, sBk, sBn;
+  __device__ GemmDesc<T, T, T> get(int i) const {
+    GemmDesc<T, T, T> g = gemm_empty<T, T, T>();
+    g.A = A + i * sa; g.B = B + i * sb; g.C = C + i * sc;
+    g.M = M; g.N = N; g.K = K;
+    g.sAm = sAm; g.sAk = sAk; g.sBk = sBk; g.sBn = sBn; g.sCm = N; g.sCn = 1;
+    g.valid = 1;
+    return g;
+  }
+};
+
+template <typename T>
+__global__ void k_set_identity_core(MpsList<T> L, int k, int m) {
+  int i = blockIdx.y;
+  T* o = core_ptr(L.p[i], k);
+  long tot = (long)m * m;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x)
+    o[e] = (e / m == e % m) ? (T)1 : (T)0;
+}
+
+template <typename T>
+__global__ void k_set_ranks(MpsList<T> L, RankArr r, int cnt) {
+  int i = threadIdx.x;
+  if (i >= cnt) return;
+  for (int k = 0; k <= L.p[i]->n; ++k) L.p[i]->r[k] = r.r[k];
+}
+
+template <typename T>
+__global__ void k_copy_plain(const T* src, T* dst, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    dst[e] = src[e];
+}
+
+template <typename T>
+__global__ void k_moments_dense(const T* f, double* out, long N3, int what, const int* cvec) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
+       e += (long)gridDim.x * blockDim.x) {
+    double rho = 0, jx = 0, jy = 0, jz = 0;
+    for (int i = 0; i < 19; ++i) {
+      double v = (double)f[i * N3 + e];
+      rho += v;
+      jx += cvec[3 * i] * v;
+      jy += cvec[3 * i + 1] * v;
+      jz += cvec[3 * i + 2] * v;
+    }
+    if (what == 1) {
+      out[e] = rho;
+    } else {
+      double s = 1.0;
+      if (what == 3) s = (rho != 0.0) ? 1.0 / rho : 0.0;
+      out[e] = jx * s;
+      out[N3 + e] = jy * s;
+      out[2 * N3 + e] = jz * s;
+    }
+  }
+}
+
+__global__ void k_div_scalar(const double* a, double b, double* out) {
+  if (threadIdx.x == 0) out[0] = a[0] / b;
+}
+
+// ============================================================================
+template <typename T>
+class Engine {
+ public:
+  typedef T Tacc;
+  int n = 0, chi = 1;
+  double tol = 0.0;
+  hipStream_t st = nullptr;
+  int capb[MAXN + 1];  // capacity bond of pooled MPS: 2 min(chi, full-rank bound)
+  int cpb[MAXN + 1];   // bond bound of rounded MPS: min(chi, full-rank bound)
+  int maxbond = 1;
+  long maxcore = 0;
+  long envcap = 0, tcap = 0;
+  int lds_elems = 8000;
+  std::vector<Mps<T>> pool;
+  std::vector<int> freelist;
+  std::vector<void*> allocs;
+  QrProb<T>* qp = nullptr;
+  QrWork qw;
+  T* qtmp = nullptr;
+  double* rbuf = nullptr;
+  long qslot = 0, rslot = 0;
+  T* ctmp = nullptr;
+  SvdProb* sp = nullptr;
+  double* svdW = nullptr;
+  double* svdUS = nullptr;
+  double* svdWk = nullptr;
+  long sw = 0, sus = 0;
+  double* rdelta = nullptr;
+  double* rnorm = nullptr;
+  double* rdisc = nullptr;
+  double* stats = nullptr;  // [0] max discarded ratio of the current step
+  int* istats = nullptr;    // [0] SVD sweep-limit hits, [1] non-finite flag
+  T* envL = nullptr;
+  T* envR = nullptr;
+  T* T1 = nullptr;
+  T* T2 = nullptr;
+  int pbatch = 1;
+  int sweeps = 2;
+  long roundings = 0, products = 0;
+
+  void* dalloc(size_t bytes) {
+    void* p = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    }
+    allocs.push_back(p);
+    return p;
+  }
+  ~Engine() {
+    for (void* p : allocs) (void)hipFree(p);
+  }
+
+  static int full_bound(int n, int k) {
+    long a = 1, b = 1;
+    for (int j = 0; j < k && a < (1 << 20); ++j) a *= 8;
+    for (int j = 0; j < n - k && b < (1 << 20); ++j) b *= 8;
+    long m = a < b ? a : b;
+    return (int)(m > (1 << 20) ? (1 << 20) : m);
+  }
+
+  void setup(int n_, int chi_, double tol_, hipStream_t s, int npool, int pbatch_) {
+    n = n_; chi = chi_; tol = tol_; st = s; pbatch = pbatch_;
+    capb[0] = capb[n] = 1;
+    cpb[0] = cpb[n] = 1;
+    maxbond = 1;
+    for (int k = 1; k < n; ++k) {
+      int fb = full_bound(n, k);
+      cpb[k] = std::min(chi, fb);
+      capb[k] = 2 * cpb[k];
+      maxbond = std::max(maxbond, capb[k]);
+    }
+    maxcore = 0;
+    for (int k = 0; k < n; ++k) maxcore = std::max(maxcore, (long)capb[k] * PHYS * capb[k + 1]);
+    int dev = 0, lds = 0;
+    HIP_OK(hipGetDevice(&dev));
+    HIP_OK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    long want = std::min<long>(lds, 147456) - 16384;
+    lds_elems = (int)std::max<long>(want / 8, 1024);
+    if (hipFuncSetAttribute((const void*)k_jacobi_svd, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_householder<T>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess) {
+      (void)hipGetLastError();
+      lds_elems = (65536 - 16384) / 8;
+    }
+    for (int i = 0; i < npool; ++i) pool.push_back(make_mps(capb));
+    freelist.clear();
+    for (int i = npool - 1; i >= 0; --i) freelist.push_back(i);
+    int scap = maxbond, mcap = PHYS * maxbond;
+    qp = (QrProb<T>*)dalloc(sizeof(QrProb<T>) * MAXB);
+    long sq = (long)scap * scap, mq = (long)mcap * scap;
+    qw.sq = sq; qw.mq = mq;
+    qw.G = (double*)dalloc(8 * sq * MAXB);
+    qw.R1 = (double*)dalloc(8 * sq * MAXB);
+    qw.Racc = (double*)dalloc(8 * sq * MAXB);
+    qw.Rt = (double*)dalloc(8 * sq * MAXB);
+    qw.Rinv = (double*)dalloc(8 * sq * MAXB);
+    qw.Q1 = (double*)dalloc(8 * mq * MAXB);
+    qw.Q2 = (double*)dalloc(8 * mq * MAXB);
+    qslot = mq;  // Q is m x p with p <= s
+    rslot = sq;  // R is p x s; in the m <= s case it is m x s with m <= s
+    qtmp = (T*)dalloc(sizeof(T) * qslot * MAXB);
+    rbuf = (double*)dalloc(8 * rslot * MAXB);
+    ctmp = (T*)dalloc(sizeof(T) * maxcore * MAXB);
+    sp = (SvdProb*)dalloc(sizeof(SvdProb) * MAXB);
+    sw = sq;   // W is p x p
+    sus = sq;  // US is s x r, Wk is p x r
+    svdW = (double*)dalloc(8 * sw * MAXB);
+    svdUS = (double*)dalloc(8 * sus * MAXB);
+    svdWk = (double*)dalloc(8 * sus * MAXB);
+    rdelta = (double*)dalloc(8 * MAXB);
+    rnorm = (double*)dalloc(8 * MAXB);
+    rdisc = (double*)dalloc(8 * MAXB * (MAXN + 1));
+    stats = (double*)dalloc(8 * 16);
+    istats = (int*)dalloc(4 * 16);
+    HIP_OK(hipMemsetAsync(stats, 0, 8 * 16, st));
+    HIP_OK(hipMemsetAsync(istats, 0, 4 * 16, st));
+    long ec = 1, tc = 1;
+    for (int k = 0; k <= n; ++k) {
+      long b = cpb[k];
+      ec = std::max(ec, b * b * b);
+    }
+    for (int k = 0; k < n; ++k) {
+      long a = cpb[k], a2 = cpb[k + 1];
+      tc = std::max(tc, std::max(a * a * PHYS * a2, PHYS * a * a2 * a2));
+    }
+    envcap = ec;
+    tcap = tc;
+    envL = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
+    envR = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
+    T1 = (T*)dalloc(sizeof(T) * tcap * pbatch);
+    T2 = (T*)dalloc(sizeof(T) * tcap * pbatch);
+  }
+
+  Mps<T> make_mps(const int* cap) {
+    Mps<T> m;
+    m.n = n;
+    long off = 0;
+    for (int k = 0; k <= n; ++k) m.cap[k] = cap[k];
+    for (int k = 0; k < n; ++k) {
+      m.off[k] = off;
+      off += (long)cap[k] * PHYS * cap[k + 1];
+    }
+    m.total = off;
+    m.data = (T*)dalloc(sizeof(T) * off);
+    m.dev = (MpsDev<T>*)dalloc(sizeof(MpsDev<T>));
+    MpsDev<T> h;
+    memset(&h, 0, sizeof(h));
+    h.data = m.data;
+    h.n = n;
+    for (int k = 0; k < n; ++k) h.off[k] = m.off[k];
+    for (int k = 0; k <= n; ++k) {
+      h.cap[k] = cap[k];
+      h.r[k] = 1;
+    }
+    HIP_OK(hipMemcpy(m.dev, &h, sizeof(h), hipMemcpyHostToDevice));
+    HIP_OK(hipMemset(m.data, 0, sizeof(T) * off));
+    return m;
+  }
+
+  int acquire() {
+    if (freelist.empty()) throw Error(-2, "MPS pool exhausted");
+    int i = freelist.back();
+    freelist.pop_back();
+    return i;
+  }
+  void release(int i) {
+    if (i >= 0) freelist.push_back(i);
+  }
+  MpsDev<T>* D(int i) const { return pool[i].dev; }
+  // grid-stride chunks for kernels walking one core of capacity size
+  int chunks() const { return (int)std::max<long>(1, std::min<long>(64, (maxcore + 255) / 256)); }
+  int chunks_q() const {
+    long e = (long)PHYS * maxbond * maxbond;
+    return (int)std::max<long>(1, std::min<long>(64, (e + 255) / 256));
+  }
+
+  MpsList<T> list_idx(const std::vector<int>& v, size_t off, int cnt) const {
+    MpsList<T> l;
+    memset(&l, 0, sizeof(l));
+    for (int i = 0; i < cnt; ++i) l.p[i] = D(v[off + i]);
+    return l;
+  }
+
+  // ------------------------------------------------------------ QR op
+  template <typename F>
+  void qr(const F& f, int nprob, int mcap, int scap) {
+    if (nprob <= 0) return;
+    hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob);
+    hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
+                       (const QrProb<T>*)qp);
+    hipLaunchKernelGGL(k_householder<T>, dim3(nprob), dim3(256), (size_t)lds_elems * 8, st,
+                       (const QrProb<T>*)qp, qw, lds_elems);
+    HIP_OK(hipGetLastError());
+  }
+
+  // ------------------------------------------------------------ rounding
+  // Rounding (TT-rounding as a centre sweep): QR orthogonalisation from the
+  // left moves the centre to the last site; truncated SVDs then shift it
+  // back to the first site (svd-move equation), truncating only at the
+  // centre with per-bond threshold tol^2 ||X||^2 / (n - 1) and rank cap chi.
+  void round(const std::vector<int>& X, int chi_cap = -1, double tol_r = -1.0) {
+    if (chi_cap < 0) chi_cap = chi;
+    if (tol_r < 0) tol_r = tol;
+    for (size_t off = 0; off < X.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, X.size() - off);
+      round_list(list_idx(X, off, cnt), cnt, chi_cap, tol_r);
+    }
+  }
+
+  void round_list(MpsList<T> L, int cnt, int chi_cap, double tol_r) {
+    roundings += cnt;
+    dim3 blk(256);
+    for (int k = 0; k < n - 1; ++k) {
+      int mcap = capb[k] * PHYS, scap = capb[k + 1];
+      qr(FnQrLeft<T>{L, k, qtmp, qslot, rbuf, rslot}, cnt, mcap, scap);
+      launch_gemm<double, T, T, double>(FnRTimesCore<T>{L, qp, ctmp, maxcore, k}, cnt, scap,
+                                        PHYS * capb[k + 2], 1, st);
+      hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, L,
+                         (const QrProb<T>*)qp, k + 1, cnt);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)qtmp, qslot, k);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp, maxcore,
+                         k + 1);
+    }
+    hipLaunchKernelGGL(k_round_threshold<T>, dim3(cnt), blk, 0, st, L, tol_r, rdelta, rnorm, cnt);
+    HIP_OK(hipMemsetAsync(rdisc, 0, 8 * MAXB * (MAXN + 1), st));
+    for (int k = n - 1; k >= 1; --k) {
+      int mcap = PHYS * capb[k + 1], scap = capb[k];
+      qr(FnQrRightT<T>{L, k, qtmp, qslot, rbuf, rslot}, cnt, mcap, scap);
+      hipLaunchKernelGGL(k_svd_prep<FnSvdTrunc<T>>, dim3(1), dim3(64), 0, st,
+                         FnSvdTrunc<T>{L, (const QrProb<T>*)qp, k, svdW, sw, svdUS, svdWk, sus,
+                                       rdelta, rdisc, chi_cap, istats, nullptr, 0},
+                         sp, cnt);
+      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), blk, (size_t)lds_elems * 8, st,
+                         (const SvdProb*)sp, lds_elems, 40);
+      launch_gemm<T, double, T, double>(FnCoreTimesUS<T>{L, qp, svdUS, sus, ctmp, maxcore, k},
+                                        cnt, capb[k - 1] * PHYS, scap, 1, st);
+      launch_gemm<double, T, T, double>(FnWtQt<T>{L, qp, svdWk, sus, k}, cnt, scap, mcap, 1, st);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp, maxcore,
+                         k - 1);
+    }
+    hipLaunchKernelGGL(k_round_finish, dim3(1), dim3(64), 0, st, (const double*)rdisc,
+                       (const double*)rnorm, stats, cnt);
+    HIP_OK(hipGetLastError());
+  }
+
+  // ------------------------------------------------------------ additions
+  // dst_i = c2i * a_i + c2i+1 * b_i (block-diagonal cores)
+  void add(const std::vector<int>& dst, const std::vector<int>& a, const std::vector<int>& b,
+           const std::vector<Coef>& coefs, const double* rho0) {
+    const int per = MAXB / 2;
+    for (size_t off = 0; off < dst.size(); off += per) {
+      int cnt = (int)std::min<size_t>(per, dst.size() - off);
+      CoefArr ca;
+      memset(&ca, 0, sizeof(ca));
+      for (int i = 0; i < cnt; ++i) {
+        ca.c[2 * i] = coefs[2 * (off + i)];
+        ca.c[2 * i + 1] = coefs[2 * (off + i) + 1];
+      }
+      hipLaunchKernelGGL(k_add<T>, dim3(chunks(), n, cnt), dim3(256), 0, st, list_idx(dst, off, cnt),
+                         list_idx(a, off, cnt), list_idx(b, off, cnt), ca, rho0);
+    }
+    HIP_OK(hipGetLastError());
+  }
+
+  void copy_scaled(const std::vector<int>& dst, const std::vector<int>& src,
+                   const std::vector<Coef>& coefs, const double* rho0) {
+    for (size_t off = 0; off < dst.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, dst.size() - off);
+      CoefArr ca;
+      memset(&ca, 0, sizeof(ca));
+      for (int i = 0; i < cnt; ++i) ca.c[i] = coefs[off + i];
+      hipLaunchKernelGGL(k_copy_scaled<T>, dim3(chunks(), n, cnt), dim3(256), 0, st,
+                         list_idx(dst, off, cnt), list_idx(src, off, cnt), ca, rho0);
+    }
+    HIP_OK(hipGetLastError());
+  }
+
+  struct Term {
+    Coef c;
+    int obj;
+  };
+
+  // Batched sums, each a pairwise tree: adjacent items are added and
+  // rounded level by level, an odd last item is carried up.  Terms with a
+  // zero constant coefficient are dropped.  Returns a fresh object per sum.
+  std::vector<int> sums(const std::vector<std::vector<Term>>& S, const double* rho0) {
+    struct Item {
+      Coef c;
+      int obj;
+      bool owned;
+    };
+    std::vector<std::vector<Item>> items(S.size());
+    for (size_t s = 0; s < S.size(); ++s)
+      for (const Term& t : S[s])
+        if (!(t.c.p == 0 && t.c.a == 0.0)) items[s].push_back({t.c, t.obj, false});
+    for (;;) {
+      std::vector<int> dst, a, b;
+      std::vector<Coef> co;
+      std::vector<std::pair<size_t, size_t>> where;
+      for (size_t s = 0; s < items.size(); ++s) {
+        auto& it = items[s];
+        for (size_t j = 0; j + 1 < it.size(); j += 2) {
+          dst.push_back(acquire());
+          a.push_back(it[j].obj);
+          b.push_back(it[j + 1].obj);
+          co.push_back(it[j].c);
+          co.push_back(it[j + 1].c);
+          where.push_back({s, j});
+        }
+      }
+      if (dst.empty()) break;
+      add(dst, a, b, co, rho0);
+      round(dst);
+      // rebuild item lists
+      size_t q = 0;
+      for (size_t s = 0; s < items.size(); ++s) {
+        auto& it = items[s];
+        if (it.size() < 2) continue;
+        std::vector<Item> nx;
+        for (size_t j = 0; j + 1 < it.size(); j += 2) {
+          if (it[j].owned) release(it[j].obj);
+          if (it[j + 1].owned) release(it[j + 1].obj);
+          nx.push_back({Coef{1.0, 0}, dst[q++], true});
+        }
+        if (it.size() % 2) nx.push_back(it.back());
+        it = nx;
+      }
+    }
+    std::vector<int> out(S.size(), -1);
+    std::vector<int> cd, cs;
+    std::vector<Coef> cc;
+    for (size_t s = 0; s < items.size(); ++s) {
+      auto& it = items[s];
+      if (it.empty()) {
+        int o = acquire();
+        set_zero(o);
+        out[s] = o;
+      } else if (it[0].owned && it[0].c.p == 0 && it[0].c.a == 1.0) {
+        out[s] = it[0].obj;
+      } else {
+        int o = acquire();
+        cd.push_back(o);
+        cs.push_back(it[0].obj);
+        cc.push_back(it[0].c);
+        out[s] = o;
+        if (it[0].owned) release_later_.push_back(it[0].obj);
+      }
+    }
+    if (!cd.empty()) copy_scaled(cd, cs, cc, rho0);
+    for (int o : release_later_) release(o);
+    release_later_.clear();
+    return out;
+  }
+  std::vector<int> release_later_;
+
+  void set_zero(int o) {
+    std::vector<int> v{o};
+    MpsList<T> l = list_idx(v, 0, 1);
+    hipLaunchKernelGGL(k_set_ones<T>, dim3(1), dim3(64), 0, st, l, 1);
+    std::vector<Coef> c{Coef{0.0, 0}};
+    copy_scaled(v, v, c, nullptr);
+  }
+
+  void set_ones(int o) {
+    std::vector<int> v{o};
+    hipLaunchKernelGGL(k_set_ones<T>, dim3(1), dim3(64), 0, st, list_idx(v, 0, 1), 1);
+    HIP_OK(hipGetLastError());
+  }
+
+  // ------------------------------------------------------------ products
+  // Variational compressed Hadamard products (Section 2.3): candidate = the
+  // higher-rank factor, right-canonicalised by QR; environments; sweeps
+  // 1 -> n -> 1 (twice by default) with a QR centre shift after every
+  // local update.
+  std::vector<int> prods(const std::vector<std::pair<int, int>>& P) {
+    std::vector<int> out(P.size());
+    for (size_t i = 0; i < P.size(); ++i) out[i] = acquire();
+    for (size_t off = 0; off < P.size(); off += pbatch) {
+      int cnt = (int)std::min<size_t>(pbatch, P.size() - off);
+      std::vector<int> d(cnt), x(cnt), y(cnt);
+      for (int i = 0; i < cnt; ++i) {
+        d[i] = out[off + i];
+        x[i] = P[off + i].first;
+        y[i] = P[off + i].second;
+      }
+      prod_list(list_idx(d, 0, cnt), list_idx(x, 0, cnt), list_idx(y, 0, cnt), cnt);
+    }
+    return out;
+  }
+
+  void prod_list(MpsList<T> Dl, MpsList<T> Xl, MpsList<T> Yl, int cnt) {
+    products += cnt;
+    ProdCtx<T> c{Dl, Xl, Yl, envL, envR, envcap, T1, T2, tcap, n + 1};
+    dim3 blk(256);
+    hipLaunchKernelGGL(k_prod_init<T>, dim3(n + 1, cnt), blk, 0, st, c, n);
+    // right-canonicalise the candidate
+    for (int k = n - 1; k >= 1; --k) {
+      qr(FnQrRightT<T>{Dl, k, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[k + 1], cpb[k]);
+      launch_gemm<T, double, T, double>(FnCoreTimesRt<T>{Dl, qp, ctmp, maxcore, k}, cnt,
+                                        PHYS * cpb[k - 1], cpb[k], 1, st);
+      hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, Dl,
+                         (const QrProb<T>*)qp, k, cnt);
+      hipLaunchKernelGGL(k_store_core_T<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const QrProb<T>*)qp,
+                         k);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)ctmp, maxcore,
+                         k - 1);
+    }
+    for (int k = n - 1; k >= 1; --k) right_env(c, k, cnt);
+    std::vector<int> pos;
+    for (int k = 0; k < n; ++k) pos.push_back(k);
+    for (int k = n - 2; k >= 0; --k) pos.push_back(k);
+    std::vector<int> one = pos;
+    for (int s = 1; s < sweeps; ++s) pos.insert(pos.end(), one.begin() + 1, one.end());
+    for (size_t idx = 0; idx < pos.size(); ++idx) {
+      int p = pos[idx];
+      local_update(c, p, cnt);
+      if (idx + 1 == pos.size()) break;
+      int nxt = pos[idx + 1];
+      if (nxt > p) {
+        qr(FnQrLeft<T>{Dl, p, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[p], cpb[p + 1]);
+        hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, Dl,
+                           (const QrProb<T>*)qp, p + 1, cnt);
+        hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)qtmp, qslot,
+                           p);
+        launch_gemm<T, T, T, Tacc>(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
+                                   cpb[p + 1] * cpb[p + 1], 1, st);
+      } else {
+        qr(FnQrRightT<T>{Dl, p, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[p + 1], cpb[p]);
+        hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, Dl,
+                           (const QrProb<T>*)qp, p, cnt);
+        hipLaunchKernelGGL(k_store_core_T<T>, dim3(chunks(), cnt), blk, 0, st, Dl,
+                           (const QrProb<T>*)qp, p);
+        right_env(c, p, cnt);
+      }
+    }
+    HIP_OK(hipGetLastError());
+  }
+
+  void local_update(const ProdCtx<T>& c, int p, int cnt) {
+    launch_gemm<T, T, T, Tacc>(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st);
+    launch_gemm<T, T, T, Tacc>(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1], PHYS * cpb[p],
+                               st);
+    launch_gemm<T, T, T, Tacc>(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st);
+  }
+
+  void right_env(const ProdCtx<T>& c, int p, int cnt) {
+    launch_gemm<T, T, T, Tacc>(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], PHYS * cpb[p], cpb[p + 1],
+                               st);
+    launch_gemm<T, T, T, Tacc>(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st);
+    launch_gemm<T, T, T, Tacc>(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st);
+  }
+
+  // ------------------------------------------------------------ shifts, slices
+  void shift(const std::vector<int>& dst, const std::vector<int>& src, const std::vector<int>& ax,
+             const std::vector<int>& dir, const std::vector<int>& cyc) {
+    for (size_t off = 0; off < dst.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, dst.size() - off);
+      IntArr a, d, c;
+      for (int i = 0; i < cnt; ++i) {
+        a.v[i] = ax[off + i];
+        d.v[i] = dir[off + i];
+        c.v[i] = cyc[off + i];
+      }
+      hipLaunchKernelGGL(k_shift<T>, dim3(chunks(), n, cnt), dim3(256), 0, st, list_idx(dst, off, cnt),
+                         list_idx(src, off, cnt), a, d, c);
+    }
+    HIP_OK(hipGetLastError());
+  }
+
+  // Streaming f_new(x) = f(x - c) one axis at a time (x, y, z order), each
+  // shift followed by rounding.  Returns fresh objects.
+  std::vector<int> stream(const std::vector<int>& src, const std::vector<const int*>& cvec,
+                          const int* axis_open) {
+    std::vector<int> cur = src;
+    std::vector<bool> owned(src.size(), false);
+    for (int ax = 0; ax < 3; ++ax) {
+      std::vector<int> dst, s, a, d, cy, who;
+      for (size_t i = 0; i < src.size(); ++i) {
+        if (cvec[i][ax] == 0) continue;
+        dst.push_back(acquire());
+        s.push_back(cur[i]);
+        a.push_back(ax);
+        d.push_back(cvec[i][ax]);
+        cy.push_back(axis_open[ax] ? 0 : 1);
+        who.push_back((int)i);
+      }
+      if (dst.empty()) continue;
+      shift(dst, s, a, d, cy);
+      round(dst);
+      for (size_t j = 0; j < who.size(); ++j) {
+        int i = who[j];
+        if (owned[i]) release(cur[i]);
+        cur[i] = dst[j];
+        owned[i] = true;
+      }
+    }
+    // items with c = 0 get a copy so that every result is a fresh object
+    std::vector<int> cd, cs;
+    std::vector<Coef> cc;
+    for (size_t i = 0; i < src.size(); ++i)
+      if (!owned[i]) {
+        int o = acquire();
+        cd.push_back(o);
+        cs.push_back(cur[i]);
+        cc.push_back(Coef{1.0, 0});
+        cur[i] = o;
+      }
+    if (!cd.empty()) copy_scaled(cd, cs, cc, nullptr);
+    return cur;
+  }
+
+  std::vector<int> slice(const std::vector<int>& src, const std::vector<int>& ax,
+                         const std::vector<int>& idx) {
+    std::vector<int> dst(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = acquire();
+    for (size_t off = 0; off < dst.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, dst.size() - off);
+      IntArr a, d;
+      for (int i = 0; i < cnt; ++i) {
+        a.v[i] = ax[off + i];
+        d.v[i] = idx[off + i];
+      }
+      hipLaunchKernelGGL(k_slice<T>, dim3(chunks(), n, cnt), dim3(256), 0, st, list_idx(dst, off, cnt),
+                         list_idx(src, off, cnt), a, d);
+    }
+    HIP_OK(hipGetLastError());
+    return dst;
+  }
+
+  // <1, X> into out[i] (device doubles)
+  void inner_ones(const std::vector<int>& src, double* out) {
+    for (size_t off = 0; off < src.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, src.size() - off);
+      hipLaunchKernelGGL(k_inner_ones<T>, dim3(cnt), dim3(256), 0, st, list_idx(src, off, cnt),
+                         out + off, cnt);
+    }
+    HIP_OK(hipGetLastError());
+  }
+
+  // ------------------------------------------------------------ dense I/O
+  // Contract objects to dense scale-ordered arrays: out[i * N^3 + ...]
+  void to_dense(const std::vector<int>& src, T* out, T* work) {
+    long N3 = 1L << (3 * n);
+    for (size_t off = 0; off < src.size(); off += MAXB) {
+      int cnt = (int)std::min<size_t>(MAXB, src.size() - off);
+      MpsList<T> L = list_idx(src, off, cnt);
+      T* a = work;
+      T* b = out + off * N3;
+      // T_0 = 1 (rows = 1, r_0 = 1)
+      std::vector<T> ones(cnt, (T)1);
+      for (int i = 0; i < cnt; ++i)
+        HIP_OK(hipMemcpyAsync(a + i * N3, &ones[i], sizeof(T), hipMemcpyHostToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+      long rows = 1;
+      for (int k = 0; k < n; ++k) {
+        T* dst = (k % 2 == 0) ? b : a;
+        T* srcb = (k % 2 == 0) ? a : b;
+        // ensure the final result lands in `b`: n steps alternate a->b->a...
+        launch_gemm<T, T, T, Tacc>(FnContract<T>{L, srcb, dst, N3, rows, k}, cnt, (int)rows,
+                                   PHYS * cpb[k + 1], 1, st);
+        rows *= PHYS;
+      }
+      if (n % 2 == 0) {
+        // last write went to `a`
+        int ch = (int)std::max<long>(1, std::min<long>(2048, (N3 * cnt + 255) / 256));
+        hipLaunchKernelGGL(k_copy_plain<T>, dim3(ch), dim3(256), 0, st, (const T*)a, b, N3 * cnt);
+      }
+    }
+    HIP_OK(hipGetLastError());
+  }
+};
+
+}  // namespace mpslbm

@@ -1,0 +1,162 @@
+// Grouped, strided, batched GEMM on MFMA (gfx950).
+//
+// C = alpha * A * B + beta * C for many small problems in one launch.  A
+// problem is produced on the device by a functor (so shapes may depend on
+// bond dimensions that live in device memory); the launch grid covers the
+// host-known capacity and workgroups whose tile or batch entry is outside
+// the actual problem exit at once.
+//
+// Tiles are 64x64 per 256-thread workgroup (four waves, 32x32 each = 2x2
+// MFMA 16x16 blocks), K staged through LDS 16 at a time.  Operands are read
+// through arbitrary element strides and converted to the accumulation type
+// Tacc on the way into LDS; Tacc = double uses v_mfma_f64_16x16x4f64,
+// Tacc = float uses v_mfma_f32_16x16x4f32.
+#pragma once
+#include "common.h"
+
+namespace mpslbm {
+
+template <typename TA, typename TB, typename TC>
+struct GemmDesc {
+  const TA* A;
+  const TB* B;
+  TC* C;
+  int M, N, K;
+  int nb1, nb2;  // batch entry b = b1 + nb1 * b2
+  long sAm, sAk, sBk, sBn, sCm, sCn;
+  long bA1, bB1, bC1, bA2, bB2, bC2;
+  double alpha, beta;
+  int valid;
+};
+
+template <typename TA, typename TB, typename TC>
+__host__ __device__ inline GemmDesc<TA, TB, TC> gemm_empty() {
+  GemmDesc<TA, TB, TC> d;
+  d.A = nullptr; d.B = nullptr; d.C = nullptr;
+  d.M = d.N = d.K = 0; d.nb1 = d.nb2 = 1;
+  d.sAm = d.sAk = d.sBk = d.sBn = d.sCm = d.sCn = 0;
+  d.bA1 = d.bB1 = d.bC1 = d.bA2 = d.bB2 = d.bC2 = 0;
+  d.alpha = 1.0; d.beta = 0.0; d.valid = 0;
+  return d;
+}
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+// Operand layouts of the 16x16x4 MFMAs: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16]; the four accumulator registers of lane l hold
+// column l % 16 and, per register v, row 4 (l / 16) + v for FP32 but row
+// l / 16 + 4 v for FP64 (checked on gfx950 with a one-wave probe).
+template <typename Tacc> struct MfmaT;
+template <> struct MfmaT<double> {
+  typedef d4 V;
+  __device__ static V op(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return (lane >> 4) + 4 * v; }
+};
+template <> struct MfmaT<float> {
+  typedef f4 V;
+  __device__ static V op(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int GT = 64;   // tile edge
+constexpr int GK = 16;   // K step
+
+template <typename TA, typename TB, typename TC, typename Tacc, typename F>
+__global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap) {
+  typedef typename MfmaT<Tacc>::V V;
+  __shared__ Tacc As[GK][GT + 1];
+  __shared__ Tacc Bs[GK][GT + 1];
+  long wg = blockIdx.x;
+  int tile = (int)(wg % tiles_cap);
+  long rest = wg / tiles_cap;
+  int b = (int)(rest % batch_cap);
+  int prob = (int)(rest / batch_cap);
+  GemmDesc<TA, TB, TC> d = f.get(prob);
+  if (!d.valid) return;
+  if (b >= d.nb1 * d.nb2) return;
+  int tn = (d.N + GT - 1) / GT;
+  int tm = (d.M + GT - 1) / GT;
+  if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
+  int ti = tile / tn, tj = tile % tn;
+  int b1 = b % d.nb1, b2 = b / d.nb1;
+  const TA* A = d.A + b1 * d.bA1 + b2 * d.bA2;
+  const TB* B = d.B + b1 * d.bB1 + b2 * d.bB2;
+  TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
+  int m0 = ti * GT, n0 = tj * GT;
+  int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  int wm = w >> 1, wn = w & 1;
+  V acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j)
+      for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
+  const bool a_k_contig = (d.sAk == 1);
+  const bool b_n_contig = (d.sBn == 1);
+  for (int k0 = 0; k0 < d.K; k0 += GK) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int e = tid + 256 * q;
+      int mm, kk;
+      if (a_k_contig) { mm = e >> 4; kk = e & 15; } else { mm = e & 63; kk = e >> 6; }
+      int gm = m0 + mm, gk = k0 + kk;
+      Tacc v = 0;
+      if (gm < d.M && gk < d.K) v = (Tacc)A[gm * d.sAm + gk * d.sAk];
+      As[kk][mm] = v;
+      int nn, kb;
+      if (b_n_contig) { kb = e >> 6; nn = e & 63; } else { nn = e >> 4; kb = e & 15; }
+      int gn = n0 + nn, gk2 = k0 + kb;
+      Tacc u = 0;
+      if (gn < d.N && gk2 < d.K) u = (Tacc)B[gk2 * d.sBk + gn * d.sBn];
+      Bs[kb][nn] = u;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < GK / 4; ++ks) {
+      int kr = ks * 4 + (lane >> 4);
+      Tacc a0 = As[kr][wm * 32 + (lane & 15)];
+      Tacc a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+      Tacc bb0 = Bs[kr][wn * 32 + (lane & 15)];
+      Tacc bb1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+      acc[0][0] = MfmaT<Tacc>::op(a0, bb0, acc[0][0]);
+      acc[0][1] = MfmaT<Tacc>::op(a0, bb1, acc[0][1]);
+      acc[1][0] = MfmaT<Tacc>::op(a1, bb0, acc[1][0]);
+      acc[1][1] = MfmaT<Tacc>::op(a1, bb1, acc[1][1]);
+    }
+    __syncthreads();
+  }
+  const double alpha = d.alpha, beta = d.beta;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        int row = m0 + wm * 32 + i * 16 + MfmaT<Tacc>::row(lane, v);
+        int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        if (row < d.M && col < d.N) {
+          TC* p = C + row * d.sCm + col * d.sCn;
+          double val = alpha * (double)acc[i][j][v];
+          if (beta != 0.0) val += beta * (double)(*p);
+          *p = (TC)val;
+        }
+      }
+}
+
+// Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps).
+template <typename TA, typename TB, typename TC, typename Tacc, typename F>
+inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap,
+                        hipStream_t s) {
+  if (nprob <= 0 || mcap <= 0 || ncap <= 0 || batch_cap <= 0) return;
+  int tiles = ceil_div(mcap, GT) * ceil_div(ncap, GT);
+  long grid = (long)nprob * batch_cap * tiles;
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F>), dim3((unsigned)grid), dim3(256), 0, s,
+                     f, tiles, batch_cap);
+  HIP_OK(hipGetLastError());
+}
+
+}  // namespace mpslbm

@@ -1,0 +1,202 @@
+"""Thin ctypes binding of the gfx950 MPS lattice Boltzmann library.
+
+Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  The names follow the C ABI declared in
+include/mps_lbm.h.  Loading fails loudly when the shared library has not
+been built; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmps_lbm.so")
+
+MAX_SITES = 10
+
+OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+D3Q19 = 19
+FP64, FP32 = 0, 1
+INV_TAYLOR2, INV_NEWTON = 0, 1
+BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
+POPS, RHO, J, VEL = 0, 1, 2, 3
+
+EXPORTED = ["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
+            "mps_lbm_to_dense", "mps_lbm_observables", "mps_lbm_destroy",
+            "mps_lbm_last_error", "mps_lbm_version"]
+
+
+class Config(C.Structure):
+    _fields_ = [
+        ("n", C.c_int), ("lattice", C.c_int), ("chi_max", C.c_int), ("chi_mask_max", C.c_int),
+        ("tol", C.c_double), ("tol_mask", C.c_double), ("tau", C.c_double),
+        ("g", C.c_double * 3), ("inv_rho_mode", C.c_int), ("inv_rho_iters", C.c_int),
+        ("precision", C.c_int), ("sweeps", C.c_int), ("axis_open", C.c_int * 3),
+        ("face_bc", C.c_int * 6), ("face_val", (C.c_double * 3) * 6),
+        ("seed", C.c_ulonglong),
+    ]
+
+
+class Obs(C.Structure):
+    _fields_ = [
+        ("step", C.c_longlong), ("mass", C.c_double), ("momentum", C.c_double * 3),
+        ("rho0", C.c_double), ("n_fluid", C.c_double), ("max_bond", C.c_int),
+        ("bonds", (C.c_int * MAX_SITES) * 19), ("nvps", C.c_double),
+        ("compression", C.c_double), ("max_discarded", C.c_double), ("mask_bond", C.c_int),
+        ("mask_trunc_err", C.c_double), ("roundings", C.c_longlong),
+        ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load the shared library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = C.CDLL(path)
+    P = C.c_void_p
+    DP = C.POINTER(C.c_double)
+    lib.mps_lbm_default_config.argtypes = [C.POINTER(Config)]
+    lib.mps_lbm_default_config.restype = None
+    lib.mps_lbm_init_from_field.argtypes = [C.POINTER(Config), DP, DP, DP,
+                                            C.POINTER(C.c_uint8), P, C.POINTER(P)]
+    lib.mps_lbm_init_from_field.restype = C.c_int
+    lib.mps_lbm_step.argtypes = [P, C.c_int]
+    lib.mps_lbm_step.restype = C.c_int
+    lib.mps_lbm_to_dense.argtypes = [P, C.c_int, DP, C.c_size_t]
+    lib.mps_lbm_to_dense.restype = C.c_int
+    lib.mps_lbm_observables.argtypes = [P, C.POINTER(Obs)]
+    lib.mps_lbm_observables.restype = C.c_int
+    lib.mps_lbm_destroy.argtypes = [P]
+    lib.mps_lbm_destroy.restype = None
+    lib.mps_lbm_last_error.argtypes = []
+    lib.mps_lbm_last_error.restype = C.c_char_p
+    lib.mps_lbm_version.argtypes = []
+    lib.mps_lbm_version.restype = C.c_char_p
+    _lib = lib
+    return lib
+
+
+class MpsLbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"mps_lbm error {code}: {msg}")
+        self.code = code
+
+
+def _check(code):
+    if code != OK:
+        raise MpsLbmError(code, load().mps_lbm_last_error().decode())
+
+
+def mps_lbm_default_config() -> Config:
+    c = Config()
+    load().mps_lbm_default_config(C.byref(c))
+    return c
+
+
+def _dp(a):
+    return None if a is None else a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def mps_lbm_init_from_field(cfg: Config, rho=None, u=None, f=None, solid=None,
+                            hip_stream: Optional[int] = None):
+    """Create a simulation handle; arrays are C-order FP64 ([x][y][z])."""
+    lib = load()
+    rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+    s = None
+    if solid is not None:
+        solid = np.ascontiguousarray(solid, dtype=np.uint8)
+        s = solid.ctypes.data_as(C.POINTER(C.c_uint8))
+    h = C.c_void_p()
+    _check(lib.mps_lbm_init_from_field(C.byref(cfg), _dp(rho), _dp(u), _dp(f), s,
+                                       C.c_void_p(hip_stream or 0), C.byref(h)))
+    return h
+
+
+def mps_lbm_step(h, nsteps: int = 1):
+    _check(load().mps_lbm_step(h, int(nsteps)))
+
+
+def mps_lbm_to_dense(h, what: int, N: int) -> np.ndarray:
+    shape = {POPS: (19, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
+    out = np.empty(shape, dtype=np.float64)
+    _check(load().mps_lbm_to_dense(h, int(what), _dp(out), out.size))
+    return out
+
+
+def mps_lbm_observables(h) -> Obs:
+    o = Obs()
+    _check(load().mps_lbm_observables(h, C.byref(o)))
+    return o
+
+
+def mps_lbm_destroy(h):
+    if h:
+        load().mps_lbm_destroy(h)
+
+
+def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_TAYLOR2,
+                     inv_iters: int = 2, seed: int = 2512) -> Config:
+    """Config from a workloads.Case."""
+    c = mps_lbm_default_config()
+    c.n = case.n
+    c.chi_max = int(case.chi)
+    c.chi_mask_max = int(case.chi_mask or 0)
+    c.tol = float(case.tol)
+    c.tol_mask = float(case.tol_mask)
+    c.tau = float(case.tau)
+    for a in range(3):
+        c.g[a] = float(case.g[a])
+        c.axis_open[a] = int(case.axis_open[a])
+    for face in range(6):
+        c.face_bc[face] = int(case.face_bc[face])
+        for a in range(3):
+            c.face_val[face][a] = float(case.face_val[face][a])
+    prec = precision or case.precision
+    c.precision = {"fp64": FP64, "fp32": FP32}.get(prec, FP32)
+    c.sweeps = sweeps
+    c.inv_rho_mode = inv_mode
+    c.inv_rho_iters = inv_iters
+    c.seed = seed
+    return c
+
+
+class Simulation:
+    """Convenience wrapper owning one handle."""
+
+    def __init__(self, case, precision=None, hip_stream=None, **kw):
+        self.case = case
+        self.cfg = config_from_case(case, precision, **kw)
+        self.h = mps_lbm_init_from_field(self.cfg, rho=case.rho0_field(), u=case.u0_field(),
+                                         solid=case.solid, hip_stream=hip_stream)
+
+    def step(self, n=1):
+        mps_lbm_step(self.h, n)
+
+    def dense(self, what=POPS):
+        return mps_lbm_to_dense(self.h, what, self.case.N)
+
+    def observables(self):
+        return mps_lbm_observables(self.h)
+
+    def close(self):
+        if self.h:
+            mps_lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,106 @@
+"""C-ABI checks that need no GPU: the shared library loads, exports every
+symbol include/mps_lbm.h declares, and rejects bad arguments before it
+touches a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def lib():
+    from paper_2512_07615_amd import mps_lbm as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return L
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "mps_lbm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mps_lbm_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_the_abi():
+    names = declared_functions()
+    for need in ["mps_lbm_init_from_field", "mps_lbm_step", "mps_lbm_to_dense",
+                 "mps_lbm_observables", "mps_lbm_destroy", "mps_lbm_last_error"]:
+        assert need in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = lib()
+    so = C.CDLL(L.LIB_PATH)
+    for name in declared_functions():
+        getattr(so, name)  # raises AttributeError if missing
+    assert sorted(L.EXPORTED) == declared_functions()
+
+
+def test_config_struct_layout_matches_header():
+    L = lib()
+    # field order/sizes of mps_lbm_config as declared in the header
+    c = L.Config
+    assert c.n.offset == 0
+    assert c.tol.offset % 8 == 0
+    assert C.sizeof(c) == c.seed.offset + 8
+
+
+def test_default_config_values():
+    L = lib()
+    c = L.mps_lbm_default_config()
+    assert c.lattice == L.D3Q19 and c.chi_max == 16 and c.sweeps == 2
+    assert c.tol == 1e-10 and c.tau == 0.8 and c.precision == L.FP64
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tau", 0.5, -1), ("tau", 0.3, -1), ("n", 1, -1), ("n", 11, -1), ("chi_max", 0, -1),
+    ("lattice", 15, -1), ("precision", 7, -1), ("inv_rho_mode", 9, -1), ("sweeps", 0, -1),
+    ("chi_max", 4096, -5),
+])
+def test_invalid_config_rejected_before_device_use(field, value, code):
+    L = lib()
+    c = L.mps_lbm_default_config()
+    setattr(c, field, value)
+    h = C.c_void_p()
+    so = L.load()
+    rc = so.mps_lbm_init_from_field(C.byref(c), None, None, None, None, None, C.byref(h))
+    assert rc == code
+    assert so.mps_lbm_last_error().decode() != ""
+    assert not h.value
+
+
+def test_bc_on_periodic_axis_and_missing_fields_rejected():
+    L = lib()
+    so = L.load()
+    c = L.mps_lbm_default_config()
+    c.face_bc[0] = L.BC_PRESSURE
+    c.face_val[0][0] = 1.0
+    h = C.c_void_p()
+    assert so.mps_lbm_init_from_field(C.byref(c), None, None, None, None, None,
+                                      C.byref(h)) == L.EINVAL
+    c = L.mps_lbm_default_config()
+    c.axis_open[0] = 1
+    c.face_bc[1] = L.BC_PRESSURE
+    c.face_val[1][0] = 0.0   # rho_b must be positive
+    assert so.mps_lbm_init_from_field(C.byref(c), None, None, None, None, None,
+                                      C.byref(h)) == L.EINVAL
+    c = L.mps_lbm_default_config()
+    rho = np.ones((16, 16, 16))
+    # u missing and f missing
+    assert so.mps_lbm_init_from_field(C.byref(c), rho.ctypes.data_as(C.POINTER(C.c_double)),
+                                      None, None, None, None, C.byref(h)) == L.EINVAL
+
+
+def test_null_handle_calls_fail_cleanly():
+    L = lib()
+    so = L.load()
+    assert so.mps_lbm_step(None, 1) == L.EINVAL
+    out = np.zeros(8)
+    assert so.mps_lbm_to_dense(None, 0, out.ctypes.data_as(C.POINTER(C.c_double)), 8) == L.EINVAL
+    o = L.Obs()
+    assert so.mps_lbm_observables(None, C.byref(o)) == L.EINVAL
+    so.mps_lbm_destroy(None)
+    assert so.mps_lbm_version().decode().startswith("mps-lbm")
