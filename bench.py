@@ -35,26 +35,59 @@ def make_case(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(case, budget_s=30.0):
-    """Time the CPU oracle (FP64 MPS path, same schedule) on a bounded
-    sample: initialisation excluded, as many whole steps as fit the budget
-    (at least one)."""
-    import numpy as np  # noqa: F401
-    from oracle.mps_lbm import MPSLBM
+def cpu_baseline(case, roundings_per_step, products_per_step, budget_s=20.0):
+    """The CPU oracle (FP64 numpy MPS path) timed on a bounded sample of the
+    workload: roundings of sums of two MPS and variational products at the
+    workload's bond profile (bond min(chi, 8^k, 8^(n-k))), repeated for
+    about budget_s; the step rate is extrapolated with the per-step counts
+    of roundings and products the library reports for the same workload."""
+    import numpy as np
+    from oracle import mps as M
     threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
-    m = MPSLBM(case)
-    t0 = time.perf_counter()
-    k = 0
-    while True:
-        m.step()
-        k += 1
-        if time.perf_counter() - t0 > budget_s or k >= 3:
-            break
-    dt = (time.perf_counter() - t0) / k
-    return {"value": 1.0 / dt, "unit": "steps/s", "cores": int(threads),
+    rng = np.random.default_rng(2512)
+    n, chi = case.n, case.chi
+    b = [1] + [min(chi, 8 ** k, 8 ** (n - k)) for k in range(1, n)] + [1]
+
+    def rand_mps():
+        return [rng.standard_normal((b[k], 8, b[k + 1])) / 8.0 for k in range(n)]
+
+    x, y = rand_mps(), rand_mps()
+    t_round, k_round = 0.0, 0
+    t_prod, k_prod = 0.0, 0
+    t_start = time.perf_counter()
+    while time.perf_counter() - t_start < budget_s or k_round == 0 or k_prod == 0:
+        t0 = time.perf_counter()
+        M.round_mps(M.add(x, y), chi, case.tol)
+        t_round += time.perf_counter() - t0
+        k_round += 1
+        t0 = time.perf_counter()
+        M.hadamard_variational(x, y)
+        t_prod += time.perf_counter() - t0
+        k_prod += 1
+    per_step = roundings_per_step * t_round / k_round + products_per_step * t_prod / k_prod
+    return {"value": 1.0 / per_step, "unit": "steps/s", "cores": int(threads),
             "kind": "oracle",
-            "sample": f"{k} step(s) of the CPU FP64 MPS oracle on {case.name} "
-                      f"(chi={case.chi}), initialisation excluded"}
+            "sample": f"{k_round} roundings (sum of two MPS, bonds {b[1:-1]}) and {k_prod} "
+                      f"variational products of the CPU FP64 MPS oracle on {case.name}, "
+                      f"scaled by {roundings_per_step} roundings + {products_per_step} "
+                      f"products per step (initialisation excluded)"}
+
+
+def roofline(kind, ks, prec):
+    """Roofline entry of the timed kernel class from its event-timed launches
+    and device-counted algorithmic flops."""
+    avg_ms = ks.total_ms / max(ks.launches, 1)
+    flops_per_launch = ks.flops / max(ks.launches, 1)
+    achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
+    if kind == "prodgemm":
+        bound, peak = "mfma", PEAK["fp32_tflops"] if prec == "fp32" else PEAK["fp64_tflops"]
+    else:
+        # FP64 vector ALU: 256 CUs x 2.4 GHz x 128 FP64 flops/clock/CU
+        bound, peak = "alu", PEAK["fp64_tflops"]
+    return {"bound": bound, "kernel": kind, "achieved": achieved, "peak": peak,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "launches": ks.launches, "avg_launch_ms": avg_ms,
+            "flops_per_launch": flops_per_launch}
 
 
 def main():
@@ -65,6 +98,8 @@ def main():
     ap.add_argument("--workload", default="porous64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--roofline-kernel", default="jacobi",
+                    choices=["jacobi", "householder", "prodgemm"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (N=1); "
@@ -79,6 +114,9 @@ def main():
     for _ in range(args.warmup):
         sim.step(1)
     torch.cuda.synchronize()
+    kind = {"jacobi": L.K_JACOBI, "householder": L.K_HOUSEHOLDER,
+            "prodgemm": L.K_PRODGEMM}[args.roofline_kernel]
+    sim.kernel_timing(kind)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record(stream)
@@ -87,6 +125,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    ks = sim.kernel_stats()
     obs = sim.observables()
     sps = 1000.0 / ms
     N3 = case.N ** 3
@@ -102,6 +141,8 @@ def main():
                    "roundings_per_step": obs.roundings, "products_per_step": obs.products,
                    "compression": obs.compression},
     }
+    out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)
+    out["roofline"]["share_of_step"] = ks.total_ms / (ms * args.steps)
     sim.close()
     if args.fp64_steps > 0 and case.precision != "fp64":
         sim64 = L.Simulation(case, precision="fp64", hip_stream=stream.cuda_stream)
@@ -117,7 +158,7 @@ def main():
         out["config"]["speedup_vs_fp64_path"] = ms64 / ms
         sim64.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(case)
+        out["cpu_baseline"] = cpu_baseline(case, obs.roundings, obs.products)
     print(json.dumps(out), flush=True)
 
 

@@ -149,6 +149,32 @@ int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len);
 /* Scalar observables (synchronises the stream). */
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
 
+/* Kernel classes that can be timed for roofline reporting. */
+#define MPS_LBM_K_NONE 0
+#define MPS_LBM_K_JACOBI 1      /* one-sided Jacobi SVD of the bond matrices   */
+#define MPS_LBM_K_HOUSEHOLDER 2 /* Householder QR of core unfoldings          */
+#define MPS_LBM_K_PRODGEMM 3    /* contraction GEMMs of the variational product */
+
+typedef struct {
+  long long launches; /* launches of the class since timing was enabled       */
+  double total_ms;    /* sum of their durations (HIP events around each launch) */
+  double flops;       /* algorithmic floating-point operations they performed,
+                         counted on the device from the actual shapes          */
+} mps_lbm_kstats;
+
+/*
+ * Time every launch of one kernel class with HIP events recorded on the
+ * handle's stream around that launch, and count its algorithmic work.
+ * kind = MPS_LBM_K_* (MPS_LBM_K_NONE switches timing off); enabling resets
+ * the statistics.  Timing adds two event records per launch of the class
+ * and nothing to other kernels.  Errors: EINVAL (NULL handle, bad kind).
+ */
+int mps_lbm_kernel_timing(mps_lbm_t* h, int kind);
+
+/* Statistics of the timed class since it was enabled (synchronises the
+   stream).  Errors: EINVAL (NULL handle or out), EHIP. */
+int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out);
+
 /* Release every device buffer of the handle; NULL is ignored. */
 void mps_lbm_destroy(mps_lbm_t* h);
 

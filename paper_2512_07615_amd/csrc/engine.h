@@ -518,6 +518,48 @@ class Engine {
   int pbatch = 1;
   int sweeps = 2;
   long roundings = 0, products = 0;
+  // timing of one kernel class: HIP events around each of its launches
+  int tkind = 0;
+  std::vector<hipEvent_t> evs;
+  size_t ev_next = 0;
+  long long tlaunches = 0;
+  double tms = 0.0;
+  double* kflops = nullptr;  // device counter of the class's algorithmic flops
+
+  void timing(int kind) {
+    flush_events();
+    tkind = kind;
+    tlaunches = 0;
+    tms = 0.0;
+    if (!kflops) kflops = (double*)dalloc(64);
+    HIP_OK(hipMemsetAsync(kflops, 0, 8, st));
+    if (kind && evs.empty()) {
+      evs.resize(8192);
+      for (auto& e : evs) HIP_OK(hipEventCreate(&e));
+    }
+  }
+  void tbegin(int kind) {
+    if (tkind != kind) return;
+    if (ev_next + 2 > evs.size()) flush_events();
+    HIP_OK(hipEventRecord(evs[ev_next], st));
+  }
+  void tend(int kind) {
+    if (tkind != kind) return;
+    HIP_OK(hipEventRecord(evs[ev_next + 1], st));
+    ev_next += 2;
+    ++tlaunches;
+  }
+  double* kf(int kind) const { return tkind == kind ? kflops : nullptr; }
+  void flush_events() {
+    if (ev_next == 0) return;
+    HIP_OK(hipStreamSynchronize(st));
+    for (size_t i = 0; i + 1 < ev_next; i += 2) {
+      float ms = 0.f;
+      HIP_OK(hipEventElapsedTime(&ms, evs[i], evs[i + 1]));
+      tms += ms;
+    }
+    ev_next = 0;
+  }
 
   void* dalloc(size_t bytes) {
     void* p = nullptr;
@@ -531,6 +573,7 @@ class Engine {
   }
   ~Engine() {
     for (void* p : allocs) (void)hipFree(p);
+    for (auto& e : evs) (void)hipEventDestroy(e);
   }
 
   static int full_bound(int n, int k) {
@@ -673,8 +716,10 @@ class Engine {
     hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob);
     hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
                        (const QrProb<T>*)qp);
+    tbegin(2);
     hipLaunchKernelGGL(k_householder<T>, dim3(nprob), dim3(256), (size_t)lds_elems * 8, st,
-                       (const QrProb<T>*)qp, qw, lds_elems);
+                       (const QrProb<T>*)qp, qw, lds_elems, kf(2));
+    tend(2);
     HIP_OK(hipGetLastError());
   }
 
@@ -715,8 +760,10 @@ class Engine {
                          FnSvdTrunc<T>{L, (const QrProb<T>*)qp, k, svdW, sw, svdUS, svdWk, sus,
                                        rdelta, rdisc, chi_cap, istats, nullptr, 0},
                          sp, cnt);
+      tbegin(1);
       hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), blk, (size_t)lds_elems * 8, st,
-                         (const SvdProb*)sp, lds_elems, 40);
+                         (const SvdProb*)sp, lds_elems, 40, kf(1));
+      tend(1);
       launch_gemm<T, double, T, double>(FnCoreTimesUS<T>{L, qp, svdUS, sus, ctmp, maxcore, k},
                                         cnt, capb[k - 1] * PHYS, scap, 1, st);
       launch_gemm<double, T, T, double>(FnWtQt<T>{L, qp, svdWk, sus, k}, cnt, scap, mcap, 1, st);
@@ -907,8 +954,10 @@ class Engine {
                            (const QrProb<T>*)qp, p + 1, cnt);
         hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)qtmp, qslot,
                            p);
+        tbegin(3);
         launch_gemm<T, T, T, Tacc>(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
-                                   cpb[p + 1] * cpb[p + 1], 1, st);
+                                   cpb[p + 1] * cpb[p + 1], 1, st, kf(3));
+        tend(3);
       } else {
         qr(FnQrRightT<T>{Dl, p, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[p + 1], cpb[p]);
         hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, Dl,
@@ -922,17 +971,32 @@ class Engine {
   }
 
   void local_update(const ProdCtx<T>& c, int p, int cnt) {
-    launch_gemm<T, T, T, Tacc>(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st);
+    tbegin(3);
+    launch_gemm<T, T, T, Tacc>(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st,
+                               kf(3));
+    tend(3);
+    tbegin(3);
     launch_gemm<T, T, T, Tacc>(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1], PHYS * cpb[p],
-                               st);
-    launch_gemm<T, T, T, Tacc>(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st);
+                               st, kf(3));
+    tend(3);
+    tbegin(3);
+    launch_gemm<T, T, T, Tacc>(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st,
+                               kf(3));
+    tend(3);
   }
 
   void right_env(const ProdCtx<T>& c, int p, int cnt) {
+    tbegin(3);
     launch_gemm<T, T, T, Tacc>(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], PHYS * cpb[p], cpb[p + 1],
-                               st);
-    launch_gemm<T, T, T, Tacc>(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st);
-    launch_gemm<T, T, T, Tacc>(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st);
+                               st, kf(3));
+    tend(3);
+    tbegin(3);
+    launch_gemm<T, T, T, Tacc>(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st,
+                               kf(3));
+    tend(3);
+    tbegin(3);
+    launch_gemm<T, T, T, Tacc>(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3));
+    tend(3);
   }
 
   // ------------------------------------------------------------ shifts, slices

@@ -67,7 +67,7 @@ constexpr int GT = 64;   // tile edge
 constexpr int GK = 16;   // K step
 
 template <typename TA, typename TB, typename TC, typename Tacc, typename F>
-__global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap) {
+__global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops) {
   typedef typename MfmaT<Tacc>::V V;
   __shared__ Tacc As[GK][GT + 1];
   __shared__ Tacc Bs[GK][GT + 1];
@@ -82,6 +82,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap)
   int tn = (d.N + GT - 1) / GT;
   int tm = (d.M + GT - 1) / GT;
   if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
+  if (flops && tile == 0 && threadIdx.x == 0) atomicAdd(flops, 2.0 * d.M * d.N * d.K);
   int ti = tile / tn, tj = tile % tn;
   int b1 = b % d.nb1, b2 = b / d.nb1;
   const TA* A = d.A + b1 * d.bA1 + b2 * d.bA2;
@@ -149,13 +150,13 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap)
 // Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps).
 template <typename TA, typename TB, typename TC, typename Tacc, typename F>
 inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap,
-                        hipStream_t s) {
+                        hipStream_t s, double* flops = nullptr) {
   if (nprob <= 0 || mcap <= 0 || ncap <= 0 || batch_cap <= 0) return;
   int tiles = ceil_div(mcap, GT) * ceil_div(ncap, GT);
   long grid = (long)nprob * batch_cap * tiles;
   if (grid <= 0) return;
   hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F>), dim3((unsigned)grid), dim3(256), 0, s,
-                     f, tiles, batch_cap);
+                     f, tiles, batch_cap, flops);
   HIP_OK(hipGetLastError());
 }
 

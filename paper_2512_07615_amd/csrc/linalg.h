@@ -246,7 +246,7 @@ __global__ void k_qr_export_r(const QrProb<T>* qp, const double* Racc, long sq) 
 // Working copies live in LDS when they fit, else in the FP64 workspaces.
 template <typename T>
 __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork w,
-                                                     int lds_elems) {
+                                                     int lds_elems, double* flops) {
   extern __shared__ double sh[];
   __shared__ double tau_s[1024];
   __shared__ double red[8];
@@ -333,6 +333,13 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
     int i = (int)(e / p), c = (int)(e % p);
     q.Q[e] = (T)Qw[(long)c * m + i];
   }
+  if (flops && tid == 0) {
+    // reflector generation 2(m-j), trailing update 4(m-j)(s-j-1), Q formation 4(m-j)(p-j)
+    double f = 0.0;
+    for (int j = 0; j < p; ++j)
+      f += 2.0 * (m - j) + 4.0 * (m - j) * (s - j - 1) + 4.0 * (m - j) * (p - j);
+    atomicAdd(flops, f);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -364,7 +371,7 @@ __global__ void k_svd_prep(F f, SvdProb* sp, int nprob) {
 }
 
 __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_elems,
-                                                    int max_sweeps) {
+                                                    int max_sweeps, double* flops) {
   extern __shared__ double sh[];
   __shared__ int rotated;
   __shared__ int perm[1024];
@@ -383,6 +390,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_e
   const double eps = 2.220446049250313e-16;
   const double tol = eps * sqrt((double)(m > 1 ? m : 1));
   const int P = (n % 2) ? n + 1 : n;  // players (one dummy if odd)
+  double work = 0.0;  // algorithmic flops of this wave (pairs tested, rotations applied)
   int sweep = 0;
   for (; sweep < max_sweeps && n > 1; ++sweep) {
     if (tid == 0) rotated = 0;
@@ -402,6 +410,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_e
           al += x * x; be += y * y; ga += x * y;
         }
         al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
+        work += 6.0 * m;
         // relative orthogonality test; sqrt(al) sqrt(be) avoids underflow of al * be
         if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
         double zeta = (be - al) / (2.0 * ga);
@@ -420,6 +429,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_e
           wb[r] = sn * x + cs * y;
         }
         if (lane == 0) rotated = 1;
+        work += 6.0 * m + 6.0 * n;
       }
       __syncthreads();
     }
@@ -428,6 +438,7 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_e
     if (!any) break;
   }
   if (sweep >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
+  if (flops && lane == 0) atomicAdd(flops, work);
   // singular values = column norms (stored temporarily in W's spare? use global sv)
   double* sv = p.sv;
   // column norms into a scratch region: reuse perm-sorted pass with LDS array

@@ -40,6 +40,8 @@ struct Sim {
   virtual void step(int nsteps) = 0;
   virtual void to_dense(int what, double* out) = 0;
   virtual void observables(mps_lbm_obs* o) = 0;
+  virtual void set_timing(int kind) = 0;
+  virtual void kstats(mps_lbm_kstats* o) = 0;
 };
 
 template <typename T>
@@ -484,6 +486,17 @@ struct SimT : Sim {
     if (mom) (void)hipFree(mom);
   }
 
+  void set_timing(int kind) override { E.timing(kind); }
+
+  void kstats(mps_lbm_kstats* o) override {
+    E.flush_events();
+    double fl = 0.0;
+    if (E.kflops) HIP_OK(hipMemcpy(&fl, E.kflops, 8, hipMemcpyDeviceToHost));
+    o->launches = E.tlaunches;
+    o->total_ms = E.tms;
+    o->flops = fl;
+  }
+
   void observables(mps_lbm_obs* o) override {
     memset(o, 0, sizeof(*o));
     std::vector<int> objs(f, f + 19);
@@ -664,6 +677,28 @@ int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out) {
     return fail(e.code, e.what());
   } catch (const std::exception& e) {
     return fail(MPS_LBM_EHIP, e.what());
+  }
+}
+
+int mps_lbm_kernel_timing(mps_lbm_t* h, int kind) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (kind < MPS_LBM_K_NONE || kind > MPS_LBM_K_PRODGEMM) return fail(MPS_LBM_EINVAL, "bad kind");
+  try {
+    h->sim->set_timing(kind);
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  try {
+    h->sim->kstats(out);
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
   }
 }
 

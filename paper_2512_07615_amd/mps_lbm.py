@@ -25,9 +25,12 @@ INV_TAYLOR2, INV_NEWTON = 0, 1
 BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
 POPS, RHO, J, VEL = 0, 1, 2, 3
 
-EXPORTED = ["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
-            "mps_lbm_to_dense", "mps_lbm_observables", "mps_lbm_destroy",
-            "mps_lbm_last_error", "mps_lbm_version"]
+K_NONE, K_JACOBI, K_HOUSEHOLDER, K_PRODGEMM = 0, 1, 2, 3
+
+EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
+                   "mps_lbm_to_dense", "mps_lbm_observables", "mps_lbm_destroy",
+                   "mps_lbm_last_error", "mps_lbm_version", "mps_lbm_kernel_timing",
+                   "mps_lbm_kernel_stats"])
 
 
 class Config(C.Structure):
@@ -50,6 +53,10 @@ class Obs(C.Structure):
         ("mask_trunc_err", C.c_double), ("roundings", C.c_longlong),
         ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
     ]
+
+
+class KStats(C.Structure):
+    _fields_ = [("launches", C.c_longlong), ("total_ms", C.c_double), ("flops", C.c_double)]
 
 
 _lib = None
@@ -82,6 +89,10 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_last_error.restype = C.c_char_p
     lib.mps_lbm_version.argtypes = []
     lib.mps_lbm_version.restype = C.c_char_p
+    lib.mps_lbm_kernel_timing.argtypes = [P, C.c_int]
+    lib.mps_lbm_kernel_timing.restype = C.c_int
+    lib.mps_lbm_kernel_stats.argtypes = [P, C.POINTER(KStats)]
+    lib.mps_lbm_kernel_stats.restype = C.c_int
     _lib = lib
     return lib
 
@@ -141,6 +152,16 @@ def mps_lbm_observables(h) -> Obs:
     return o
 
 
+def mps_lbm_kernel_timing(h, kind: int):
+    _check(load().mps_lbm_kernel_timing(h, int(kind)))
+
+
+def mps_lbm_kernel_stats(h) -> KStats:
+    k = KStats()
+    _check(load().mps_lbm_kernel_stats(h, C.byref(k)))
+    return k
+
+
 def mps_lbm_destroy(h):
     if h:
         load().mps_lbm_destroy(h)
@@ -189,6 +210,12 @@ class Simulation:
 
     def observables(self):
         return mps_lbm_observables(self.h)
+
+    def kernel_timing(self, kind):
+        mps_lbm_kernel_timing(self.h, kind)
+
+    def kernel_stats(self):
+        return mps_lbm_kernel_stats(self.h)
 
     def close(self):
         if self.h:
