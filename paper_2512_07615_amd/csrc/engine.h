@@ -197,7 +197,7 @@ struct FnSvdTrunc {
   __device__ SvdProb get(int i) const {
     QrProb<T> q = qp[i];
     SvdProb p;
-    p.L = q.R; p.W = W + i * sw;
+    p.L = q.R; p.W = W + i * sw; p.Lw = q.R;  // rotated in place when not in LDS
     p.rows = q.s; p.cols = q.p; p.valid = 1;
     p.delta2 = delta2[i]; p.chi = chi;
     p.rank_out = &L.p[i]->r[k];
@@ -479,6 +479,201 @@ __global__ void k_div_scalar(const double* a, double b, double* out) {
 }
 
 // ============================================================================
+// FP32 policy: rank-revealing Cholesky-QR2 and Gram-eigen truncation.
+template <typename T>
+__global__ void k_cq_dims(const QrProb<T>* qp, int* n1, int nprob) {
+  int i = threadIdx.x;
+  if (i < nprob) n1[i] = (qp[i].valid && qp[i].m > qp[i].s) ? qp[i].s : 0;
+}
+template <typename T>
+struct FCqGram1 {  // G = A^T A
+  const QrProb<T>* qp; CholWork w;
+  __device__ GemmDesc<T, T, double> get(int i) const {
+    GemmDesc<T, T, double> d = gemm_empty<T, T, double>();
+    QrProb<T> q = qp[i];
+    if (!q.valid || q.m <= q.s) return d;
+    d.A = q.A; d.B = q.A; d.C = w.G + i * w.sq;
+    d.M = q.s; d.N = q.s; d.K = q.m;
+    d.sAm = q.sAk; d.sAk = q.sAm; d.sBk = q.sAm; d.sBn = q.sAk;
+    d.sCm = q.s; d.sCn = 1; d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+struct FCqQ1 {  // Q1 = A B1 (m x rho1)
+  const QrProb<T>* qp; CholWork w;
+  __device__ GemmDesc<T, double, double> get(int i) const {
+    GemmDesc<T, double, double> d = gemm_empty<T, double, double>();
+    QrProb<T> q = qp[i];
+    if (!q.valid || q.m <= q.s) return d;
+    int r1 = w.rank[2 * i];
+    d.A = q.A; d.B = w.B1 + i * w.sq; d.C = w.Q1 + i * w.mq;
+    d.M = q.m; d.N = r1; d.K = q.s;
+    d.sAm = q.sAm; d.sAk = q.sAk; d.sBk = r1; d.sBn = 1; d.sCm = r1; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+struct FCqGram2 {  // G = Q1^T Q1 (rho1 x rho1)
+  const QrProb<T>* qp; CholWork w;
+  __device__ GemmDesc<double, double, double> get(int i) const {
+    GemmDesc<double, double, double> d = gemm_empty<double, double, double>();
+    QrProb<T> q = qp[i];
+    if (!q.valid || q.m <= q.s) return d;
+    int r1 = w.rank[2 * i];
+    const double* X = w.Q1 + i * w.mq;
+    d.A = X; d.B = X; d.C = w.G + i * w.sq;
+    d.M = r1; d.N = r1; d.K = q.m;
+    d.sAm = 1; d.sAk = r1; d.sBk = r1; d.sBn = 1; d.sCm = r1; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+__global__ void k_cq_dims2(const QrProb<T>* qp, const int* rank, int* n2, int nprob) {
+  int i = threadIdx.x;
+  if (i < nprob) n2[i] = (qp[i].valid && qp[i].m > qp[i].s) ? rank[2 * i] : 0;
+}
+template <typename T>
+struct FCqQ {  // Q = Q1 B2 (m x rho2) -> output
+  const QrProb<T>* qp; CholWork w;
+  __device__ GemmDesc<double, double, T> get(int i) const {
+    GemmDesc<double, double, T> d = gemm_empty<double, double, T>();
+    QrProb<T> q = qp[i];
+    if (!q.valid || q.m <= q.s) return d;
+    int r1 = w.rank[2 * i], r2 = w.rank[2 * i + 1];
+    d.A = w.Q1 + i * w.mq; d.B = w.B2 + i * w.sq; d.C = q.Q;
+    d.M = q.m; d.N = r2; d.K = r1;
+    d.sAm = r1; d.sAk = 1; d.sBk = r2; d.sBn = 1; d.sCm = r2; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+struct FCqR {  // R = R2 R1 (rho2 x s) -> output
+  const QrProb<T>* qp; CholWork w;
+  __device__ GemmDesc<double, double, double> get(int i) const {
+    GemmDesc<double, double, double> d = gemm_empty<double, double, double>();
+    QrProb<T> q = qp[i];
+    if (!q.valid || q.m <= q.s) return d;
+    int r1 = w.rank[2 * i], r2 = w.rank[2 * i + 1];
+    d.A = w.R2 + i * w.sq; d.B = w.R1 + i * w.sq; d.C = q.R;
+    d.M = r2; d.N = q.s; d.K = r1;
+    d.sAm = r1; d.sAk = 1; d.sBk = q.s; d.sBn = 1; d.sCm = q.s; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+// pass-2 rank into p; an all-zero Q (A = 0) becomes e_0 so Q stays orthonormal
+template <typename T>
+__global__ void k_cq_finish(QrProb<T>* qp, const int* rank, int nprob) {
+  int i = blockIdx.x;
+  if (i >= nprob) return;
+  QrProb<T> q = qp[i];
+  if (!q.valid || q.m <= q.s) return;
+  __shared__ double red[8];
+  int r2 = rank[2 * i + 1];
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < q.m; e += blockDim.x) acc += fabs((double)q.Q[(long)e * r2]);
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) {
+    qp[i].p = r2;
+    if (acc == 0.0) q.Q[0] = (T)1;
+  }
+}
+
+// Widen a rank-deficient Q (m x p, ld p) to m x s (ld s) with zero columns,
+// R to s rows with zero rows, so that a caller with host-fixed bond sizes sees
+// the Householder layout (Q^T Q is then a projector, Q Q^T A = A still holds).
+// One workgroup per problem; tmp holds m*s elements per problem.
+template <typename T>
+__global__ void k_qr_widen(QrProb<T>* qp, T* tmp, long tslot, int nprob) {
+  int i = blockIdx.x;
+  if (i >= nprob) return;
+  QrProb<T> q = qp[i];
+  if (!q.valid || q.m <= q.s || q.p >= q.s) return;
+  T* t = tmp + i * tslot;
+  long mp = (long)q.m * q.p;
+  for (long e = threadIdx.x; e < mp; e += blockDim.x) t[e] = q.Q[e];
+  __syncthreads();
+  for (long e = threadIdx.x; e < (long)q.m * q.s; e += blockDim.x) {
+    long row = e / q.s;
+    int col = (int)(e % q.s);
+    q.Q[e] = col < q.p ? t[row * q.p + col] : (T)0;
+  }
+  // R is p x s (ld s): rows p..s-1 become zero
+  for (long e = (long)q.p * q.s + threadIdx.x; e < (long)q.s * q.s; e += blockDim.x) q.R[e] = 0.0;
+  __syncthreads();
+  if (threadIdx.x == 0) qp[i].p = q.s;
+}
+
+// Gram of the right unfolding M (r_k x 8 r_{k+1}) of core k: G = M M^T (FP64)
+template <typename T>
+struct FGramM {
+  MpsList<T> L; int k; double* G; long sq;
+  __device__ GemmDesc<T, T, double> get(int i) const {
+    GemmDesc<T, T, double> d = gemm_empty<T, T, double>();
+    MpsDev<T>* m = L.p[i];
+    int s = m->r[k], c = PHYS * m->r[k + 1];
+    d.A = core_ptr(m, k); d.B = core_ptr(m, k); d.C = G + i * sq;
+    d.M = s; d.N = s; d.K = c;
+    d.sAm = c; d.sAk = 1; d.sBk = 1; d.sBn = c; d.sCm = s; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+template <typename T>
+struct FnEigTrunc {
+  MpsList<T> L; int k; double* G; long sq; double* US; double* Ut; long sus;
+  const double* delta2; double* disc; int chi; int* fail;
+  __device__ EigProb get(int i) const {
+    EigProb p;
+    p.G = G + i * sq;
+    p.s = L.p[i]->r[k];
+    p.valid = 1;
+    p.delta2 = delta2[i];
+    p.chi = chi;
+    p.rank_out = &L.p[i]->r[k];
+    p.US = US + i * sus;
+    p.Ut = Ut + i * sus;
+    p.disc = disc + i * (MAXN + 1) + k;
+    p.fail = fail;
+    return p;
+  }
+};
+// core_k <- Ut (r x s) M (s x 8 r_{k+1}) into tmp
+template <typename T>
+struct FUtM {
+  MpsList<T> L; const EigProb* ep; T* tmp; long slot; int k;
+  __device__ GemmDesc<double, T, T> get(int i) const {
+    GemmDesc<double, T, T> d = gemm_empty<double, T, T>();
+    MpsDev<T>* m = L.p[i];
+    int s = ep[i].s, r = m->r[k], c = PHYS * m->r[k + 1];
+    d.A = ep[i].Ut; d.B = core_ptr(m, k); d.C = tmp + i * slot;
+    d.M = r; d.N = c; d.K = s;
+    d.sAm = s; d.sAk = 1; d.sBk = c; d.sBn = 1; d.sCm = c; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+// core_{k-1} <- core_{k-1} ((8 r_{k-1}) x s) US (s x r) into tmp
+template <typename T>
+struct FCoreUS2 {
+  MpsList<T> L; const EigProb* ep; T* tmp; long slot; int k;
+  __device__ GemmDesc<T, double, T> get(int i) const {
+    GemmDesc<T, double, T> d = gemm_empty<T, double, T>();
+    MpsDev<T>* m = L.p[i];
+    int s = ep[i].s, r = m->r[k], rl = m->r[k - 1];
+    d.A = core_ptr(m, k - 1); d.B = ep[i].US; d.C = tmp + i * slot;
+    d.M = rl * PHYS; d.N = r; d.K = s;
+    d.sAm = s; d.sAk = 1; d.sBk = r; d.sBn = 1; d.sCm = r; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+
+// ============================================================================
 template <typename T>
 class Engine {
  public:
@@ -515,6 +710,12 @@ class Engine {
   T* envR = nullptr;
   T* T1 = nullptr;
   T* T2 = nullptr;
+  // FP32 policy: rank-revealing Cholesky-QR2 and Gram-eigen truncation
+  bool fast = false;
+  CholWork cw;
+  int* cq_n = nullptr;  // [2 * MAXB] dims of the two Cholesky passes
+  EigProb* ep = nullptr;
+  double eps_rank = 1e-14;
   int pbatch = 1;
   int sweeps = 2;
   long roundings = 0, products = 0;
@@ -606,6 +807,11 @@ class Engine {
                             lds_elems * 8) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_householder<T>,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_chol_piv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_jacobi_eig,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_elems * 8) != hipSuccess) {
       (void)hipGetLastError();
       lds_elems = (65536 - 16384) / 8;
@@ -653,6 +859,17 @@ class Engine {
     }
     envcap = ec;
     tcap = tc;
+    fast = (sizeof(T) == 4);
+    cw.sq = sq; cw.mq = mq;
+    cw.G = (double*)dalloc(8 * sq * MAXB);
+    cw.B1 = (double*)dalloc(8 * sq * MAXB);
+    cw.R1 = (double*)dalloc(8 * sq * MAXB);
+    cw.B2 = (double*)dalloc(8 * sq * MAXB);
+    cw.R2 = (double*)dalloc(8 * sq * MAXB);
+    cw.Q1 = (double*)dalloc(8 * mq * MAXB);
+    cw.rank = (int*)dalloc(4 * 4 * MAXB);  // [0, 2 MAXB): per-problem pairs; [2 MAXB, 3 MAXB): pass 2
+    cq_n = (int*)dalloc(4 * 2 * MAXB);
+    ep = (EigProb*)dalloc(sizeof(EigProb) * MAXB);
     envL = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
     envR = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
     T1 = (T*)dalloc(sizeof(T) * tcap * pbatch);
@@ -716,10 +933,37 @@ class Engine {
     hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob);
     hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
                        (const QrProb<T>*)qp);
+    if (fast) {
+      qr_cholesky(nprob, mcap, scap);
+      return;
+    }
     tbegin(2);
     hipLaunchKernelGGL(k_householder<T>, dim3(nprob), dim3(256), (size_t)lds_elems * 8, st,
                        (const QrProb<T>*)qp, qw, lds_elems, kf(2));
     tend(2);
+    HIP_OK(hipGetLastError());
+  }
+
+  // rank-revealing Cholesky-QR2 of the materialised problems (m > s)
+  void qr_cholesky(int nprob, int mcap, int scap) {
+    size_t lds = (size_t)lds_elems * 8;
+    CholWork w = cw;
+    hipLaunchKernelGGL(k_cq_dims<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp, cq_n, nprob);
+    launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)cq_n, 1, w.G,
+                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob);
+    hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 0);
+    launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
+    launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_cq_dims2<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp,
+                       (const int*)w.rank, cq_n + MAXB, nprob);
+    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)(cq_n + MAXB), 1,
+                       w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob);
+    hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 1);
+    launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);
+    launch_gemm<double, double, double, double>(FCqR<T>{qp, w}, nprob, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_cq_finish<T>, dim3(nprob), dim3(256), 0, st, qp, (const int*)w.rank,
+                       nprob);
     HIP_OK(hipGetLastError());
   }
 
@@ -753,7 +997,26 @@ class Engine {
     }
     hipLaunchKernelGGL(k_round_threshold<T>, dim3(cnt), blk, 0, st, L, tol_r, rdelta, rnorm, cnt);
     HIP_OK(hipMemsetAsync(rdisc, 0, 8 * MAXB * (MAXN + 1), st));
-    for (int k = n - 1; k >= 1; --k) {
+    for (int k = n - 1; k >= 1 && fast; --k) {
+      int scap = capb[k], ccap = PHYS * capb[k + 1];
+      launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
+      hipLaunchKernelGGL(k_eig_prep<FnEigTrunc<T>>, dim3(1), dim3(64), 0, st,
+                         FnEigTrunc<T>{L, k, cw.G, cw.sq, svdUS, svdWk, sus, rdelta, rdisc,
+                                       chi_cap, istats},
+                         ep, cnt);
+      tbegin(1);
+      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
+                         (const EigProb*)ep, lds_elems, 40, kf(1));
+      tend(1);
+      launch_gemm<double, T, T, double>(FUtM<T>{L, ep, qtmp, qslot, k}, cnt, scap, ccap, 1, st);
+      launch_gemm<T, double, T, double>(FCoreUS2<T>{L, ep, ctmp, maxcore, k}, cnt,
+                                        PHYS * capb[k - 1], scap, 1, st);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)qtmp,
+                         qslot, k);
+      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp,
+                         maxcore, k - 1);
+    }
+    for (int k = n - 1; k >= 1 && !fast; --k) {
       int mcap = PHYS * capb[k + 1], scap = capb[k];
       qr(FnQrRightT<T>{L, k, qtmp, qslot, rbuf, rslot}, cnt, mcap, scap);
       hipLaunchKernelGGL(k_svd_prep<FnSvdTrunc<T>>, dim3(1), dim3(64), 0, st,
@@ -761,7 +1024,7 @@ class Engine {
                                        rdelta, rdisc, chi_cap, istats, nullptr, 0},
                          sp, cnt);
       tbegin(1);
-      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), blk, (size_t)lds_elems * 8, st,
+      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
                          (const SvdProb*)sp, lds_elems, 40, kf(1));
       tend(1);
       launch_gemm<T, double, T, double>(FnCoreTimesUS<T>{L, qp, svdUS, sus, ctmp, maxcore, k},

@@ -343,127 +343,275 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
 }
 
 // ---------------------------------------------------------------------------
-// One-sided Jacobi SVD (FP64) with truncation.
-// L (rows x cols, column-major, ld = rows) and W (cols x cols, column-major)
-// are rotated in place: L W = U S.  Afterwards singular values are sorted,
-// the rank is chosen by the tail rule (smallest r >= 1 with
-// sum_{j >= r} s_j^2 <= delta2, capped at chi) and the kept columns are
-// packed: US (rows x r, row-major, ld r) and Wk (cols x r, row-major, ld r).
-struct SvdProb {
-  double* L;
-  double* W;
-  int rows, cols;
-  int valid;
-  double delta2;   // per-bond threshold
-  int chi;
-  int* rank_out;   // where the chosen rank is stored (an MPS bond)
-  double* US;      // rows x r
-  double* Wk;      // cols x r
-  double* sv;      // singular values (sorted) out, length cols (may be null)
-  double* disc;    // discarded weight out (may be null)
-  int* fail;       // incremented when the sweep limit is hit (may be null)
+// Rank-revealing Cholesky-QR (FP32 precision policy).
+//
+// Pass 1: G = A^T A (FP64), pivoted Cholesky P^T G P = R^T R stopped at the
+// numerical rank rho (remaining diagonal <= eps_rank * max diagonal of G),
+// Q1 = A P R11^{-1} (m x rho).  Pass 2 repeats it on Q1 (Cholesky-QR2), so
+// that Q = Q1 B2 is orthonormal to FP64 rounding; R = R2 R1 P^T (rho x s).
+// Directions with singular value below sqrt(eps_rank) of the largest are
+// dropped, which is below the resolution of FP32 data; the bond then
+// shrinks to rho.  A zero matrix gives rho = 1 with Q = e_0 and R = 0.
+struct CholWork {
+  double* G;     // s x s Gram (pass 1) / rho1 x rho1 (pass 2)
+  double* B1;    // s x rho1 : P R11^{-1}
+  double* R1;    // rho1 x s : R P^T
+  double* B2;    // rho1 x rho2
+  double* R2;    // rho2 x rho1
+  double* Q1;    // m x rho1 (FP64)
+  int* rank;     // [2 * problem]: rho1, rho2
+  long sq, mq;
 };
 
-template <typename F>
-__global__ void k_svd_prep(F f, SvdProb* sp, int nprob) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nprob) sp[i] = f.get(i);
-}
-
-__global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_elems,
-                                                    int max_sweeps, double* flops) {
+// Pivoted Cholesky of G (n x n, row-major, FP64) with threshold; writes
+// B = P[:, :rho] R11^{-1} (n x rho, ld rho) and Rp = R P^T (rho x n, ld n).
+__global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
+                                                  long sq, double* Bbase, double* Rbase,
+                                                  int* rank_out, double eps_rank, int lds_elems,
+                                                  int nprob) {
   extern __shared__ double sh[];
-  __shared__ int rotated;
   __shared__ int perm[1024];
   __shared__ double red[8];
-  SvdProb p = sp[blockIdx.x];
-  if (!p.valid) return;
-  const int m = p.rows, n = p.cols, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nwaves = blockDim.x >> 6;
-  bool in_lds = (long)m * n + (long)n * n <= lds_elems;
-  double* L = in_lds ? sh : p.L;
-  double* W = in_lds ? sh + (long)m * n : p.W;
-  if (in_lds)
-    for (long e = tid; e < (long)m * n; e += blockDim.x) L[e] = p.L[e];
-  for (long e = tid; e < (long)n * n; e += blockDim.x) W[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  __shared__ int ired[8];
+  __shared__ int rho_s;
+  __shared__ double dmax0;
+  __shared__ double dmax_piv;
+  const int pr = blockIdx.x;
+  if (pr >= nprob) return;
+  const int n = dims[pr * dim_stride];
+  if (n <= 0) return;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  double* Gg = Gbase + pr * sq;
+  double* G = ((long)n * n <= lds_elems) ? sh : Gg;
+  if (G != Gg)
+    for (long e = tid; e < (long)n * n; e += blockDim.x) G[e] = Gg[e];
+  for (int i = tid; i < n; i += blockDim.x) perm[i] = i;
   __syncthreads();
-  const double eps = 2.220446049250313e-16;
-  const double tol = eps * sqrt((double)(m > 1 ? m : 1));
-  const int P = (n % 2) ? n + 1 : n;  // players (one dummy if odd)
-  double work = 0.0;  // algorithmic flops of this wave (pairs tested, rotations applied)
+  double dm = 0.0;
+  for (int i = tid; i < n; i += blockDim.x) dm = fmax(dm, G[(long)i * n + i]);
+  for (int o = 32; o > 0; o >>= 1) dm = fmax(dm, __shfl_xor(dm, o, 64));
+  if (lane == 0) red[wv] = dm;
+  __syncthreads();
+  if (tid == 0) {
+    double m = 0.0;
+    for (int i = 0; i < nw; ++i) m = fmax(m, red[i]);
+    dmax0 = m;
+    rho_s = n;
+  }
+  __syncthreads();
+  const double thr = eps_rank * dmax0;
+  int j = 0;
+  for (; j < n; ++j) {
+    // pivot: largest remaining diagonal
+    double best = -1.0;
+    int bi = j;
+    for (int i = j + tid; i < n; i += blockDim.x) {
+      double v = G[(long)i * n + i];
+      if (v > best) { best = v; bi = i; }
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+      double ob = __shfl_xor(best, o, 64);
+      int oi = __shfl_xor(bi, o, 64);
+      if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+    }
+    if (lane == 0) { red[wv] = best; ired[wv] = bi; }
+    __syncthreads();
+    if (tid == 0) {
+      double b = red[0];
+      int ii = ired[0];
+      for (int w = 1; w < nw; ++w)
+        if (red[w] > b || (red[w] == b && ired[w] < ii)) { b = red[w]; ii = ired[w]; }
+      ired[0] = ii;
+      red[0] = b;
+      if (!(b > thr) || !(b > 0.0)) rho_s = j;
+    }
+    __syncthreads();
+    if (rho_s == j) break;
+    const int pv = ired[0];
+    // symmetric swap of rows/cols j and pv (full matrix kept symmetric)
+    if (pv != j) {
+      for (int c = tid; c < n; c += blockDim.x) {
+        double t = G[(long)j * n + c];
+        G[(long)j * n + c] = G[(long)pv * n + c];
+        G[(long)pv * n + c] = t;
+      }
+      __syncthreads();
+      for (int r = tid; r < n; r += blockDim.x) {
+        double t = G[(long)r * n + j];
+        G[(long)r * n + j] = G[(long)r * n + pv];
+        G[(long)r * n + pv] = t;
+      }
+      if (tid == 0) { int t = perm[j]; perm[j] = perm[pv]; perm[pv] = t; }
+      __syncthreads();
+    }
+    if (tid == 0) dmax_piv = sqrt(G[(long)j * n + j]);
+    __syncthreads();  // every thread reads the pivot before row j is overwritten
+    const double rjj = dmax_piv;
+    for (int c = j + tid; c < n; c += blockDim.x)
+      G[(long)j * n + c] = (c == j) ? rjj : G[(long)j * n + c] / rjj;
+    __syncthreads();
+    const int rem = n - j - 1;
+    const long tot = (long)rem * rem;
+    for (long e = tid; e < tot; e += blockDim.x) {
+      int a = j + 1 + (int)(e / rem), b = j + 1 + (int)(e % rem);
+      G[(long)a * n + b] -= G[(long)j * n + a] * G[(long)j * n + b];
+    }
+    __syncthreads();
+  }
+  const int rho = rho_s;
+  const int rr = rho > 0 ? rho : 1;
+  double* B = Bbase + pr * sq;  // n x rr
+  double* Rp = Rbase + pr * sq; // rr x n
+  if (tid == 0) rank_out[pr] = rr;
+  // Rp[r][perm[c]] = R[r][c] (upper trapezoid), zero rank -> zero row
+  for (long e = tid; e < (long)rr * n; e += blockDim.x) {
+    int r = (int)(e / n), c = (int)(e % n);
+    Rp[(long)r * n + perm[c]] = (rho > 0 && c >= r) ? G[(long)r * n + c] : 0.0;
+  }
+  // B = P[:, :rho] R11^{-1}: column c of R11^{-1} by back substitution
+  for (long e = tid; e < (long)n * rr; e += blockDim.x) B[e] = 0.0;
+  __syncthreads();
+  if (rho == 0) {
+    return;
+  }
+  for (int c = tid; c < rho; c += blockDim.x) {
+    // x solves R11 x = e_c; stored into B[perm[i]][c]
+    // use the strictly lower part of G as scratch for x (column c only touches row i < c)
+    double xc = 1.0 / G[(long)c * n + c];
+    B[(long)perm[c] * rr + c] = xc;
+    for (int i = c - 1; i >= 0; --i) {
+      double acc = 0.0;
+      for (int k = i + 1; k <= c; ++k) acc += G[(long)i * n + k] * B[(long)perm[k] * rr + c];
+      B[(long)perm[i] * rr + c] = -acc / G[(long)i * n + i];
+    }
+  }
+}
+
+// k_chol_piv writes its ranks densely (pass 1 into rank[0..n), pass 2 into
+// rank[2 MAXB ..)); this moves them to rank[2 i + pass].
+__global__ void k_cq_spread(int* rank, int nprob, int pass) {
+  if (threadIdx.x != 0) return;
+  if (pass == 0) {
+    for (int i = nprob - 1; i >= 0; --i) rank[2 * i] = rank[i];
+  } else {
+    for (int i = 0; i < nprob; ++i) rank[2 * i + 1] = rank[2 * MAXB + i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided (Hestenes) Jacobi on the n columns of an m x n matrix A stored
+// column-major (ld m): plane rotations orthogonalise column pairs until a
+// whole sweep rotates none, so that A V = U S with mutually orthogonal
+// columns.  W (nw x n, column-major, ld nw), when given, receives the same
+// rotations (W = V when it starts as the identity).  A round of the
+// round-robin tournament ordering pairs disjoint columns, so all its pairs
+// are processed at once: one group of G lanes per pair, G a power of two
+// between 8 and 64 chosen so that the round is spread over every wave of
+// the workgroup.  Works for A and W in LDS or in global memory.
+__device__ inline double group_sum(double v, int G) {
+  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ inline int jacobi_group_lanes(int n, int nwaves) {
+  int pairs = ((n % 2) ? n + 1 : n) / 2;
+  int G = 64;
+  while (G > 8 && (long)pairs * G > 64L * nwaves) G >>= 1;
+  return G;
+}
+
+// Returns the number of sweeps performed (== max_sweeps when the sweep
+// limit stopped it).  `work` accumulates the flops of this thread's group
+// leader; `flag` is a shared int.
+__device__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n, int max_sweeps,
+                             double tol, double& work, int* flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int P = (n % 2) ? n + 1 : n;
+  const int G = jacobi_group_lanes(n, nwaves);
+  const int gpw = 64 / G, gl = lane % G, grp = lane / G;
+  const int par = nwaves * gpw;
   int sweep = 0;
   for (; sweep < max_sweeps && n > 1; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) *flag = 0;
     __syncthreads();
+    int rot = 0;
     for (int t = 0; t < P - 1; ++t) {
-      for (int k = wv; k < P / 2; k += nwaves) {
-        int i1, i2;
-        if (k == 0) { i1 = t; i2 = P - 1; }
-        else { i1 = (t + k) % (P - 1); i2 = (t - k + (P - 1)) % (P - 1); }
-        if (i1 >= n || i2 >= n) continue;
-        int a = i1 < i2 ? i1 : i2, b = i1 < i2 ? i2 : i1;
-        double* ca = L + (long)a * m;
-        double* cb = L + (long)b * m;
-        double al = 0, be = 0, ga = 0;
-        for (int r = lane; r < m; r += 64) {
-          double x = ca[r], y = cb[r];
-          al += x * x; be += y * y; ga += x * y;
+      for (int base = 0; base < P / 2; base += par) {
+        const int k = base + wv * gpw + grp;
+        int i1 = n, i2 = n;
+        if (k < P / 2) {
+          if (k == 0) { i1 = t; i2 = P - 1; }
+          else { i1 = (t + k) % (P - 1); i2 = (t - k + (P - 1)) % (P - 1); }
         }
-        al = wave_sum(al); be = wave_sum(be); ga = wave_sum(ga);
-        work += 6.0 * m;
+        const bool act = i1 < n && i2 < n;
+        const int a = act ? (i1 < i2 ? i1 : i2) : 0, b = act ? (i1 < i2 ? i2 : i1) : 0;
+        double* ca = A + (long)a * m;
+        double* cb = A + (long)b * m;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        if (act)
+          for (int r = gl; r < m; r += G) {
+            double x = ca[r], y = cb[r];
+            al += x * x; be += y * y; ga += x * y;
+          }
+        al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
+        if (!act) continue;
+        if (gl == 0) work += 6.0 * m;
         // relative orthogonality test; sqrt(al) sqrt(be) avoids underflow of al * be
         if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
         double zeta = (be - al) / (2.0 * ga);
         double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        for (int r = lane; r < m; r += 64) {
+        for (int r = gl; r < m; r += G) {
           double x = ca[r], y = cb[r];
           ca[r] = cs * x - sn * y;
           cb[r] = sn * x + cs * y;
         }
-        double* wa = W + (long)a * n;
-        double* wb = W + (long)b * n;
-        for (int r = lane; r < n; r += 64) {
-          double x = wa[r], y = wb[r];
-          wa[r] = cs * x - sn * y;
-          wb[r] = sn * x + cs * y;
+        if (W) {
+          double* wa = W + (long)a * nw;
+          double* wb = W + (long)b * nw;
+          for (int r = gl; r < nw; r += G) {
+            double x = wa[r], y = wb[r];
+            wa[r] = cs * x - sn * y;
+            wb[r] = sn * x + cs * y;
+          }
         }
-        if (lane == 0) rotated = 1;
-        work += 6.0 * m + 6.0 * n;
+        if (gl == 0) work += 6.0 * (m + (W ? nw : 0));
+        rot = 1;
       }
       __syncthreads();
     }
-    int any = rotated;
+    if (rot) *flag = 1;  // every writer stores the same value
+    __syncthreads();
+    const int any = *flag;
     __syncthreads();
     if (!any) break;
   }
-  if (sweep >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
-  if (flops && lane == 0) atomicAdd(flops, work);
-  // singular values = column norms (stored temporarily in W's spare? use global sv)
-  double* sv = p.sv;
-  // column norms into a scratch region: reuse perm-sorted pass with LDS array
-  __shared__ double nrm[1024];
-  __shared__ int nonfin;
-  if (tid == 0) nonfin = 0;
+  return sweep;
+}
+
+// Column norms of A into nrm (a non-finite norm becomes -1 and sets
+// *nonfin), then perm = indices sorted by decreasing norm (ties by index),
+// a permutation whatever the values.
+__device__ void jacobi_sorted_norms(const double* A, int m, int n, double* nrm, int* perm,
+                                    int* nonfin) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwaves = blockDim.x >> 6;
+  if (tid == 0) *nonfin = 0;
   __syncthreads();
   for (int c = wv; c < n; c += nwaves) {
     double acc = 0.0;
-    for (int r = lane; r < m; r += 64) acc += L[(long)c * m + r] * L[(long)c * m + r];
+    for (int r = lane; r < m; r += 64) acc += A[(long)c * m + r] * A[(long)c * m + r];
     acc = wave_sum(acc);
     if (lane == 0) {
       double v = sqrt(acc);
-      // a non-finite norm is ranked last and reported; the sort below must
-      // stay a permutation whatever the values
       if (!(v <= 1.7976931348623157e308)) {
-        nonfin = 1;
+        *nonfin = 1;
         v = -1.0;
       }
       nrm[c] = v;
     }
   }
   __syncthreads();
-  if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
-  // sort descending (rank by counting; ties by index)
   for (int c = tid; c < n; c += blockDim.x) {
     int pos = 0;
     double v = nrm[c];
@@ -474,48 +622,212 @@ __global__ __launch_bounds__(256) void k_jacobi_svd(const SvdProb* sp, int lds_e
     perm[pos] = c;
   }
   __syncthreads();
-  __shared__ int rsel;
-  __shared__ double dsel;
+}
+
+// Rank rule on sorted weights w_j (sigma_j^2): the smallest r >= 1 whose
+// tail sum_{j >= r} w_j is <= delta2, capped at chi and at the numerical
+// rank nz; returns r and the discarded tail.
+__device__ inline int rank_rule_dev(const double* nrm, const int* perm, int n, bool squared,
+                                    double delta2, int chi, int nz, double* tail_out) {
+  double acc = 0.0;
+  int best = n;
+  for (int j = n - 1; j >= 1; --j) {
+    double v = fmax(nrm[perm[j]], 0.0);
+    acc += squared ? v * v : v;
+    if (acc <= delta2) best = j; else break;
+  }
+  int r = best;
+  if (r > nz) r = nz;
+  if (r > chi) r = chi;
+  if (r < 1) r = 1;
+  double tail = 0.0;
+  for (int j = r; j < n; ++j) {
+    double v = fmax(nrm[perm[j]], 0.0);
+    tail += squared ? v * v : v;
+  }
+  *tail_out = tail;
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric eigendecomposition of a Gram matrix G = M M^T (FP64) by
+// one-sided Jacobi on its columns without accumulating rotations: for a
+// positive semi-definite G the rotated columns converge to lambda_j u_j, so
+// lambda_j = ||g_j|| and u_j = g_j / lambda_j (FP32 precision policy).  The
+// truncation rule and packing match k_jacobi_svd with sigma_j =
+// sqrt(lambda_j): US = U_r Sigma_r (s x r) and Ut = Sigma_r^{-1} U_r^T (r x s).
+// Eigenvalues below 1e-14 lambda_max count as zero (the Gram of FP32 data
+// carries no information below that level).
+struct EigProb {
+  double* G;      // s x s (column j contiguous; G is symmetric)
+  int s;
+  int valid;
+  double delta2;
+  int chi;
+  int* rank_out;
+  double* US;
+  double* Ut;
+  double* disc;
+  int* fail;
+};
+
+template <typename F>
+__global__ void k_eig_prep(F f, EigProb* ep, int nprob) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nprob) ep[i] = f.get(i);
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_elems,
+                                                     int max_sweeps, double* flops) {
+  extern __shared__ double sh[];
+  __shared__ int flag, nonfin, rsel;
+  __shared__ int perm[1024];
+  __shared__ double nrm[1024];
+  __shared__ double hc[1024];
+  __shared__ double red[16];
+  EigProb p = ep[blockIdx.x];
+  if (!p.valid) return;
+  const int n = p.s, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const bool in_lds = (long)n * n <= lds_elems;
+  double* L = in_lds ? sh : p.G;
+  if (in_lds)
+    for (long e = tid; e < (long)n * n; e += blockDim.x) L[e] = p.G[e];
+  __syncthreads();
+  double work = 0.0;
+  const int sw = jacobi_sweeps(L, n, nullptr, 0, n, max_sweeps,
+                               2.220446049250313e-16 * sqrt((double)(n > 1 ? n : 1)), work, &flag);
+  if (sw >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
+  if (flops && work > 0.0) atomicAdd(flops, work);
+  jacobi_sorted_norms(L, n, n, nrm, perm, &nonfin);
+  if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
   if (tid == 0) {
-    // tail[r] = sum_{j >= r} s_j^2 ; choose smallest r >= 1 with tail <= delta2
+    double lmax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
+    int nz = 0;
+    for (int j = 0; j < n; ++j)
+      if (nrm[perm[j]] > 1e-14 * lmax) ++nz;
     double tail = 0.0;
-    int r = n;
-    double tail_at_r = 0.0;
-    // walk from the end accumulating
-    double acc = 0.0;
-    int best = n;
-    for (int j = n - 1; j >= 1; --j) {
-      acc += nrm[perm[j]] * nrm[perm[j]];
-      if (acc <= p.delta2) { best = j; tail_at_r = acc; } else break;
-    }
-    r = best;
-    if (r > p.chi) {
-      r = p.chi;
-      tail = 0.0;
-      for (int j = r; j < n; ++j) tail += nrm[perm[j]] * nrm[perm[j]];
-      tail_at_r = tail;
-    }
-    if (r < 1) r = 1;
+    int r = rank_rule_dev(nrm, perm, n, false, p.delta2, p.chi, nz, &tail);
     rsel = r;
-    dsel = tail_at_r;
     if (p.rank_out) *p.rank_out = r;
-    if (p.disc) *p.disc = tail_at_r;
+    if (p.disc) *p.disc = tail;
   }
   __syncthreads();
   const int r = rsel;
-  if (sv)
-    for (int j = tid; j < n; j += blockDim.x) sv[j] = nrm[perm[j]];
-  // pack kept columns: US[row][j] = L[perm[j]][row]; Wk[row][j] = W[perm[j]][row]
+  // u_j = g_j / lambda_j is accurate only up to eps lambda_max / lambda_j in
+  // the directions of the larger eigenvalues; classical Gram-Schmidt applied
+  // twice, in order of decreasing lambda, removes exactly that part and
+  // makes the kept U orthonormal to working precision.
+  for (int j = 0; j < r; ++j) {
+    double* cj = L + (long)perm[j] * n;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = wv; i < j; i += nwaves) {
+        const double* ci = L + (long)perm[i] * n;
+        double acc = 0.0;
+        for (int row = lane; row < n; row += 64) acc += ci[row] * cj[row];
+        acc = wave_sum(acc);
+        if (lane == 0) hc[i] = acc;
+      }
+      __syncthreads();
+      for (int row = tid; row < n; row += blockDim.x) {
+        double v = cj[row];
+        for (int i = 0; i < j; ++i) v -= hc[i] * L[(long)perm[i] * n + row];
+        cj[row] = v;
+      }
+      __syncthreads();
+    }
+    double acc = 0.0;
+    for (int row = tid; row < n; row += blockDim.x) acc += cj[row] * cj[row];
+    acc = block_sum(acc, red);
+    double inv = acc > 0.0 ? 1.0 / sqrt(acc) : 0.0;
+    for (int row = tid; row < n; row += blockDim.x) cj[row] *= inv;
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)n * r; e += blockDim.x) {
+    int row = (int)(e / r), j = (int)(e % r);
+    double sg = sqrt(fmax(nrm[perm[j]], 0.0));
+    double u = L[(long)perm[j] * n + row];
+    // US = U Sigma (s x r) ; Ut = Sigma^{-1} U^T (r x s)
+    p.US[e] = u * sg;
+    p.Ut[(long)j * n + row] = sg > 0.0 ? u / sg : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi SVD (FP64) with truncation.
+// L (rows x cols, column-major, ld = rows) is copied to LDS (or to the
+// scratch L2 when it does not fit) and rotated together with W (cols x
+// cols, the accumulated rotations, in LDS when it fits beside L, else in
+// p.W): L W = U S.  Afterwards singular values are sorted, the rank is
+// chosen by the tail rule (smallest r >= 1 with sum_{j >= r} s_j^2 <=
+// delta2, capped at chi) and the kept columns are packed: US (rows x r,
+// row-major, ld r) and Wk (cols x r, row-major, ld r).
+struct SvdProb {
+  double* L;
+  double* W;       // cols x cols scratch (accumulated rotations when not in LDS)
+  double* Lw;      // rows x cols scratch (the rotated L when not in LDS)
+  int rows, cols;
+  int valid;
+  double delta2;   // per-bond threshold
+  int chi;
+  int* rank_out;   // where the chosen rank is stored (an MPS bond)
+  double* US;      // rows x r
+  double* Wk;      // cols x r
+  double* sv;      // singular values (sorted) out, length cols (may be null)
+  double* disc;    // discarded weight out (may be null)
+  int* fail;       // [0] sweep-limit hits, [1] non-finite values (may be null)
+};
+
+template <typename F>
+__global__ void k_svd_prep(F f, SvdProb* sp, int nprob) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nprob) sp[i] = f.get(i);
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_elems,
+                                                     int max_sweeps, double* flops) {
+  extern __shared__ double sh[];
+  __shared__ int flag, nonfin, rsel;
+  __shared__ int perm[1024];
+  __shared__ double nrm[1024];
+  SvdProb p = sp[blockIdx.x];
+  if (!p.valid) return;
+  const int m = p.rows, n = p.cols, tid = threadIdx.x;
+  const long mn = (long)m * n, nn = (long)n * n;
+  const bool a_lds = mn <= lds_elems;
+  const bool w_lds = a_lds && mn + nn <= lds_elems;
+  double* A = a_lds ? sh : p.Lw;
+  double* W = w_lds ? sh + mn : p.W;
+  for (long e = tid; e < mn; e += blockDim.x) A[e] = p.L[e];
+  for (long e = tid; e < nn; e += blockDim.x) W[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  __syncthreads();
+  double work = 0.0;
+  const int sw = jacobi_sweeps(A, m, W, n, n, max_sweeps,
+                               2.220446049250313e-16 * sqrt((double)(m > 1 ? m : 1)), work, &flag);
+  if (sw >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
+  if (flops && work > 0.0) atomicAdd(flops, work);
+  jacobi_sorted_norms(A, m, n, nrm, perm, &nonfin);
+  if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
+  if (tid == 0) {
+    double tail = 0.0;
+    int r = rank_rule_dev(nrm, perm, n, true, p.delta2, p.chi, n, &tail);
+    rsel = r;
+    if (p.rank_out) *p.rank_out = r;
+    if (p.disc) *p.disc = tail;
+  }
+  __syncthreads();
+  const int r = rsel;
+  if (p.sv)
+    for (int j = tid; j < n; j += blockDim.x) p.sv[j] = nrm[perm[j]];
+  // pack kept columns: US[row][j] = A[perm[j]][row]; Wk[row][j] = W[perm[j]][row]
   for (long e = tid; e < (long)m * r; e += blockDim.x) {
     int row = (int)(e / r), j = (int)(e % r);
-    p.US[e] = L[(long)perm[j] * m + row];
+    p.US[e] = A[(long)perm[j] * m + row];
   }
   for (long e = tid; e < (long)n * r; e += blockDim.x) {
     int row = (int)(e / r), j = (int)(e % r);
     p.Wk[e] = W[(long)perm[j] * n + row];
   }
-  (void)red;
-  (void)dsel;
 }
 
 }  // namespace mpslbm

@@ -119,6 +119,8 @@ struct SimT : Sim {
                                          rest, 1, t, 1},
                               cnt, m, t, 1, st);
       E.qr(FnQrDense<T>{Y, (long)m * t, m, t, E.qtmp, E.qslot, E.rbuf, E.rslot}, cnt, m, t);
+      // the bond is fixed at t here: a rank-revealing QR must keep t columns
+      hipLaunchKernelGGL(k_qr_widen<T>, dim3(cnt), dim3(256), 0, st, E.qp, Y, (long)m * t, cnt);
       hipLaunchKernelGGL(k_store_core<T>, dim3(E.chunks(), cnt), dim3(256), 0, st, L, (const T*)E.qtmp,
                          E.qslot, k);
       // W' = Q^T W  (t x rest)

@@ -105,3 +105,52 @@ def test_one_step_channel8_fp32():
     d.step()
     sim.close()
     assert rel(got, d.f) < 2e-5
+
+
+@pytest.mark.parametrize("which", ["porous16", "vascular16"])
+def test_open_faces_untruncated_fp32(which):
+    """FP32 policy, untruncated (chi at full rank): the dense oracle is the
+    reference; the bound is FP32 rounding accumulated over two steps (each
+    value passes some tens of roundings of relative size ~1e-7)."""
+    L = lib()
+    if which == "porous16":
+        case = WL.case_porous(n=4, chi=64, tol=1e-7)
+    else:
+        case = WL.case_vascular(n=4, chi=64, tol=1e-7)
+    case = _case_with_flow(case)
+    sim = L.Simulation(case, precision="fp32")
+    d = DenseLBM(case)
+    for _ in range(2):
+        sim.step(1)
+        d.step()
+    got = sim.dense(L.POPS)
+    sim.close()
+    r = rel(got, d.f)
+    print(which, "fp32 rel", r, flush=True)
+    assert r < 5e-5
+
+
+def _vel_rel_l2(a, b):
+    return float(np.sqrt(((a - b) ** 2).sum() / max((b ** 2).sum(), 1e-300)))
+
+
+def test_porous32_chi16_truncated_vs_mps_oracle():
+    """Truncated run (chi = 16 < full rank) on a 32^3 porous medium: FP64
+    and FP32 policies against the CPU MPS oracle on the same schedule."""
+    L = lib()
+    case = WL.case_porous(n=5, chi=16, tol=1e-6)
+    case = _case_with_flow(case)
+    m = MPSLBM(case)
+    sims = {p: L.Simulation(case, precision=p) for p in ("fp64", "fp32")}
+    for _ in range(2):
+        m.step()
+        for s in sims.values():
+            s.step(1)
+    ref = m.dense_populations()
+    out = {}
+    for p, s in sims.items():
+        out[p] = rel(s.dense(L.POPS), ref)
+        s.close()
+    print("porous32 chi16 rel vs MPS oracle", out, flush=True)
+    assert out["fp64"] < 1e-6
+    assert out["fp32"] < 1e-3
