@@ -139,6 +139,8 @@ def main():
                    "equiv_mlups": N3 * sps / 1e6, "max_bond": obs.max_bond,
                    "mask_bond": obs.mask_bond, "mask_trunc_err": obs.mask_trunc_err,
                    "roundings_per_step": obs.roundings, "products_per_step": obs.products,
+                   "jacobi_sweeps_mean": obs.jacobi_sweeps, "jacobi_sweep_limit_hits": obs.svd_failures,
+                   "lds_bytes": obs.lds_bytes,
                    "compression": obs.compression},
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)

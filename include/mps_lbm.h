@@ -105,6 +105,8 @@ typedef struct {
   long long products;      /* variational products in the last step         */
   int svd_failures;        /* Jacobi SVDs that hit the sweep limit (total)   */
   int nonfinite;           /* 1 if a NaN/Inf was seen in the state           */
+  double jacobi_sweeps;    /* mean Jacobi sweeps per truncation problem (total) */
+  int lds_bytes;           /* LDS per workgroup the factorisation kernels use */
 } mps_lbm_obs;
 
 /* Fill *cfg with defaults: D3Q19, FP64, TAYLOR2, 2 sweeps, tol 1e-10,
@@ -148,6 +150,24 @@ int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len);
 
 /* Scalar observables (synchronises the stream). */
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
+
+/* mps_lbm_get_mps: index of the obstacle-mask MPS (0..18 are populations) */
+#define MPS_LBM_MPS_MASK 19
+
+/*
+ * Copy one MPS of the state to the host (synchronises the stream).
+ * which = 0..18 selects population i (D3Q19 order above), MPS_LBM_MPS_MASK
+ * the obstacle mask m_O (Section 3.2.1, objects equation).  bonds receives
+ * n + 1 ints: r_0 = 1, r_1, ..., r_n = 1.  When out is non-NULL it receives
+ * the cores one after another, core k (k = 0..n-1) as a C-order FP64 array
+ * [r_k][8][r_{k+1}] (MPS equation, Section 2.1), its middle index being
+ * sigma = 4 x_k + 2 y_k + z_k with x_k the k-th most significant bit of x
+ * (scale ordering, Section 2.4); out_len is the number of doubles at out
+ * and must be at least sum_k r_k 8 r_{k+1}.  Pass out = NULL to read the
+ * bonds only.  Errors: EINVAL (NULL handle or bonds, which out of range, no
+ * obstacle mask, out_len too small), EHIP.
+ */
+int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* bonds);
 
 /* Kernel classes that can be timed for roofline reporting. */
 #define MPS_LBM_K_NONE 0

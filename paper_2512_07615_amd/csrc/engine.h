@@ -674,6 +674,100 @@ struct FCoreUS2 {
 };
 
 // ============================================================================
+// TT-SVD of dense fields (Section 2.1, svd-comp equation).  At site k the
+// remainder M (8 r_k x rest, row-major, rest = 8^(n-1-k)) is factored as
+// M^T = Q R (Householder; Q = I when rest <= 8 r_k) and R^T = U S W^T (Jacobi
+// SVD with the rank rule), so that M = U S (Q W)^T: the kept columns of U are
+// core k and S W^T Q^T is the next remainder.
+template <typename T>
+struct FnTtQr {
+  MpsList<T> L; const T* cur; long slot; int k; long rest; T* qout; double* rout; long rslot;
+  __device__ QrProb<T> get(int i) const {
+    QrProb<T> q;
+    q.A = cur + i * slot;
+    q.m = (int)rest;
+    q.s = PHYS * L.p[i]->r[k];
+    q.sAm = 1; q.sAk = rest;
+    q.p = 0; q.valid = 1;
+    q.Q = qout + i * slot;
+    q.R = rout + i * rslot;
+    return q;
+  }
+};
+
+template <typename T>
+struct FnTtSvd {
+  MpsList<T> L; const QrProb<T>* qp; int k; double* W; long wslot; double* US; double* Wk;
+  long uslot; double* sv; long svslot; const double* delta2; double* disc; int chi; int* fail;
+  __device__ SvdProb get(int i) const {
+    QrProb<T> q = qp[i];
+    SvdProb p;
+    p.L = q.R; p.Lw = q.R; p.W = W + i * wslot;
+    p.rows = q.s; p.cols = q.p; p.valid = 1;
+    p.delta2 = delta2[i]; p.chi = chi;
+    p.rank_out = &L.p[i]->r[k + 1];
+    p.US = US + i * uslot; p.Wk = Wk + i * uslot;
+    p.sv = sv + i * svslot;
+    p.disc = disc + i;
+    p.fail = fail;
+    return p;
+  }
+};
+
+// core k = U_r (U S with column j divided by s_j); Wk column j scaled by s_j
+template <typename T>
+__global__ void k_tt_core(MpsList<T> L, int k, const QrProb<T>* qp, const double* US, double* Wk,
+                          long uslot, const double* sv, long svslot) {
+  const int i = blockIdx.y;
+  MpsDev<T>* d = L.p[i];
+  const int m = PHYS * d->r[k], r = d->r[k + 1], p = qp[i].p;
+  const double* us = US + i * uslot;
+  double* wk = Wk + i * uslot;
+  const double* s = sv + i * svslot;
+  T* core = core_ptr(d, k);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * r;
+       e += (long)gridDim.x * blockDim.x) {
+    double sg = s[e % r];
+    core[e] = (T)(sg > 0.0 ? us[e] / sg : 0.0);
+  }
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)p * r;
+       e += (long)gridDim.x * blockDim.x)
+    wk[e] *= s[e % r];
+}
+
+// next remainder (r x rest) = (Wk S)^T (r x p) * Q^T (p x rest)
+template <typename T>
+struct FnTtNext {
+  MpsList<T> L; const QrProb<T>* qp; const double* Wk; long uslot; T* nxt; long slot; int k;
+  long rest;
+  __device__ GemmDesc<double, T, T> get(int i) const {
+    GemmDesc<double, T, T> d = gemm_empty<double, T, T>();
+    QrProb<T> q = qp[i];
+    const int r = L.p[i]->r[k + 1];
+    d.A = Wk + i * uslot; d.B = q.Q; d.C = nxt + i * slot;
+    d.M = r; d.N = (int)rest; d.K = q.p;
+    d.sAm = 1; d.sAk = r;
+    d.sBk = 1; d.sBn = q.p;
+    d.sCm = rest; d.sCn = 1;
+    d.valid = 1;
+    return d;
+  }
+};
+
+template <typename T>
+__global__ void k_dense_delta2(const T* W, long N3, int cnt, double f, double* out) {
+  __shared__ double red[8];
+  const int i = blockIdx.x;
+  double acc = 0.0;
+  for (long e = threadIdx.x; e < N3; e += blockDim.x) {
+    double v = (double)W[i * N3 + e];
+    acc += v * v;
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) out[i] = f * acc;
+}
+
+// ============================================================================
 template <typename T>
 class Engine {
  public:
@@ -705,7 +799,8 @@ class Engine {
   double* rnorm = nullptr;
   double* rdisc = nullptr;
   double* stats = nullptr;  // [0] max discarded ratio of the current step
-  int* istats = nullptr;    // [0] SVD sweep-limit hits, [1] non-finite flag
+  int* istats = nullptr;    // [0] SVD sweep-limit hits, [1] non-finite flag,
+                            // [2] Jacobi sweeps, [3] Jacobi problems (totals)
   T* envL = nullptr;
   T* envR = nullptr;
   T* T1 = nullptr;
@@ -1379,6 +1474,79 @@ class Engine {
       }
     }
     HIP_OK(hipGetLastError());
+  }
+
+  // TT-SVD of cnt dense scale-ordered fields W (slot N^3 each; overwritten)
+  // into the MPS objs, truncating each bond by the rank rule at tol_r
+  // (threshold tol_r^2 ||W||^2 / (n - 1)) and rank cap chi_r.  Every SVD is
+  // the FP64 Householder + Jacobi pair, whatever the precision policy.
+  void tt_svd(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r) {
+    const long N3 = 1L << (3 * n);
+    MpsList<T> L = list_idx(objs, 0, cnt);
+    RankArr ones;
+    for (int k = 0; k <= MAXN; ++k) ones.r[k] = 1;
+    hipLaunchKernelGGL(k_set_ranks<T>, dim3(1), dim3(64), 0, st, L, ones, cnt);
+    const long mmax = (long)PHYS * std::max(1, std::min(chi_r, maxbond));
+    {
+      // the SVD at site k has min(8^(n-1-k), 8 r_k) columns; one workgroup
+      // handles at most 1024
+      long rest = N3;
+      for (int k = 0; k < n - 1; ++k) {
+        rest /= PHYS;
+        long m = (long)PHYS * std::min<long>(chi_r, full_bound(n, k));
+        if (std::min(rest, m) > 1024)
+          throw Error(-5, "initial decomposition needs an SVD wider than 1024 columns "
+                          "(reduce chi_max)");
+      }
+    }
+    size_t mark = allocs.size();
+    T* nxt = (T*)dalloc(sizeof(T) * N3 * cnt);
+    T* Qb = (T*)dalloc(sizeof(T) * N3 * cnt);
+    double* Rb = (double*)dalloc(8 * mmax * mmax * cnt);
+    double* Wb = (double*)dalloc(8 * mmax * mmax * cnt);
+    double* USb = (double*)dalloc(8 * mmax * mmax * cnt);
+    double* Wkb = (double*)dalloc(8 * mmax * mmax * cnt);
+    double* svb = (double*)dalloc(8 * mmax * cnt);
+    double* d2 = (double*)dalloc(8 * cnt);
+    double* disc = (double*)dalloc(8 * cnt);
+    QrWork tw = qw;
+    tw.Q1 = (double*)dalloc(8 * N3 * cnt);
+    tw.Q2 = (double*)dalloc(8 * N3 * cnt);
+    tw.mq = N3;
+    hipLaunchKernelGGL(k_dense_delta2<T>, dim3(cnt), dim3(256), 0, st, (const T*)W, N3, cnt,
+                       tol_r * tol_r / (double)(n > 1 ? n - 1 : 1), d2);
+    T* cur = W;
+    long rest = N3;
+    for (int k = 0; k < n - 1; ++k) {
+      rest /= PHYS;
+      const int mcap = (int)mmax;
+      hipLaunchKernelGGL((k_qr_prep<T, FnTtQr<T>>), dim3(1), dim3(64), 0, st,
+                         FnTtQr<T>{L, cur, N3, k, rest, Qb, Rb, mmax * mmax}, qp, cnt);
+      int ch = (int)std::max<long>(1, std::min<long>(2048, (rest * mcap + 255) / 256));
+      hipLaunchKernelGGL(k_qr_identity<T>, dim3(ch, cnt), dim3(256), 0, st, (const QrProb<T>*)qp);
+      hipLaunchKernelGGL(k_householder<T>, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
+                         (const QrProb<T>*)qp, tw, lds_elems, (double*)nullptr);
+      hipLaunchKernelGGL(k_svd_prep<FnTtSvd<T>>, dim3(1), dim3(64), 0, st,
+                         FnTtSvd<T>{L, (const QrProb<T>*)qp, k, Wb, mmax * mmax, USb, Wkb,
+                                    mmax * mmax, svb, mmax, d2, disc, chi_r, istats},
+                         sp, cnt);
+      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
+                         (const SvdProb*)sp, lds_elems, 60, (double*)nullptr);
+      hipLaunchKernelGGL(k_tt_core<T>, dim3(64, cnt), dim3(256), 0, st, L, k, (const QrProb<T>*)qp,
+                         (const double*)USb, Wkb, mmax * mmax, (const double*)svb, mmax);
+      launch_gemm<double, T, T, double>(
+          FnTtNext<T>{L, (const QrProb<T>*)qp, Wkb, mmax * mmax, nxt, N3, k, rest}, cnt,
+          std::min(chi_r, maxbond), (int)rest, 1, st);
+      std::swap(cur, nxt);
+    }
+    hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), dim3(256), 0, st, L, (const T*)cur, N3,
+                       n - 1);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    while (allocs.size() > mark) {
+      (void)hipFree(allocs.back());
+      allocs.pop_back();
+    }
   }
 };
 

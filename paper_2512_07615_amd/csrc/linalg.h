@@ -524,7 +524,7 @@ __device__ inline int jacobi_group_lanes(int n, int nwaves) {
 // limit stopped it).  `work` accumulates the flops of this thread's group
 // leader; `flag` is a shared int.
 __device__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n, int max_sweeps,
-                             double tol, double& work, int* flag) {
+                             double tol, double small2, double& work, int* flag) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   const int P = (n % 2) ? n + 1 : n;
@@ -557,8 +557,11 @@ __device__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n, int max
         al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
         if (!act) continue;
         if (gl == 0) work += 6.0 * m;
-        // relative orthogonality test; sqrt(al) sqrt(be) avoids underflow of al * be
+        // relative orthogonality test; sqrt(al) sqrt(be) avoids underflow of
+        // al * be; a column below the rounding level of the whole matrix
+        // (norm^2 <= small2) is numerically zero and is not rotated
         if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        if (al <= small2 || be <= small2) continue;
         double zeta = (be - al) / (2.0 * ga);
         double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
         double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
@@ -688,16 +691,27 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
   EigProb p = ep[blockIdx.x];
   if (!p.valid) return;
   const int n = p.s, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (n > 1024) {  // beyond the index arrays: refused (callers never get here)
+    if (tid == 0 && p.fail) atomicAdd(p.fail + 1, 1);
+    return;
+  }
   const int nwaves = blockDim.x >> 6;
   const bool in_lds = (long)n * n <= lds_elems;
   double* L = in_lds ? sh : p.G;
   if (in_lds)
     for (long e = tid; e < (long)n * n; e += blockDim.x) L[e] = p.G[e];
-  __syncthreads();
+  double fro2 = 0.0;
+  for (long e = tid; e < (long)n * n; e += blockDim.x) fro2 += L[e] * L[e];
+  fro2 = block_sum(fro2, red);
+  const double eps = 2.220446049250313e-16;
   double work = 0.0;
-  const int sw = jacobi_sweeps(L, n, nullptr, 0, n, max_sweeps,
-                               2.220446049250313e-16 * sqrt((double)(n > 1 ? n : 1)), work, &flag);
-  if (sw >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
+  const int sw = jacobi_sweeps(L, n, nullptr, 0, n, max_sweeps, eps * sqrt((double)(n > 1 ? n : 1)),
+                               eps * eps * fro2, work, &flag);
+  if (tid == 0 && p.fail) {
+    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
+    atomicAdd(p.fail + 2, sw);
+    atomicAdd(p.fail + 3, 1);
+  }
   if (flops && work > 0.0) atomicAdd(flops, work);
   jacobi_sorted_norms(L, n, n, nrm, perm, &nonfin);
   if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
@@ -775,7 +789,7 @@ struct SvdProb {
   double* Wk;      // cols x r
   double* sv;      // singular values (sorted) out, length cols (may be null)
   double* disc;    // discarded weight out (may be null)
-  int* fail;       // [0] sweep-limit hits, [1] non-finite values (may be null)
+  int* fail;       // [0] sweep-limit hits, [1] non-finite values, [2] sweeps, [3] problems
 };
 
 template <typename F>
@@ -790,9 +804,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_
   __shared__ int flag, nonfin, rsel;
   __shared__ int perm[1024];
   __shared__ double nrm[1024];
+  __shared__ double red[16];
   SvdProb p = sp[blockIdx.x];
   if (!p.valid) return;
   const int m = p.rows, n = p.cols, tid = threadIdx.x;
+  if (n > 1024) {  // beyond the index arrays: refused (callers never get here)
+    if (tid == 0 && p.fail) atomicAdd(p.fail + 1, 1);
+    return;
+  }
   const long mn = (long)m * n, nn = (long)n * n;
   const bool a_lds = mn <= lds_elems;
   const bool w_lds = a_lds && mn + nn <= lds_elems;
@@ -800,11 +819,18 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_
   double* W = w_lds ? sh + mn : p.W;
   for (long e = tid; e < mn; e += blockDim.x) A[e] = p.L[e];
   for (long e = tid; e < nn; e += blockDim.x) W[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
-  __syncthreads();
+  double fro2 = 0.0;
+  for (long e = tid; e < mn; e += blockDim.x) fro2 += p.L[e] * p.L[e];
+  fro2 = block_sum(fro2, red);
+  const double eps = 2.220446049250313e-16;
   double work = 0.0;
-  const int sw = jacobi_sweeps(A, m, W, n, n, max_sweeps,
-                               2.220446049250313e-16 * sqrt((double)(m > 1 ? m : 1)), work, &flag);
-  if (sw >= max_sweeps && tid == 0 && p.fail) atomicAdd(p.fail, 1);
+  const int sw = jacobi_sweeps(A, m, W, n, n, max_sweeps, eps * sqrt((double)(m > 1 ? m : 1)),
+                               eps * eps * fro2, work, &flag);
+  if (tid == 0 && p.fail) {
+    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
+    atomicAdd(p.fail + 2, sw);
+    atomicAdd(p.fail + 3, 1);
+  }
   if (flops && work > 0.0) atomicAdd(flops, work);
   jacobi_sorted_norms(A, m, n, nrm, perm, &nonfin);
   if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);

@@ -42,6 +42,7 @@ struct Sim {
   virtual void observables(mps_lbm_obs* o) = 0;
   virtual void set_timing(int kind) = 0;
   virtual void kstats(mps_lbm_kstats* o) = 0;
+  virtual int get_mps(int which, double* out, size_t out_len, int* bonds) = 0;
 };
 
 template <typename T>
@@ -74,68 +75,14 @@ struct SimT : Sim {
     chi_mask = c.chi_mask_max > 0 ? std::min(c.chi_mask_max, c.chi_max) : c.chi_max;
   }
 
-  // --- dense -> MPS: randomized range finder at the capacity bonds, then
-  // an exact rounding to (chi, tol).  W holds cnt scale-ordered fields.
+  // --- dense -> MPS: TT-SVD (Section 2.1, svd-comp equation) of cnt
+  // scale-ordered fields W, truncated at (chi_r, tol_r).  W is overwritten.
   int dense_chunks(long count) const {
     return (int)std::max<long>(1, std::min<long>(2048, (count + 255) / 256));
   }
 
-  void dense_to_mps(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r,
-                    unsigned long long seed) {
-    int tgt[MAXN + 1];
-    tgt[0] = 1;
-    tgt[n] = 1;
-    for (int k = 1; k < n; ++k) {
-      long m = (long)tgt[k - 1] * PHYS;
-      long rest = 1;
-      for (int j = 0; j < n - k; ++j) rest *= PHYS;
-      long t = std::min<long>(m, std::min<long>(rest, E.capb[k]));
-      tgt[k] = (int)t;
-    }
-    RankArr ra;
-    for (int k = 0; k <= n; ++k) ra.r[k] = tgt[k];
-    MpsList<T> L = E.list_idx(objs, 0, cnt);
-    hipLaunchKernelGGL(k_set_ranks<T>, dim3(1), dim3(64), 0, st, L, ra, cnt);
-    T* Wn = (T*)E.dalloc(sizeof(T) * N3 * cnt);
-    long maxY = 0;
-    for (int k = 1; k < n; ++k) maxY = std::max(maxY, (long)tgt[k - 1] * PHYS * tgt[k]);
-    T* Y = (T*)E.dalloc(sizeof(T) * std::max<long>(maxY, 1) * cnt);
-    T* Om = (T*)E.dalloc(sizeof(T) * std::max<long>(N3, 1));
-    T* cur = W;
-    for (int k = 0; k < n - 1; ++k) {
-      int m = tgt[k] * PHYS, t = tgt[k + 1];
-      long rest = N3 / ((long)tgt[k] * PHYS) / 1;  // columns of the current W (m x rest)
-      rest = N3;
-      for (int j = 0; j <= k; ++j) rest /= PHYS;
-      if (t == m) {
-        hipLaunchKernelGGL(k_set_identity_core<T>, dim3(E.chunks(), cnt), dim3(256), 0, st, L, k, m);
-        continue;  // W (m x rest) is reinterpreted at the next site
-      }
-      // W currently holds (tgt[k] * 8) x rest per field
-      long cnt_om = rest * t;
-      hipLaunchKernelGGL(k_gauss<T>, dim3(dense_chunks(cnt_om)), dim3(256), 0, st, Om, cnt_om,
-                         (uint64_t)(seed * 1315423911ull + k + 1));
-      launch_gemm<T, T, T, T>(FnDense<T>{cur, N3, Om, 0, Y, (long)m * t, m, t, (int)rest,
-                                         rest, 1, t, 1},
-                              cnt, m, t, 1, st);
-      E.qr(FnQrDense<T>{Y, (long)m * t, m, t, E.qtmp, E.qslot, E.rbuf, E.rslot}, cnt, m, t);
-      // the bond is fixed at t here: a rank-revealing QR must keep t columns
-      hipLaunchKernelGGL(k_qr_widen<T>, dim3(cnt), dim3(256), 0, st, E.qp, Y, (long)m * t, cnt);
-      hipLaunchKernelGGL(k_store_core<T>, dim3(E.chunks(), cnt), dim3(256), 0, st, L, (const T*)E.qtmp,
-                         E.qslot, k);
-      // W' = Q^T W  (t x rest)
-      launch_gemm<T, T, T, T>(FnDense<T>{E.qtmp, E.qslot, cur, N3, Wn, N3, t, (int)rest, m, 1, t,
-                                         rest, 1},
-                              cnt, t, (int)rest, 1, st);
-      std::swap(cur, Wn);
-    }
-    hipLaunchKernelGGL(k_store_core<T>, dim3(E.chunks(), cnt), dim3(256), 0, st, L, (const T*)cur, N3,
-                       n - 1);
-    HIP_OK(hipGetLastError());
-    E.round(objs, chi_r, tol_r);
-    HIP_OK(hipStreamSynchronize(st));
-    // scratch buffers are released with the engine; keep memory bounded
-    free_last(3);
+  void dense_to_mps(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r) {
+    E.tt_svd(W, cnt, objs, chi_r, tol_r);
   }
 
   void free_last(int k) {
@@ -175,7 +122,7 @@ struct SimT : Sim {
       T* Wkeep = (T*)E.dalloc(sizeof(T) * N3);
       hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W, Wkeep,
                          N3);
-      dense_to_mps(W, 1, {mask}, chi_mask, cfg.tol_mask, cfg.seed ^ 0x5a5a5a5aull);
+      dense_to_mps(W, 1, {mask}, chi_mask, cfg.tol_mask);
       // decomposition error of the mask
       T* back = (T*)E.dalloc(sizeof(T) * N3);
       T* work = (T*)E.dalloc(sizeof(T) * N3);
@@ -228,7 +175,7 @@ struct SimT : Sim {
                        st, (const double*)dd, W, n, 19, 1);
     std::vector<int> objs(19);
     for (int i = 0; i < 19; ++i) objs[i] = f[i] = E.acquire();
-    dense_to_mps(W, 19, objs, cfg.chi_max, cfg.tol, cfg.seed);
+    dense_to_mps(W, 19, objs, cfg.chi_max, cfg.tol);
     HIP_OK(hipStreamSynchronize(st));
     // release the dense staging (W, dd, and the solid copy)
     (void)hipFree(W);
@@ -488,6 +435,30 @@ struct SimT : Sim {
     if (mom) (void)hipFree(mom);
   }
 
+  int get_mps(int which, double* out, size_t out_len, int* bonds) override {
+    int idx = which < 19 ? f[which] : mask;
+    if (idx < 0) return fail(MPS_LBM_EINVAL, "no obstacle mask in this simulation");
+    MpsDev<T> d;
+    HIP_OK(hipMemcpyAsync(&d, E.D(idx), sizeof(d), hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    size_t need = 0;
+    for (int k = 0; k <= n; ++k) bonds[k] = d.r[k];
+    for (int k = 0; k < n; ++k) need += (size_t)d.r[k] * PHYS * d.r[k + 1];
+    if (!out) return MPS_LBM_OK;
+    if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
+    std::vector<T> tmp(need);
+    size_t pos = 0;
+    for (int k = 0; k < n; ++k) {
+      size_t cnt = (size_t)d.r[k] * PHYS * d.r[k + 1];
+      HIP_OK(hipMemcpyAsync(tmp.data() + pos, d.data + d.off[k], sizeof(T) * cnt,
+                            hipMemcpyDeviceToHost, st));
+      pos += cnt;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    for (size_t e = 0; e < need; ++e) out[e] = (double)tmp[e];
+    return MPS_LBM_OK;
+  }
+
   void set_timing(int kind) override { E.timing(kind); }
 
   void kstats(mps_lbm_kstats* o) override {
@@ -505,10 +476,10 @@ struct SimT : Sim {
     E.inner_ones(objs, scratch);
     double s[19];
     double stat[2] = {0, 0};
-    int ist[2] = {0, 0};
+    int ist[4] = {0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(s, scratch, 8 * 19, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(stat, E.stats, 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(ist, E.istats, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ist, E.istats, 16, hipMemcpyDeviceToHost, st));
     double r0 = 0.0;
     HIP_OK(hipMemcpyAsync(&r0, rho0, 8, hipMemcpyDeviceToHost, st));
     std::vector<MpsDev<T>> descs(19);
@@ -546,6 +517,8 @@ struct SimT : Sim {
     o->products = last_products;
     o->svd_failures = ist[0];
     o->nonfinite = ist[1];
+    o->jacobi_sweeps = ist[3] > 0 ? (double)ist[2] / ist[3] : 0.0;
+    o->lds_bytes = E.lds_elems * 8;
   }
 };
 
@@ -662,6 +635,19 @@ int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len) {
   try {
     h->sim->to_dense(what, out);
     return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(MPS_LBM_EHIP, e.what());
+  }
+}
+
+int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* bonds) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!bonds) return fail(MPS_LBM_EINVAL, "bonds is NULL");
+  if (which < 0 || which > MPS_LBM_MPS_MASK) return fail(MPS_LBM_EINVAL, "bad which");
+  try {
+    return h->sim->get_mps(which, out, out_len, bonds);
   } catch (const Error& e) {
     return fail(e.code, e.what());
   } catch (const std::exception& e) {

@@ -26,11 +26,12 @@ BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
 POPS, RHO, J, VEL = 0, 1, 2, 3
 
 K_NONE, K_JACOBI, K_HOUSEHOLDER, K_PRODGEMM = 0, 1, 2, 3
+MPS_MASK = 19
 
 EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
                    "mps_lbm_to_dense", "mps_lbm_observables", "mps_lbm_destroy",
                    "mps_lbm_last_error", "mps_lbm_version", "mps_lbm_kernel_timing",
-                   "mps_lbm_kernel_stats"])
+                   "mps_lbm_kernel_stats", "mps_lbm_get_mps"])
 
 
 class Config(C.Structure):
@@ -52,6 +53,7 @@ class Obs(C.Structure):
         ("compression", C.c_double), ("max_discarded", C.c_double), ("mask_bond", C.c_int),
         ("mask_trunc_err", C.c_double), ("roundings", C.c_longlong),
         ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
+        ("jacobi_sweeps", C.c_double), ("lds_bytes", C.c_int),
     ]
 
 
@@ -93,6 +95,8 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_kernel_timing.restype = C.c_int
     lib.mps_lbm_kernel_stats.argtypes = [P, C.POINTER(KStats)]
     lib.mps_lbm_kernel_stats.restype = C.c_int
+    lib.mps_lbm_get_mps.argtypes = [P, C.c_int, DP, C.c_size_t, C.POINTER(C.c_int)]
+    lib.mps_lbm_get_mps.restype = C.c_int
     _lib = lib
     return lib
 
@@ -162,6 +166,22 @@ def mps_lbm_kernel_stats(h) -> KStats:
     return k
 
 
+def mps_lbm_get_mps(h, which: int, n: int):
+    """One MPS of the state as a list of FP64 cores [r_k][8][r_{k+1}]."""
+    lib = load()
+    bonds = (C.c_int * (n + 1))()
+    _check(lib.mps_lbm_get_mps(h, int(which), None, 0, bonds))
+    b = [int(bonds[k]) for k in range(n + 1)]
+    sizes = [b[k] * 8 * b[k + 1] for k in range(n)]
+    out = np.empty(sum(sizes), dtype=np.float64)
+    _check(lib.mps_lbm_get_mps(h, int(which), _dp(out), out.size, bonds))
+    cores, pos = [], 0
+    for k in range(n):
+        cores.append(out[pos:pos + sizes[k]].reshape(b[k], 8, b[k + 1]).copy())
+        pos += sizes[k]
+    return cores
+
+
 def mps_lbm_destroy(h):
     if h:
         load().mps_lbm_destroy(h)
@@ -216,6 +236,9 @@ class Simulation:
 
     def kernel_stats(self):
         return mps_lbm_kernel_stats(self.h)
+
+    def mps(self, which):
+        return mps_lbm_get_mps(self.h, which, self.case.n)
 
     def close(self):
         if self.h:
