@@ -608,6 +608,12 @@ __global__ void k_qr_widen(QrProb<T>* qp, T* tmp, long tslot, int nprob) {
   if (threadIdx.x == 0) qp[i].p = q.s;
 }
 
+template <typename T>
+__global__ void k_rank_dims(MpsList<T> L, int k, int* out, int cnt) {
+  int i = threadIdx.x;
+  if (i < cnt) out[i] = L.p[i]->r[k];
+}
+
 // Gram of the right unfolding M (r_k x 8 r_{k+1}) of core k: G = M M^T (FP64)
 template <typename T>
 struct FGramM {
@@ -625,12 +631,13 @@ struct FGramM {
 };
 template <typename T>
 struct FnEigTrunc {
-  MpsList<T> L; int k; double* G; long sq; double* US; double* Ut; long sus;
+  MpsList<T> L; int k; double* Rp; long sq; const int* crank; double* US; double* Ut; long sus;
   const double* delta2; double* disc; int chi; int* fail;
   __device__ EigProb get(int i) const {
     EigProb p;
-    p.G = G + i * sq;
+    p.A = Rp + i * sq;  // R P^T (c x s, row-major) read as its transpose
     p.s = L.p[i]->r[k];
+    p.c = crank[i];
     p.valid = 1;
     p.delta2 = delta2[i];
     p.chi = chi;
@@ -1095,9 +1102,13 @@ class Engine {
     for (int k = n - 1; k >= 1 && fast; --k) {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
       launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
+      hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
+      hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
+                         (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
+                         lds_elems, cnt, 0);
       hipLaunchKernelGGL(k_eig_prep<FnEigTrunc<T>>, dim3(1), dim3(64), 0, st,
-                         FnEigTrunc<T>{L, k, cw.G, cw.sq, svdUS, svdWk, sus, rdelta, rdisc,
-                                       chi_cap, istats},
+                         FnEigTrunc<T>{L, k, cw.R1, cw.sq, (const int*)cw.rank, svdUS, svdWk,
+                                       sus, rdelta, rdisc, chi_cap, istats},
                          ep, cnt);
       tbegin(1);
       hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,

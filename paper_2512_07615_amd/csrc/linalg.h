@@ -238,19 +238,26 @@ __global__ void k_qr_export_r(const QrProb<T>* qp, const double* Racc, long sq) 
 }
 
 // ---------------------------------------------------------------------------
-// Householder QR (FP64), one workgroup per problem, for m > s.  Reflectors
+// Householder QR with column pivoting (FP64), one workgroup per problem, for
+// m > s: A P = Q R.  At step j the remaining column of largest norm is
+// moved to position j (norms downdated after each reflector), which grades
+// R so that a Jacobi SVD of R^T converges in a few sweeps.  Reflectors
 // follow the usual convention H = I - tau v v^T, v_0 = 1,
 // beta = -sign(alpha) ||x||; a column that is already zero below the
 // diagonal gets tau = 0.  Q = H_0 ... H_{p-1} [I; 0] is formed explicitly,
-// so it is orthonormal for every input, rank-deficient ones included.
-// Working copies live in LDS when they fit, else in the FP64 workspaces.
+// so it is orthonormal for every input, rank-deficient ones included.  The
+// R written out is R P^T, so that A = Q (R P^T) for the caller.  Working
+// copies live in LDS when they fit, else in the FP64 workspaces.
 template <typename T>
 __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork w,
                                                      int lds_elems, double* flops) {
   extern __shared__ double sh[];
   __shared__ double tau_s[1024];
+  __shared__ double cn[1024];
+  __shared__ int cperm[1024];
   __shared__ double red[8];
   __shared__ double bcast[2];
+  __shared__ int piv;
   QrProb<T> q = qp[blockIdx.x];
   if (!q.valid || q.m <= q.s) return;
   const int m = q.m, s = q.s, p = q.p, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -263,7 +270,36 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
     Wk[e] = (double)q.A[(long)i * q.sAm + (long)c * q.sAk];
   }
   __syncthreads();
+  for (int c = wv; c < s; c += nw) {
+    double acc = 0.0;
+    for (int i = lane; i < m; i += 64) acc += Wk[(long)c * m + i] * Wk[(long)c * m + i];
+    acc = wave_sum(acc);
+    if (lane == 0) { cn[c] = acc; cperm[c] = c; }
+  }
+  __syncthreads();
   for (int j = 0; j < p; ++j) {
+    // pivot: remaining column of largest (downdated) norm
+    if (tid == 0) {
+      int b = j;
+      double bv = cn[j];
+      for (int c = j + 1; c < s; ++c)
+        if (cn[c] > bv) { bv = cn[c]; b = c; }
+      piv = b;
+    }
+    __syncthreads();
+    const int pv = piv;
+    if (pv != j) {
+      for (int i = tid; i < m; i += blockDim.x) {
+        double t = Wk[(long)j * m + i];
+        Wk[(long)j * m + i] = Wk[(long)pv * m + i];
+        Wk[(long)pv * m + i] = t;
+      }
+      if (tid == 0) {
+        double t = cn[j]; cn[j] = cn[pv]; cn[pv] = t;
+        int u = cperm[j]; cperm[j] = cperm[pv]; cperm[pv] = u;
+      }
+      __syncthreads();
+    }
     double* col = Wk + (long)j * m;
     double part = 0.0;
     for (int i = j + 1 + tid; i < m; i += blockDim.x) part += col[i] * col[i];
@@ -296,15 +332,21 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
         acc = wave_sum(acc) + cj;
         acc *= tau;
         for (int i = j + 1 + lane; i < m; i += 64) cc[i] -= acc * col[i];
-        if (lane == 0) cc[j] -= acc;
+        if (lane == 0) {
+          const double rj = cj - acc;  // R[j][c]
+          cc[j] = rj;
+          cn[c] = fmax(cn[c] - rj * rj, 0.0);
+        }
       }
+    } else {
+      for (int c = j + 1 + tid; c < s; c += blockDim.x) cn[c] = fmax(cn[c] - Wk[(long)c * m + j] * Wk[(long)c * m + j], 0.0);
     }
     __syncthreads();
   }
-  // R (p x s), zero below the diagonal
+  // R P^T (p x s): column cperm[c] of the output is column c of R
   for (long e = tid; e < (long)p * s; e += blockDim.x) {
     int i = (int)(e / s), c = (int)(e % s);
-    q.R[e] = (c >= i) ? Wk[(long)c * m + i] : 0.0;
+    q.R[(long)i * s + cperm[c]] = (c >= i) ? Wk[(long)c * m + i] : 0.0;
   }
   // Q = H_0 ... H_{p-1} [I; 0]
   for (long e = tid; e < (long)m * p; e += blockDim.x) {
@@ -368,7 +410,7 @@ struct CholWork {
 __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
                                                   long sq, double* Bbase, double* Rbase,
                                                   int* rank_out, double eps_rank, int lds_elems,
-                                                  int nprob) {
+                                                  int nprob, int want_b = 1) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[8];
@@ -468,6 +510,7 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
     int r = (int)(e / n), c = (int)(e % n);
     Rp[(long)r * n + perm[c]] = (rho > 0 && c >= r) ? G[(long)r * n + c] : 0.0;
   }
+  if (!want_b) return;
   // B = P[:, :rho] R11^{-1}: column c of R11^{-1} by back substitution
   for (long e = tid; e < (long)n * rr; e += blockDim.x) B[e] = 0.0;
   __syncthreads();
@@ -508,8 +551,25 @@ __global__ void k_cq_spread(int* rank, int nprob, int pass) {
 // are processed at once: one group of G lanes per pair, G a power of two
 // between 8 and 64 chosen so that the round is spread over every wave of
 // the workgroup.  Works for A and W in LDS or in global memory.
+// Cross-lane moves for FP64 values: DPP within rows of 16 lanes (quad
+// permutations, half-row and row mirrors), ds_bpermute across rows.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+  int lo = __double2loint(v), hi = __double2hiint(v);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G lanes (G a power of two <= 64); every lane
+// of the group receives the sum.
 __device__ inline double group_sum(double v, int G) {
-  for (int o = G >> 1; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if (G >= 2) v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+  if (G >= 4) v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  if (G >= 8) v += dpp_f64<0x141>(v);  // row_half_mirror
+  if (G >= 16) v += dpp_f64<0x140>(v); // row_mirror
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
   return v;
 }
 
@@ -653,17 +713,18 @@ __device__ inline int rank_rule_dev(const double* nrm, const int* perm, int n, b
 }
 
 // ---------------------------------------------------------------------------
-// Symmetric eigendecomposition of a Gram matrix G = M M^T (FP64) by
-// one-sided Jacobi on its columns without accumulating rotations: for a
-// positive semi-definite G the rotated columns converge to lambda_j u_j, so
-// lambda_j = ||g_j|| and u_j = g_j / lambda_j (FP32 precision policy).  The
-// truncation rule and packing match k_jacobi_svd with sigma_j =
-// sqrt(lambda_j): US = U_r Sigma_r (s x r) and Ut = Sigma_r^{-1} U_r^T (r x s).
-// Eigenvalues below 1e-14 lambda_max count as zero (the Gram of FP32 data
-// carries no information below that level).
+// Truncated eigendecomposition of a Gram matrix G = M M^T (FP32 policy).
+// The caller factors G = A A^T by pivoted Cholesky (A = (R P^T)^T, s x c,
+// c the numerical rank); one-sided Jacobi on the columns of A then gives
+// A V = U Sigma with G = U Sigma^2 U^T.  The pivoting grades A so that the
+// sweeps converge in a few passes, and the relative orthogonality test of
+// the sweeps leaves the normalised columns orthonormal to FP64 rounding
+// without accumulating V.  The rank rule runs on sigma_j^2, ignoring
+// sigma_j^2 <= 1e-14 sigma_max^2 (FP32 data carry nothing below); packed
+// outputs: US = U_r Sigma_r (s x r) and Ut = Sigma_r^{-1} U_r^T (r x s).
 struct EigProb {
-  double* G;      // s x s (column j contiguous; G is symmetric)
-  int s;
+  double* A;      // s x c, column-major (ld s); rotated in place when not in LDS
+  int s, c;
   int valid;
   double delta2;
   int chi;
@@ -686,26 +747,26 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
   __shared__ int flag, nonfin, rsel;
   __shared__ int perm[1024];
   __shared__ double nrm[1024];
-  __shared__ double hc[1024];
   __shared__ double red[16];
   EigProb p = ep[blockIdx.x];
   if (!p.valid) return;
-  const int n = p.s, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  if (n > 1024) {  // beyond the index arrays: refused (callers never get here)
+  const int s = p.s, c = p.c, tid = threadIdx.x;
+  if (c > 1024) {  // beyond the index arrays: refused (callers never get here)
     if (tid == 0 && p.fail) atomicAdd(p.fail + 1, 1);
     return;
   }
-  const int nwaves = blockDim.x >> 6;
-  const bool in_lds = (long)n * n <= lds_elems;
-  double* L = in_lds ? sh : p.G;
+  const long sc = (long)s * c;
+  const bool in_lds = sc <= lds_elems;
+  double* A = in_lds ? sh : p.A;
   if (in_lds)
-    for (long e = tid; e < (long)n * n; e += blockDim.x) L[e] = p.G[e];
+    for (long e = tid; e < sc; e += blockDim.x) A[e] = p.A[e];
+  __syncthreads();
   double fro2 = 0.0;
-  for (long e = tid; e < (long)n * n; e += blockDim.x) fro2 += L[e] * L[e];
+  for (long e = tid; e < sc; e += blockDim.x) fro2 += A[e] * A[e];
   fro2 = block_sum(fro2, red);
   const double eps = 2.220446049250313e-16;
   double work = 0.0;
-  const int sw = jacobi_sweeps(L, n, nullptr, 0, n, max_sweeps, eps * sqrt((double)(n > 1 ? n : 1)),
+  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, eps * sqrt((double)(s > 1 ? s : 1)),
                                eps * eps * fro2, work, &flag);
   if (tid == 0 && p.fail) {
     if (sw >= max_sweeps) atomicAdd(p.fail, 1);
@@ -713,57 +774,27 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
     atomicAdd(p.fail + 3, 1);
   }
   if (flops && work > 0.0) atomicAdd(flops, work);
-  jacobi_sorted_norms(L, n, n, nrm, perm, &nonfin);
+  jacobi_sorted_norms(A, s, c, nrm, perm, &nonfin);
   if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
   if (tid == 0) {
-    double lmax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
+    double smax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
     int nz = 0;
-    for (int j = 0; j < n; ++j)
-      if (nrm[perm[j]] > 1e-14 * lmax) ++nz;
+    for (int j = 0; j < c; ++j)
+      if (nrm[perm[j]] * nrm[perm[j]] > 1e-14 * smax * smax) ++nz;
     double tail = 0.0;
-    int r = rank_rule_dev(nrm, perm, n, false, p.delta2, p.chi, nz, &tail);
+    int r = rank_rule_dev(nrm, perm, c, true, p.delta2, p.chi, nz, &tail);
     rsel = r;
     if (p.rank_out) *p.rank_out = r;
     if (p.disc) *p.disc = tail;
   }
   __syncthreads();
   const int r = rsel;
-  // u_j = g_j / lambda_j is accurate only up to eps lambda_max / lambda_j in
-  // the directions of the larger eigenvalues; classical Gram-Schmidt applied
-  // twice, in order of decreasing lambda, removes exactly that part and
-  // makes the kept U orthonormal to working precision.
-  for (int j = 0; j < r; ++j) {
-    double* cj = L + (long)perm[j] * n;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = wv; i < j; i += nwaves) {
-        const double* ci = L + (long)perm[i] * n;
-        double acc = 0.0;
-        for (int row = lane; row < n; row += 64) acc += ci[row] * cj[row];
-        acc = wave_sum(acc);
-        if (lane == 0) hc[i] = acc;
-      }
-      __syncthreads();
-      for (int row = tid; row < n; row += blockDim.x) {
-        double v = cj[row];
-        for (int i = 0; i < j; ++i) v -= hc[i] * L[(long)perm[i] * n + row];
-        cj[row] = v;
-      }
-      __syncthreads();
-    }
-    double acc = 0.0;
-    for (int row = tid; row < n; row += blockDim.x) acc += cj[row] * cj[row];
-    acc = block_sum(acc, red);
-    double inv = acc > 0.0 ? 1.0 / sqrt(acc) : 0.0;
-    for (int row = tid; row < n; row += blockDim.x) cj[row] *= inv;
-    __syncthreads();
-  }
-  for (long e = tid; e < (long)n * r; e += blockDim.x) {
+  for (long e = tid; e < (long)s * r; e += blockDim.x) {
     int row = (int)(e / r), j = (int)(e % r);
-    double sg = sqrt(fmax(nrm[perm[j]], 0.0));
-    double u = L[(long)perm[j] * n + row];
-    // US = U Sigma (s x r) ; Ut = Sigma^{-1} U^T (r x s)
-    p.US[e] = u * sg;
-    p.Ut[(long)j * n + row] = sg > 0.0 ? u / sg : 0.0;
+    double sg = nrm[perm[j]];
+    double g = A[(long)perm[j] * s + row];  // sigma_j u_j[row]
+    p.US[e] = g;
+    p.Ut[(long)j * s + row] = sg > 0.0 ? g / (sg * sg) : 0.0;
   }
 }
 
