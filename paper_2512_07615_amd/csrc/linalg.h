@@ -248,23 +248,13 @@ __global__ void k_qr_export_r(const QrProb<T>* qp, const double* Racc, long sq) 
 // so it is orthonormal for every input, rank-deficient ones included.  The
 // R written out is R P^T, so that A = Q (R P^T) for the caller.  Working
 // copies live in LDS when they fit, else in the FP64 workspaces.
+// Body of k_householder with the working copies in LDS or global memory.
 template <typename T>
-__global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork w,
-                                                     int lds_elems, double* flops) {
-  extern __shared__ double sh[];
-  __shared__ double tau_s[1024];
-  __shared__ double cn[1024];
-  __shared__ int cperm[1024];
-  __shared__ double red[8];
-  __shared__ double bcast[2];
-  __shared__ int piv;
-  QrProb<T> q = qp[blockIdx.x];
-  if (!q.valid || q.m <= q.s) return;
+__device__ __forceinline__ void hh_body(const QrProb<T>& q, double* Wk, double* Qw, double* flops,
+                                        double* tau_s, double* cn, int* cperm, double* red,
+                                        double* bcast, int* piv) {
   const int m = q.m, s = q.s, p = q.p, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nw = blockDim.x >> 6;
-  const bool in_lds = (long)m * s + (long)m * p <= lds_elems;
-  double* Wk = in_lds ? sh : w.Q1 + blockIdx.x * w.mq;
-  double* Qw = in_lds ? sh + (long)m * s : w.Q2 + blockIdx.x * w.mq;
   for (long e = tid; e < (long)m * s; e += blockDim.x) {
     int i = (int)(e % m), c = (int)(e / m);
     Wk[e] = (double)q.A[(long)i * q.sAm + (long)c * q.sAk];
@@ -284,10 +274,10 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
       double bv = cn[j];
       for (int c = j + 1; c < s; ++c)
         if (cn[c] > bv) { bv = cn[c]; b = c; }
-      piv = b;
+      (*piv) = b;
     }
     __syncthreads();
-    const int pv = piv;
+    const int pv = (*piv);
     if (pv != j) {
       for (int i = tid; i < m; i += blockDim.x) {
         double t = Wk[(long)j * m + i];
@@ -384,6 +374,26 @@ __global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_householder(const QrProb<T>* qp, QrWork w,
+                                                     int lds_elems, double* flops) {
+  extern __shared__ double sh[];
+  __shared__ double tau_s[1024];
+  __shared__ double cn[1024];
+  __shared__ int cperm[1024];
+  __shared__ double red[8];
+  __shared__ double bcast[2];
+  __shared__ int piv;
+  QrProb<T> q = qp[blockIdx.x];
+  if (!q.valid || q.m <= q.s) return;
+  const int m = q.m, s = q.s, p = q.p;
+  if ((long)m * s + (long)m * p <= lds_elems)
+    hh_body(q, sh, sh + (long)m * s, flops, tau_s, cn, cperm, red, bcast, &piv);
+  else
+    hh_body(q, w.Q1 + blockIdx.x * w.mq, w.Q2 + blockIdx.x * w.mq, flops, tau_s, cn, cperm, red,
+            bcast, &piv);
+}
+
 // ---------------------------------------------------------------------------
 // Rank-revealing Cholesky-QR (FP32 precision policy).
 //
@@ -406,27 +416,18 @@ struct CholWork {
 };
 
 // Pivoted Cholesky of G (n x n, row-major, FP64) with threshold; writes
-// B = P[:, :rho] R11^{-1} (n x rho, ld rho) and Rp = R P^T (rho x n, ld n).
-__global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
-                                                  long sq, double* Bbase, double* Rbase,
-                                                  int* rank_out, double eps_rank, int lds_elems,
-                                                  int nprob, int want_b = 1) {
-  extern __shared__ double sh[];
-  __shared__ int perm[1024];
-  __shared__ double red[8];
-  __shared__ int ired[8];
-  __shared__ int rho_s;
-  __shared__ double dmax0;
-  __shared__ double dmax_piv;
-  const int pr = blockIdx.x;
-  if (pr >= nprob) return;
-  const int n = dims[pr * dim_stride];
-  if (n <= 0) return;
+// B = P[:, :rho] R11^{-1} (n x rho, ld rho, when want_b) and Rp = R P^T
+// (rho x n, ld n).  Right-looking, with the permutation kept as an index
+// array (no row/column swaps) and the scaling of each pivot row deferred to
+// the next step, so a step costs three barriers.  The stored matrix ends up
+// holding R in its "upper" part (position order) and serves as scratch for
+// the back substitution in its "lower" part.
+// Body of k_chol_piv for G in LDS or in global memory.
+__device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, double* Bbase,
+                                          double* Rbase, int* rank_out, double eps_rank,
+                                          int want_b, int* perm, double* red, int* ired,
+                                          int* rho_s, double* dmax0, double* dpiv, double* xd) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  double* Gg = Gbase + pr * sq;
-  double* G = ((long)n * n <= lds_elems) ? sh : Gg;
-  if (G != Gg)
-    for (long e = tid; e < (long)n * n; e += blockDim.x) G[e] = Gg[e];
   for (int i = tid; i < n; i += blockDim.x) perm[i] = i;
   __syncthreads();
   double dm = 0.0;
@@ -437,18 +438,21 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   if (tid == 0) {
     double m = 0.0;
     for (int i = 0; i < nw; ++i) m = fmax(m, red[i]);
-    dmax0 = m;
-    rho_s = n;
+    (*dmax0) = m;
+    (*rho_s) = n;
   }
   __syncthreads();
-  const double thr = eps_rank * dmax0;
-  int j = 0;
-  for (; j < n; ++j) {
-    // pivot: largest remaining diagonal
+  const double thr = eps_rank * (*dmax0);
+  int prev = -1;
+  double inv_prev = 0.0;
+  for (int j = 0; j < n; ++j) {
+    // deferred scaling of the previous pivot row; pivot search on the diagonal
+    if (prev >= 0)
+      for (int c = j + tid; c < n; c += blockDim.x) G[(long)prev * n + perm[c]] *= inv_prev;
     double best = -1.0;
     int bi = j;
     for (int i = j + tid; i < n; i += blockDim.x) {
-      double v = G[(long)i * n + i];
+      double v = G[(long)perm[i] * n + perm[i]];
       if (v > best) { best = v; bi = i; }
     }
     for (int o = 32; o > 0; o >>= 1) {
@@ -463,44 +467,37 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
       int ii = ired[0];
       for (int w = 1; w < nw; ++w)
         if (red[w] > b || (red[w] == b && ired[w] < ii)) { b = red[w]; ii = ired[w]; }
-      ired[0] = ii;
-      red[0] = b;
-      if (!(b > thr) || !(b > 0.0)) rho_s = j;
+      if (!(b > thr) || !(b > 0.0)) {
+        (*rho_s) = j;
+      } else {
+        int t = perm[j]; perm[j] = perm[ii]; perm[ii] = t;
+        (*dpiv) = b;
+      }
     }
     __syncthreads();
-    if (rho_s == j) break;
-    const int pv = ired[0];
-    // symmetric swap of rows/cols j and pv (full matrix kept symmetric)
-    if (pv != j) {
-      for (int c = tid; c < n; c += blockDim.x) {
-        double t = G[(long)j * n + c];
-        G[(long)j * n + c] = G[(long)pv * n + c];
-        G[(long)pv * n + c] = t;
+    if ((*rho_s) == j) break;
+    const int pj = perm[j];
+    const double d = (*dpiv), invd = 1.0 / d;
+    // trailing update: one wave per row, lanes along the row
+    for (int a = j + 1 + wv; a < n; a += nw) {
+      const int pa = perm[a];
+      const double f = G[(long)pj * n + pa] * invd;
+      double* ga = G + (long)pa * n;
+      const double* gj = G + (long)pj * n;
+      for (int b = j + 1 + lane; b < n; b += 64) {
+        const int pb = perm[b];
+        ga[pb] -= f * gj[pb];
       }
-      __syncthreads();
-      for (int r = tid; r < n; r += blockDim.x) {
-        double t = G[(long)r * n + j];
-        G[(long)r * n + j] = G[(long)r * n + pv];
-        G[(long)r * n + pv] = t;
-      }
-      if (tid == 0) { int t = perm[j]; perm[j] = perm[pv]; perm[pv] = t; }
-      __syncthreads();
     }
-    if (tid == 0) dmax_piv = sqrt(G[(long)j * n + j]);
-    __syncthreads();  // every thread reads the pivot before row j is overwritten
-    const double rjj = dmax_piv;
-    for (int c = j + tid; c < n; c += blockDim.x)
-      G[(long)j * n + c] = (c == j) ? rjj : G[(long)j * n + c] / rjj;
-    __syncthreads();
-    const int rem = n - j - 1;
-    const long tot = (long)rem * rem;
-    for (long e = tid; e < tot; e += blockDim.x) {
-      int a = j + 1 + (int)(e / rem), b = j + 1 + (int)(e % rem);
-      G[(long)a * n + b] -= G[(long)j * n + a] * G[(long)j * n + b];
-    }
+    if (tid == 0) G[(long)pj * n + pj] = sqrt(d);
+    prev = pj;
+    inv_prev = 1.0 / sqrt(d);
     __syncthreads();
   }
-  const int rho = rho_s;
+  // the last pivot row needs no further scaling: a break at step j = rho
+  // scaled it over positions >= rho, and a full run leaves no position
+  // beyond it
+  const int rho = (*rho_s);
   const int rr = rho > 0 ? rho : 1;
   double* B = Bbase + pr * sq;  // n x rr
   double* Rp = Rbase + pr * sq; // rr x n
@@ -508,25 +505,67 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   // Rp[r][perm[c]] = R[r][c] (upper trapezoid), zero rank -> zero row
   for (long e = tid; e < (long)rr * n; e += blockDim.x) {
     int r = (int)(e / n), c = (int)(e % n);
-    Rp[(long)r * n + perm[c]] = (rho > 0 && c >= r) ? G[(long)r * n + c] : 0.0;
+    Rp[(long)r * n + perm[c]] =
+        (rho > 0 && c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
   }
   if (!want_b) return;
-  // B = P[:, :rho] R11^{-1}: column c of R11^{-1} by back substitution
+  // B = P[:, :rho] R11^{-1}.  R11 is first brought into position order
+  // (staged through B), stored with leading dimension rho; column c of the
+  // inverse is then found by back substitution, its entries x_k (k < c)
+  // kept in the unused lower part (row c) and x_c in xd[c].
+  for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
+    const int r = (int)(e / rho), c = (int)(e % rho);
+    B[e] = (c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
+  }
+  __syncthreads();
+  for (long e = tid; e < (long)rho * rho; e += blockDim.x) G[e] = B[e];
+  __syncthreads();
   for (long e = tid; e < (long)n * rr; e += blockDim.x) B[e] = 0.0;
   __syncthreads();
-  if (rho == 0) {
-    return;
-  }
   for (int c = tid; c < rho; c += blockDim.x) {
-    // x solves R11 x = e_c; stored into B[perm[i]][c]
-    // use the strictly lower part of G as scratch for x (column c only touches row i < c)
-    double xc = 1.0 / G[(long)c * n + c];
-    B[(long)perm[c] * rr + c] = xc;
+    const double* Rc = G + (long)c * rho;  // row c: x_k at k < c
+    double* Xc = G + (long)c * rho;
+    const double xc = 1.0 / Rc[c];
+    xd[c] = xc;
     for (int i = c - 1; i >= 0; --i) {
-      double acc = 0.0;
-      for (int k = i + 1; k <= c; ++k) acc += G[(long)i * n + k] * B[(long)perm[k] * rr + c];
-      B[(long)perm[i] * rr + c] = -acc / G[(long)i * n + i];
+      const double* Ri = G + (long)i * rho;
+      double acc = Ri[c] * xc;
+      for (int k = i + 1; k < c; ++k) acc += Ri[k] * Xc[k];
+      Xc[i] = -acc / Ri[i];
     }
+  }
+  __syncthreads();
+  for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
+    const int c = (int)(e / rho), k = (int)(e % rho);
+    if (k < c) B[(long)perm[k] * rr + c] = G[(long)c * rho + k];
+    else if (k == c) B[(long)perm[c] * rr + c] = xd[c];
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
+                                                  long sq, double* Bbase, double* Rbase,
+                                                  int* rank_out, double eps_rank, int lds_elems,
+                                                  int nprob, int want_b = 1) {
+  extern __shared__ double sh[];
+  __shared__ int perm[1024];
+  __shared__ double red[8];
+  __shared__ int ired[8];
+  __shared__ int rho_s;
+  __shared__ double dmax0;
+  __shared__ double dpiv;
+  __shared__ double xd[1024];
+  const int pr = blockIdx.x;
+  if (pr >= nprob) return;
+  const int n = dims[pr * dim_stride];
+  if (n <= 0 || n > 1024) return;
+  double* Gg = Gbase + pr * sq;
+  if ((long)n * n <= lds_elems) {
+    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) sh[e] = Gg[e];
+    chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+              &dmax0, &dpiv, xd);
+  } else {
+    chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+              &dmax0, &dpiv, xd);
   }
 }
 
@@ -583,7 +622,8 @@ __device__ inline int jacobi_group_lanes(int n, int nwaves) {
 // Returns the number of sweeps performed (== max_sweeps when the sweep
 // limit stopped it).  `work` accumulates the flops of this thread's group
 // leader; `flag` is a shared int.
-__device__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n, int max_sweeps,
+__device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n,
+                                             int max_sweeps,
                              double tol, double small2, double& work, int* flag) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwaves = blockDim.x >> 6;
@@ -656,7 +696,8 @@ __device__ int jacobi_sweeps(double* A, int m, double* W, int nw, int n, int max
 // Column norms of A into nrm (a non-finite norm becomes -1 and sets
 // *nonfin), then perm = indices sorted by decreasing norm (ties by index),
 // a permutation whatever the values.
-__device__ void jacobi_sorted_norms(const double* A, int m, int n, double* nrm, int* perm,
+__device__ __forceinline__ void jacobi_sorted_norms(const double* A, int m, int n, double* nrm,
+                                                   int* perm,
                                     int* nonfin) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nwaves = blockDim.x >> 6;
   if (tid == 0) *nonfin = 0;
@@ -741,6 +782,50 @@ __global__ void k_eig_prep(F f, EigProb* ep, int nprob) {
   if (i < nprob) ep[i] = f.get(i);
 }
 
+// Body of k_jacobi_eig for A in LDS or in global memory (instantiated with
+// a pointer of known address space so that LDS is reached by ds_* ops).
+__device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sweeps, double* flops,
+                                         int* flag, int* nonfin, int* rsel, int* perm,
+                                         double* nrm, double* red) {
+  const int s = p.s, c = p.c, tid = threadIdx.x;
+  const long sc = (long)s * c;
+  double fro2 = 0.0;
+  for (long e = tid; e < sc; e += blockDim.x) fro2 += A[e] * A[e];
+  fro2 = block_sum(fro2, red);
+  const double eps = 2.220446049250313e-16;
+  double work = 0.0;
+  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, eps * sqrt((double)(s > 1 ? s : 1)),
+                               eps * eps * fro2, work, flag);
+  if (tid == 0 && p.fail) {
+    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
+    atomicAdd(p.fail + 2, sw);
+    atomicAdd(p.fail + 3, 1);
+  }
+  if (flops && work > 0.0) atomicAdd(flops, work);
+  jacobi_sorted_norms(A, s, c, nrm, perm, nonfin);
+  if (tid == 0 && *nonfin && p.fail) atomicAdd(p.fail + 1, 1);
+  if (tid == 0) {
+    double smax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
+    int nz = 0;
+    for (int j = 0; j < c; ++j)
+      if (nrm[perm[j]] * nrm[perm[j]] > 1e-14 * smax * smax) ++nz;
+    double tail = 0.0;
+    int r = rank_rule_dev(nrm, perm, c, true, p.delta2, p.chi, nz, &tail);
+    *rsel = r;
+    if (p.rank_out) *p.rank_out = r;
+    if (p.disc) *p.disc = tail;
+  }
+  __syncthreads();
+  const int r = *rsel;
+  for (long e = tid; e < (long)s * r; e += blockDim.x) {
+    int row = (int)(e / r), j = (int)(e % r);
+    double sg = nrm[perm[j]];
+    double g = A[(long)perm[j] * s + row];  // sigma_j u_j[row]
+    p.US[e] = g;
+    p.Ut[(long)j * s + row] = sg > 0.0 ? g / (sg * sg) : 0.0;
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_elems,
                                                      int max_sweeps, double* flops) {
   extern __shared__ double sh[];
@@ -756,45 +841,12 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
     return;
   }
   const long sc = (long)s * c;
-  const bool in_lds = sc <= lds_elems;
-  double* A = in_lds ? sh : p.A;
-  if (in_lds)
-    for (long e = tid; e < sc; e += blockDim.x) A[e] = p.A[e];
-  __syncthreads();
-  double fro2 = 0.0;
-  for (long e = tid; e < sc; e += blockDim.x) fro2 += A[e] * A[e];
-  fro2 = block_sum(fro2, red);
-  const double eps = 2.220446049250313e-16;
-  double work = 0.0;
-  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, eps * sqrt((double)(s > 1 ? s : 1)),
-                               eps * eps * fro2, work, &flag);
-  if (tid == 0 && p.fail) {
-    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
-    atomicAdd(p.fail + 2, sw);
-    atomicAdd(p.fail + 3, 1);
-  }
-  if (flops && work > 0.0) atomicAdd(flops, work);
-  jacobi_sorted_norms(A, s, c, nrm, perm, &nonfin);
-  if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
-  if (tid == 0) {
-    double smax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
-    int nz = 0;
-    for (int j = 0; j < c; ++j)
-      if (nrm[perm[j]] * nrm[perm[j]] > 1e-14 * smax * smax) ++nz;
-    double tail = 0.0;
-    int r = rank_rule_dev(nrm, perm, c, true, p.delta2, p.chi, nz, &tail);
-    rsel = r;
-    if (p.rank_out) *p.rank_out = r;
-    if (p.disc) *p.disc = tail;
-  }
-  __syncthreads();
-  const int r = rsel;
-  for (long e = tid; e < (long)s * r; e += blockDim.x) {
-    int row = (int)(e / r), j = (int)(e % r);
-    double sg = nrm[perm[j]];
-    double g = A[(long)perm[j] * s + row];  // sigma_j u_j[row]
-    p.US[e] = g;
-    p.Ut[(long)j * s + row] = sg > 0.0 ? g / (sg * sg) : 0.0;
+  if (sc <= lds_elems) {
+    for (long e = tid; e < sc; e += blockDim.x) sh[e] = p.A[e];
+    __syncthreads();
+    eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
+  } else {
+    eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
   }
 }
 
@@ -829,6 +881,51 @@ __global__ void k_svd_prep(F f, SvdProb* sp, int nprob) {
   if (i < nprob) sp[i] = f.get(i);
 }
 
+// Body of k_jacobi_svd for A and W each in LDS or global memory.
+__device__ __forceinline__ void svd_body(const SvdProb& p, double* A, double* W, int max_sweeps,
+                                         double* flops, int* flag, int* nonfin, int* rsel,
+                                         int* perm, double* nrm, double* red) {
+  const int m = p.rows, n = p.cols, tid = threadIdx.x;
+  const long mn = (long)m * n, nn = (long)n * n;
+  for (long e = tid; e < nn; e += blockDim.x) W[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
+  __syncthreads();
+  double fro2 = 0.0;
+  for (long e = tid; e < mn; e += blockDim.x) fro2 += A[e] * A[e];
+  fro2 = block_sum(fro2, red);
+  const double eps = 2.220446049250313e-16;
+  double work = 0.0;
+  const int sw = jacobi_sweeps(A, m, W, n, n, max_sweeps, eps * sqrt((double)(m > 1 ? m : 1)),
+                               eps * eps * fro2, work, flag);
+  if (tid == 0 && p.fail) {
+    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
+    atomicAdd(p.fail + 2, sw);
+    atomicAdd(p.fail + 3, 1);
+  }
+  if (flops && work > 0.0) atomicAdd(flops, work);
+  jacobi_sorted_norms(A, m, n, nrm, perm, nonfin);
+  if (tid == 0 && *nonfin && p.fail) atomicAdd(p.fail + 1, 1);
+  if (tid == 0) {
+    double tail = 0.0;
+    int r = rank_rule_dev(nrm, perm, n, true, p.delta2, p.chi, n, &tail);
+    *rsel = r;
+    if (p.rank_out) *p.rank_out = r;
+    if (p.disc) *p.disc = tail;
+  }
+  __syncthreads();
+  const int r = *rsel;
+  if (p.sv)
+    for (int j = tid; j < n; j += blockDim.x) p.sv[j] = nrm[perm[j]];
+  // pack kept columns: US[row][j] = A[perm[j]][row]; Wk[row][j] = W[perm[j]][row]
+  for (long e = tid; e < (long)m * r; e += blockDim.x) {
+    int row = (int)(e / r), j = (int)(e % r);
+    p.US[e] = A[(long)perm[j] * m + row];
+  }
+  for (long e = tid; e < (long)n * r; e += blockDim.x) {
+    int row = (int)(e / r), j = (int)(e % r);
+    p.Wk[e] = W[(long)perm[j] * n + row];
+  }
+}
+
 __global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_elems,
                                                      int max_sweeps, double* flops) {
   extern __shared__ double sh[];
@@ -844,46 +941,15 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_
     return;
   }
   const long mn = (long)m * n, nn = (long)n * n;
-  const bool a_lds = mn <= lds_elems;
-  const bool w_lds = a_lds && mn + nn <= lds_elems;
-  double* A = a_lds ? sh : p.Lw;
-  double* W = w_lds ? sh + mn : p.W;
-  for (long e = tid; e < mn; e += blockDim.x) A[e] = p.L[e];
-  for (long e = tid; e < nn; e += blockDim.x) W[e] = ((e / n) == (e % n)) ? 1.0 : 0.0;
-  double fro2 = 0.0;
-  for (long e = tid; e < mn; e += blockDim.x) fro2 += p.L[e] * p.L[e];
-  fro2 = block_sum(fro2, red);
-  const double eps = 2.220446049250313e-16;
-  double work = 0.0;
-  const int sw = jacobi_sweeps(A, m, W, n, n, max_sweeps, eps * sqrt((double)(m > 1 ? m : 1)),
-                               eps * eps * fro2, work, &flag);
-  if (tid == 0 && p.fail) {
-    if (sw >= max_sweeps) atomicAdd(p.fail, 1);
-    atomicAdd(p.fail + 2, sw);
-    atomicAdd(p.fail + 3, 1);
-  }
-  if (flops && work > 0.0) atomicAdd(flops, work);
-  jacobi_sorted_norms(A, m, n, nrm, perm, &nonfin);
-  if (tid == 0 && nonfin && p.fail) atomicAdd(p.fail + 1, 1);
-  if (tid == 0) {
-    double tail = 0.0;
-    int r = rank_rule_dev(nrm, perm, n, true, p.delta2, p.chi, n, &tail);
-    rsel = r;
-    if (p.rank_out) *p.rank_out = r;
-    if (p.disc) *p.disc = tail;
-  }
-  __syncthreads();
-  const int r = rsel;
-  if (p.sv)
-    for (int j = tid; j < n; j += blockDim.x) p.sv[j] = nrm[perm[j]];
-  // pack kept columns: US[row][j] = A[perm[j]][row]; Wk[row][j] = W[perm[j]][row]
-  for (long e = tid; e < (long)m * r; e += blockDim.x) {
-    int row = (int)(e / r), j = (int)(e % r);
-    p.US[e] = A[(long)perm[j] * m + row];
-  }
-  for (long e = tid; e < (long)n * r; e += blockDim.x) {
-    int row = (int)(e / r), j = (int)(e % r);
-    p.Wk[e] = W[(long)perm[j] * n + row];
+  if (mn + nn <= lds_elems) {
+    for (long e = tid; e < mn; e += blockDim.x) sh[e] = p.L[e];
+    svd_body(p, sh, sh + mn, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
+  } else if (mn <= lds_elems) {
+    for (long e = tid; e < mn; e += blockDim.x) sh[e] = p.L[e];
+    svd_body(p, sh, p.W, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
+  } else {
+    for (long e = tid; e < mn; e += blockDim.x) p.Lw[e] = p.L[e];
+    svd_body(p, p.Lw, p.W, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
   }
 }
 
