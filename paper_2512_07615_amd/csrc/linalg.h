@@ -422,11 +422,104 @@ struct CholWork {
 // the next step, so a step costs three barriers.  The stored matrix ends up
 // holding R in its "upper" part (position order) and serves as scratch for
 // the back substitution in its "lower" part.
+constexpr int CPB = 16;     // panel width of the blocked pivoted Cholesky
+constexpr int CPB_MAXN = 128;  // largest order factored by the blocked variant
+
+// Blocked pivoted Cholesky for n <= CPB_MAXN with G in LDS.  Wave 0 factors
+// a panel of CPB columns (left-looking inside the panel, pivots chosen on
+// the running Schur-complement diagonal dg); then every wave applies the
+// rank-CPB update to the trailing matrix.  Row perm[j] of G receives row j
+// of R (columns perm[c], c >= j); *rho_s receives the numerical rank.
+__device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* perm, double* dg,
+                                             double* Lp, int* rho_s, int* kdone) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  for (int i = tid; i < n; i += blockDim.x) dg[i] = G[(long)i * n + i];
+  __syncthreads();
+  for (int j0 = 0; j0 < n; j0 += CPB) {
+    const int bw = n - j0 < CPB ? n - j0 : CPB;
+    if (wv == 0) {
+      int k = 0;
+      for (; k < bw; ++k) {
+        const int j = j0 + k;
+        double best = -1.0;
+        int bi = j;
+        for (int i = j + lane; i < n; i += 64) {
+          const double v = dg[i];
+          if (v > best) { best = v; bi = i; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+          const double ob = __shfl_xor(best, o, 64);
+          const int oi = __shfl_xor(bi, o, 64);
+          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+        }
+        if (!(best > thr) || !(best > 0.0)) break;  // the same decision in every lane
+        if (bi != j) {
+          if (lane < k) {
+            const double t = Lp[j * CPB + lane];
+            Lp[j * CPB + lane] = Lp[bi * CPB + lane];
+            Lp[bi * CPB + lane] = t;
+          }
+          if (lane == 0) {
+            const int t = perm[j]; perm[j] = perm[bi]; perm[bi] = t;
+            const double u = dg[j]; dg[j] = dg[bi]; dg[bi] = u;
+          }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int pj = perm[j];
+        const double r = sqrt(best), invr = 1.0 / r;
+        for (int i = j + 1 + lane; i < n; i += 64) {
+          double acc = G[(long)perm[i] * n + pj];
+          for (int q = 0; q < k; ++q) acc -= Lp[i * CPB + q] * Lp[j * CPB + q];
+          const double l = acc * invr;
+          Lp[i * CPB + k] = l;
+          dg[i] -= l * l;
+        }
+        if (lane == 0) Lp[j * CPB + k] = r;
+        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      if (lane == 0) {
+        *kdone = k;
+        if (k < bw) *rho_s = j0 + k;
+      }
+    }
+    __syncthreads();
+    const int kd = *kdone;
+    // rows of R for the finished panel columns
+    for (int k = 0; k < kd; ++k) {
+      const int j = j0 + k, pj = perm[j];
+      for (int c = j + tid; c < n; c += blockDim.x) G[(long)pj * n + perm[c]] = Lp[c * CPB + k];
+    }
+    if (kd < bw) {
+      __syncthreads();
+      break;
+    }
+    // trailing update G[a][b] -= sum_q L[a][q] L[b][q] over positions >= j0 + bw
+    const int t0 = j0 + bw;
+    for (int a = t0 + wv; a < n; a += nw) {
+      const int pa = perm[a];
+      double la[CPB];
+#pragma unroll
+      for (int q = 0; q < CPB; ++q) la[q] = q < bw ? Lp[a * CPB + q] : 0.0;
+      double* ga = G + (long)pa * n;
+      for (int b = t0 + lane; b < n; b += 64) {
+        double acc = 0.0;
+#pragma unroll
+        for (int q = 0; q < CPB; ++q) acc += la[q] * Lp[b * CPB + q];
+        ga[perm[b]] -= acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // Body of k_chol_piv for G in LDS or in global memory.
 __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, double* Bbase,
                                           double* Rbase, int* rank_out, double eps_rank,
                                           int want_b, int* perm, double* red, int* ired,
-                                          int* rho_s, double* dmax0, double* dpiv, double* xd) {
+                                          int* rho_s, double* dmax0, double* dpiv, double* xd,
+                                          double* Lp, int* kdone) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < n; i += blockDim.x) perm[i] = i;
   __syncthreads();
@@ -445,7 +538,8 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
   const double thr = eps_rank * (*dmax0);
   int prev = -1;
   double inv_prev = 0.0;
-  for (int j = 0; j < n; ++j) {
+  if (Lp) chol_blocked(G, n, thr, perm, xd, Lp, rho_s, kdone);
+  for (int j = 0; j < n && !Lp; ++j) {
     // deferred scaling of the previous pivot row; pivot search on the diagonal
     if (prev >= 0)
       for (int c = j + tid; c < n; c += blockDim.x) G[(long)prev * n + perm[c]] *= inv_prev;
@@ -554,6 +648,8 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   __shared__ double dmax0;
   __shared__ double dpiv;
   __shared__ double xd[1024];
+  __shared__ double Lp[CPB_MAXN * CPB];
+  __shared__ int kdone;
   const int pr = blockIdx.x;
   if (pr >= nprob) return;
   const int n = dims[pr * dim_stride];
@@ -562,10 +658,10 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   if ((long)n * n <= lds_elems) {
     for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) sh[e] = Gg[e];
     chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
-              &dmax0, &dpiv, xd);
+              &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone);
   } else {
     chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
-              &dmax0, &dpiv, xd);
+              &dmax0, &dpiv, xd, nullptr, &kdone);
   }
 }
 
