@@ -98,8 +98,8 @@ def main():
     ap.add_argument("--workload", default="porous64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
-    ap.add_argument("--roofline-kernel", default="jacobi",
-                    choices=["jacobi", "householder", "prodgemm"])
+    ap.add_argument("--roofline-kernel", default="cholesky",
+                    choices=["jacobi", "householder", "prodgemm", "cholesky"])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (N=1); "
@@ -115,7 +115,7 @@ def main():
         sim.step(1)
     torch.cuda.synchronize()
     kind = {"jacobi": L.K_JACOBI, "householder": L.K_HOUSEHOLDER,
-            "prodgemm": L.K_PRODGEMM}[args.roofline_kernel]
+            "prodgemm": L.K_PRODGEMM, "cholesky": L.K_CHOLESKY}[args.roofline_kernel]
     sim.kernel_timing(kind)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)

@@ -174,6 +174,7 @@ int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* b
 #define MPS_LBM_K_JACOBI 1      /* one-sided Jacobi SVD of the bond matrices   */
 #define MPS_LBM_K_HOUSEHOLDER 2 /* Householder QR of core unfoldings          */
 #define MPS_LBM_K_PRODGEMM 3    /* contraction GEMMs of the variational product */
+#define MPS_LBM_K_CHOLESKY 4    /* pivoted Cholesky of the FP32-policy Gram matrices */
 
 typedef struct {
   long long launches; /* launches of the class since timing was enabled       */

@@ -1052,15 +1052,20 @@ class Engine {
     CholWork w = cw;
     hipLaunchKernelGGL(k_cq_dims<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp, cq_n, nprob);
     launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st);
+    tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)cq_n, 1, w.G,
-                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob);
+                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4));
+    tend(4);
     hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 0);
     launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st);
     hipLaunchKernelGGL(k_cq_dims2<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp,
                        (const int*)w.rank, cq_n + MAXB, nprob);
+    tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)(cq_n + MAXB), 1,
-                       w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob);
+                       w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob, 1,
+                       kf(4));
+    tend(4);
     hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 1);
     launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqR<T>{qp, w}, nprob, scap, scap, 1, st);
@@ -1103,9 +1108,11 @@ class Engine {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
       launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
       hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
+      tbegin(4);
       hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
                          (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
-                         lds_elems, cnt, 0);
+                         lds_elems, cnt, 0, kf(4));
+      tend(4);
       hipLaunchKernelGGL(k_eig_prep<FnEigTrunc<T>>, dim3(1), dim3(64), 0, st,
                          FnEigTrunc<T>{L, k, cw.R1, cw.sq, (const int*)cw.rank, svdUS, svdWk,
                                        sus, rdelta, rdisc, chi_cap, istats},

@@ -639,7 +639,8 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
 __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
                                                   long sq, double* Bbase, double* Rbase,
                                                   int* rank_out, double eps_rank, int lds_elems,
-                                                  int nprob, int want_b = 1) {
+                                                  int nprob, int want_b = 1,
+                                                  double* flops = nullptr) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[8];
@@ -662,6 +663,15 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   } else {
     chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, nullptr, &kdone);
+  }
+  if (flops && threadIdx.x == 0) {
+    // factorisation: per pivot j a column scaling and a symmetric rank-1
+    // update of the trailing (n-j-1)^2 block; inverse of R11: rho^3 / 3
+    const int rho = rho_s;
+    double f = 0.0;
+    for (int j = 0; j < rho; ++j) f += 2.0 * (n - j - 1) * (n - j - 1) + (n - j - 1);
+    if (want_b) f += (double)rho * rho * rho / 3.0;
+    atomicAdd(flops, f);
   }
 }
 

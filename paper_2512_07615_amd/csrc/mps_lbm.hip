@@ -670,7 +670,7 @@ int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out) {
 
 int mps_lbm_kernel_timing(mps_lbm_t* h, int kind) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
-  if (kind < MPS_LBM_K_NONE || kind > MPS_LBM_K_PRODGEMM) return fail(MPS_LBM_EINVAL, "bad kind");
+  if (kind < MPS_LBM_K_NONE || kind > MPS_LBM_K_CHOLESKY) return fail(MPS_LBM_EINVAL, "bad kind");
   try {
     h->sim->set_timing(kind);
     return MPS_LBM_OK;

@@ -25,7 +25,7 @@ INV_TAYLOR2, INV_NEWTON = 0, 1
 BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
 POPS, RHO, J, VEL = 0, 1, 2, 3
 
-K_NONE, K_JACOBI, K_HOUSEHOLDER, K_PRODGEMM = 0, 1, 2, 3
+K_NONE, K_JACOBI, K_HOUSEHOLDER, K_PRODGEMM, K_CHOLESKY = 0, 1, 2, 3, 4
 MPS_MASK = 19
 
 EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
