@@ -73,6 +73,37 @@ def cpu_baseline(case, roundings_per_step, products_per_step, budget_s=20.0):
                       f"products per step (initialisation excluded)"}
 
 
+def batched_rate(case, count, stream, steps):
+    """Domain-steps/s of `count` domains of the workload (the same geometry
+    generator with different seeds) held by one handle and advanced
+    together; one untimed step first."""
+    import dataclasses
+    import torch
+    import workloads as WL
+    from paper_2512_07615_amd import mps_lbm as L
+    cases = [case]
+    for k in range(1, count):
+        if case.name.startswith("porous"):
+            cases.append(WL.case_porous(n=case.n, chi=case.chi, tau=case.tau, tol=case.tol,
+                                        precision=case.precision, seed=2514 + 100 * k))
+        else:
+            cases.append(dataclasses.replace(case))
+    b = L.BatchSimulation(cases, hip_stream=stream.cuda_stream)
+    b.step(1)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    b.close()
+    return {"domains": count, "steps": steps, "ms_per_step": ms,
+            "domain_steps_per_s": count * 1000.0 / ms,
+            "equiv_mlups": count * case.N ** 3 * 1000.0 / ms / 1e6}
+
+
 def roofline(kind, ks, prec):
     """Roofline entry of the timed kernel class from its event-timed launches
     and device-counted algorithmic flops."""
@@ -98,6 +129,12 @@ def main():
     ap.add_argument("--workload", default="porous64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=3)
+    ap.add_argument("--batch", type=int, default=8,
+                    help="also time this many domains of the workload advanced together "
+                         "(0 = skip)")
+    ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="issue the step kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--roofline-kernel", default="cholesky",
                     choices=["jacobi", "householder", "prodgemm", "cholesky"])
     args = ap.parse_args()
@@ -145,6 +182,19 @@ def main():
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)
     out["roofline"]["share_of_step"] = ks.total_ms / (ms * args.steps)
+    if not args.no_graph:
+        # the same step recorded once as a HIP graph and replayed (the timed
+        # region above issues it kernel by kernel, with per-launch events)
+        sim.kernel_timing(L.K_NONE)
+        sim.capture()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            sim.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1) / args.steps
+        out["config"]["hip_graph_steps_per_s"] = 1000.0 / gms
     sim.close()
     if args.fp64_steps > 0 and case.precision != "fp64":
         sim64 = L.Simulation(case, precision="fp64", hip_stream=stream.cuda_stream)
@@ -159,6 +209,8 @@ def main():
         out["config"]["fp64_steps_per_s"] = 1000.0 / ms64
         out["config"]["speedup_vs_fp64_path"] = ms64 / ms
         sim64.close()
+    if args.batch > 0:
+        out["config"]["batched"] = batched_rate(case, args.batch, stream, args.batch_steps)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, obs.roundings, obs.products)
     print(json.dumps(out), flush=True)

@@ -151,6 +151,44 @@ int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len);
 /* Scalar observables (synchronises the stream). */
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
 
+/*
+ * Batched domains: count independent simulations (each the problem of
+ * Section 3.2 with its own geometry, tau, g, faces and initial fields) held
+ * by one handle and advanced together by mps_lbm_step, every operation of
+ * the step being issued once for the MPS of all domains.  The domains must
+ * share n, chi_max, precision, tol, sweeps and the inverse-density mode;
+ * rho[d], u[d] and solid[d] are as in mps_lbm_init_from_field (solid, or
+ * an entry of it, may be NULL for no obstacles).  The handle's plain entry
+ * points address domain 0; the per-domain forms below address any.
+ * Errors: EINVAL (count < 1, an invalid configuration, configurations that
+ * differ in a shared field, NULL fields), ENOMEM, EHIP.
+ */
+int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* const* rho,
+                       const double* const* u, const uint8_t* const* solid, void* hip_stream,
+                       mps_lbm_t** out);
+
+/*
+ * Record the step as a HIP graph: one eager step is taken (it brings the
+ * handle's MPS pool to its peak size and counts as a step), then the next
+ * step is captured together with copies that return the new populations to
+ * the slots the step reads, and every later mps_lbm_step replays the graph
+ * (one launch per step, identical arithmetic).  The handle's stream must not
+ * be the default stream.  Kernel timing is not recorded inside the graph.
+ * Errors: EINVAL (NULL handle, default stream), EHIP.
+ */
+int mps_lbm_capture_step(mps_lbm_t* h);
+
+/* Number of domains of the handle (1 after mps_lbm_init_from_field), or
+   EINVAL for a NULL handle. */
+int mps_lbm_domains(const mps_lbm_t* h);
+
+/* mps_lbm_to_dense and mps_lbm_observables for domain 0 <= domain <
+   mps_lbm_domains(h); the roundings and products of the observables count
+   all domains of the handle.  Errors: as the plain forms, and EINVAL for a
+   domain out of range. */
+int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, size_t out_len);
+int mps_lbm_observables_domain(mps_lbm_t* h, int domain, mps_lbm_obs* out);
+
 /* mps_lbm_get_mps: index of the obstacle-mask MPS (0..18 are populations) */
 #define MPS_LBM_MPS_MASK 19
 

@@ -47,14 +47,17 @@ struct MpsList {
 };
 
 // Coefficient a * rho0^p where rho0 is a device scalar (p in {-2..1}).
+// Coefficient a * rho_0^p of a term (p in {1, 0, -1, -2}); d selects the
+// domain whose rho_0 applies when several domains are advanced together.
 struct Coef {
   double a;
   int p;
+  int d;
 };
 
 __host__ __device__ inline double coef_value(Coef c, const double* rho0) {
   if (c.p == 0) return c.a;
-  double r = rho0[0];
+  double r = rho0[c.d];
   switch (c.p) {
     case 1: return c.a * r;
     case -1: return c.a / r;

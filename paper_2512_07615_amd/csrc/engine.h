@@ -474,6 +474,18 @@ __global__ void k_moments_dense(const T* f, double* out, long N3, int what, cons
   }
 }
 
+// fill kernel (used instead of memset nodes in code that may be captured)
+__global__ void k_fill_f64(double* p, double v, long cnt) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < cnt; e += (long)gridDim.x * blockDim.x)
+    p[e] = v;
+}
+
+template <typename T>
+__global__ void k_copy_ranks(MpsDev<T>* dst, const MpsDev<T>* src) {
+  const int k = threadIdx.x;
+  if (k <= src->n) dst->r[k] = src->r[k];
+}
+
 __global__ void k_div_scalar(const double* a, double b, double* out) {
   if (threadIdx.x == 0) out[0] = a[0] / b;
 }
@@ -1005,13 +1017,22 @@ class Engine {
   }
 
   int acquire() {
-    if (freelist.empty()) throw Error(-2, "MPS pool exhausted");
+    if (freelist.empty()) {
+      // grow the pool (memory stays bounded by the peak number of live MPS)
+      pool.push_back(make_mps(capb));
+      return (int)pool.size() - 1;
+    }
     int i = freelist.back();
     freelist.pop_back();
     return i;
   }
+  // slots that release() must not recycle (the populations a captured step
+  // reads stay untouched until the step has finished with them)
+  std::vector<char> pinned;
   void release(int i) {
-    if (i >= 0) freelist.push_back(i);
+    if (i < 0) return;
+    if (i < (int)pinned.size() && pinned[i]) return;
+    freelist.push_back(i);
   }
   MpsDev<T>* D(int i) const { return pool[i].dev; }
   // grid-stride chunks for kernels walking one core of capacity size
@@ -1103,7 +1124,7 @@ class Engine {
                          k + 1);
     }
     hipLaunchKernelGGL(k_round_threshold<T>, dim3(cnt), blk, 0, st, L, tol_r, rdelta, rnorm, cnt);
-    HIP_OK(hipMemsetAsync(rdisc, 0, 8 * MAXB * (MAXN + 1), st));
+    hipLaunchKernelGGL(k_fill_f64, dim3(3), dim3(256), 0, st, rdisc, 0.0, (long)MAXB * (MAXN + 1));
     for (int k = n - 1; k >= 1 && fast; --k) {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
       launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
@@ -1395,7 +1416,7 @@ class Engine {
   // Streaming f_new(x) = f(x - c) one axis at a time (x, y, z order), each
   // shift followed by rounding.  Returns fresh objects.
   std::vector<int> stream(const std::vector<int>& src, const std::vector<const int*>& cvec,
-                          const int* axis_open) {
+                          const std::vector<const int*>& axis_open) {
     std::vector<int> cur = src;
     std::vector<bool> owned(src.size(), false);
     for (int ax = 0; ax < 3; ++ax) {
@@ -1406,7 +1427,7 @@ class Engine {
         s.push_back(cur[i]);
         a.push_back(ax);
         d.push_back(cvec[i][ax]);
-        cy.push_back(axis_open[ax] ? 0 : 1);
+        cy.push_back(axis_open[i][ax] ? 0 : 1);
         who.push_back((int)i);
       }
       if (dst.empty()) continue;

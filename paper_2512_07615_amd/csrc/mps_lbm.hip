@@ -16,6 +16,7 @@
 // rounded after each addition; the CPU oracle follows the same schedule.
 #include "../../include/mps_lbm.h"
 
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -37,76 +38,103 @@ namespace {
 
 struct Sim {
   virtual ~Sim() {}
+  virtual int domains() const = 0;
   virtual void step(int nsteps) = 0;
-  virtual void to_dense(int what, double* out) = 0;
-  virtual void observables(mps_lbm_obs* o) = 0;
+  virtual void to_dense(int d, int what, double* out) = 0;
+  virtual void observables(int d, mps_lbm_obs* o) = 0;
   virtual void set_timing(int kind) = 0;
   virtual void kstats(mps_lbm_kstats* o) = 0;
-  virtual int get_mps(int which, double* out, size_t out_len, int* bonds) = 0;
+  virtual int get_mps(int d, int which, double* out, size_t out_len, int* bonds) = 0;
+  virtual long cells() const = 0;
+  virtual void capture() = 0;
 };
 
+__global__ void k_div_vec(const double* num, const double* den, double* out, int cnt) {
+  int i = threadIdx.x;
+  if (i < cnt) out[i] = num[i] / den[i];
+}
+
+// State of one domain: its configuration and the pool indices of its MPS.
+struct Domain {
+  mps_lbm_config cfg;
+  int f[19];
+  int mask = -1, fluid = -1;
+  int fplane[6];
+  double n_fluid = 0.0;
+  double mask_err = 0.0;
+};
+
+// One engine advancing D domains of equal n, chi and precision together:
+// every operation of the step is issued once for the MPS of all domains, so
+// launches carry D times as many problems (Sections 3.2 and 2).
 template <typename T>
 struct SimT : Sim {
   typedef typename Engine<T>::Term Term;
-  mps_lbm_config cfg;
   Engine<T> E;
   hipStream_t st;
-  int n, N;
+  int n, N, D;
   long N3;
-  int f[19];
-  int one = -1, mask = -1, fluid = -1;
-  int fplane[6];
-  double* rho0 = nullptr;   // device scalar
+  std::vector<Domain> dom;
+  int one = -1;
+  double* rho0 = nullptr;   // device [D]
+  double* nfl = nullptr;    // device [D]: fluid cell counts
   double* scratch = nullptr;
-  double n_fluid = 0.0;
-  double mask_err = 0.0;
+  int* cvec_dev = nullptr;
+  double* w_dev = nullptr;
   long long steps = 0;
-  int chi_mask = 1;
+  long long last_roundings = 0, last_products = 0;
 
-  SimT(const mps_lbm_config& c, hipStream_t s) : cfg(c), st(s) {
+  SimT(const mps_lbm_config* cfgs, int count, hipStream_t s) : st(s) {
+    const mps_lbm_config& c = cfgs[0];
+    D = count;
     n = c.n;
     N = 1 << n;
     N3 = 1L << (3 * n);
-    for (int i = 0; i < 6; ++i) fplane[i] = -1;
-    E.sweeps = c.sweeps;
-    E.setup(n, c.chi_max, c.tol, s, 256, 19);
-    rho0 = (double*)E.dalloc(8 * 64);
-    scratch = (double*)E.dalloc(8 * 64);
-    chi_mask = c.chi_mask_max > 0 ? std::min(c.chi_mask_max, c.chi_max) : c.chi_max;
-  }
-
-  // --- dense -> MPS: TT-SVD (Section 2.1, svd-comp equation) of cnt
-  // scale-ordered fields W, truncated at (chi_r, tol_r).  W is overwritten.
-  int dense_chunks(long count) const {
-    return (int)std::max<long>(1, std::min<long>(2048, (count + 255) / 256));
-  }
-
-  void dense_to_mps(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r) {
-    E.tt_svd(W, cnt, objs, chi_r, tol_r);
-  }
-
-  void free_last(int k) {
-    for (int i = 0; i < k && !E.allocs.empty(); ++i) {
-      (void)hipFree(E.allocs.back());
-      E.allocs.pop_back();
+    dom.resize(D);
+    for (int d = 0; d < D; ++d) {
+      dom[d].cfg = cfgs[d];
+      for (int i = 0; i < 6; ++i) dom[d].fplane[i] = -1;
     }
-  }
-
-  void init(const double* rho, const double* u, const double* fin, const uint8_t* solid) {
+    E.sweeps = c.sweeps;
+    E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
+    rho0 = (double*)E.dalloc(8 * (D + 8));
+    nfl = (double*)E.dalloc(8 * (D + 8));
+    scratch = (double*)E.dalloc(8 * (19 * D + 64));
     int cvec[57];
     double w[19];
     for (int i = 0; i < 19; ++i) {
       for (int a = 0; a < 3; ++a) cvec[3 * i + a] = kC[i][a];
       w[i] = kW(i);
     }
-    int* dc = (int*)E.dalloc(sizeof(cvec));
-    double* dw = (double*)E.dalloc(sizeof(w));
-    HIP_OK(hipMemcpy(dc, cvec, sizeof(cvec), hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(dw, w, sizeof(w), hipMemcpyHostToDevice));
-    cvec_dev = dc;
+    cvec_dev = (int*)E.dalloc(sizeof(cvec));
+    w_dev = (double*)E.dalloc(sizeof(w));
+    HIP_OK(hipMemcpy(cvec_dev, cvec, sizeof(cvec), hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(w_dev, w, sizeof(w), hipMemcpyHostToDevice));
     one = E.acquire();
     E.set_ones(one);
-    // obstacle mask
+  }
+
+  int domains() const override { return D; }
+  long cells() const override { return N3; }
+
+  int dense_chunks(long count) const {
+    return (int)std::max<long>(1, std::min<long>(2048, (count + 255) / 256));
+  }
+
+  // dense -> MPS: TT-SVD (Section 2.1, svd-comp equation) of cnt
+  // scale-ordered fields W, truncated at (chi_r, tol_r).  W is overwritten.
+  void dense_to_mps(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r) {
+    E.tt_svd(W, cnt, objs, chi_r, tol_r);
+  }
+
+  // Initial state of domain d from dense fields (all synchronous).
+  void init_domain(int d, const double* rho, const double* u, const double* fin,
+                   const uint8_t* solid) {
+    Domain& dm = dom[d];
+    const mps_lbm_config& cfg = dm.cfg;
+    const int chi_mask =
+        cfg.chi_mask_max > 0 ? std::min(cfg.chi_mask_max, cfg.chi_max) : cfg.chi_max;
+    size_t mark = E.allocs.size();
     double* dd = (double*)E.dalloc(8 * N3 * 19);  // dense staging (FP64)
     T* W = (T*)E.dalloc(sizeof(T) * N3 * 19);
     uint8_t* dsolid = nullptr;
@@ -118,43 +146,43 @@ struct SimT : Sim {
       HIP_OK(hipMemcpy(dd, hs.data(), 8 * N3, hipMemcpyHostToDevice));
       hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(N3)), dim3(256), 0, st,
                          (const double*)dd, W, n, 1, 1);
-      mask = E.acquire();
+      dm.mask = E.acquire();
       T* Wkeep = (T*)E.dalloc(sizeof(T) * N3);
-      hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W, Wkeep,
-                         N3);
-      dense_to_mps(W, 1, {mask}, chi_mask, cfg.tol_mask);
+      hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W,
+                         Wkeep, N3);
+      dense_to_mps(W, 1, {dm.mask}, chi_mask, cfg.tol_mask);
       // decomposition error of the mask
       T* back = (T*)E.dalloc(sizeof(T) * N3);
       T* work = (T*)E.dalloc(sizeof(T) * N3);
-      E.to_dense({mask}, back, work);
+      E.to_dense({dm.mask}, back, work);
       HIP_OK(hipMemsetAsync(scratch, 0, 16, st));
-      hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st, (const T*)back,
-                         (const T*)Wkeep, N3, scratch);
+      hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st,
+                         (const T*)back, (const T*)Wkeep, N3, scratch);
       double hnorm[2];
       HIP_OK(hipMemcpyAsync(hnorm, scratch, 16, hipMemcpyDeviceToHost, st));
-      E.inner_ones({mask}, scratch + 2);
+      E.inner_ones({dm.mask}, scratch + 2);
       double ones_m = 0.0;
       HIP_OK(hipMemcpyAsync(&ones_m, scratch + 2, 8, hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
-      mask_err = hnorm[1] > 0 ? std::sqrt(hnorm[0] / hnorm[1]) : 0.0;
-      n_fluid = (double)N3 - ones_m;
-      free_last(3);
+      dm.mask_err = hnorm[1] > 0 ? std::sqrt(hnorm[0] / hnorm[1]) : 0.0;
+      dm.n_fluid = (double)N3 - ones_m;
       // fluid = round(1 - m)
-      fluid = E.acquire();
-      E.add({fluid}, {one}, {mask}, {Coef{1.0, 0}, Coef{-1.0, 0}}, nullptr);
-      E.round({fluid}, cfg.chi_max, cfg.tol_mask);
+      dm.fluid = E.acquire();
+      E.add({dm.fluid}, {one}, {dm.mask}, {Coef{1.0, 0, d}, Coef{-1.0, 0, d}}, nullptr);
+      E.round({dm.fluid}, cfg.chi_max, cfg.tol_mask);
     } else {
-      n_fluid = (double)N3;
-      fluid = one;
+      dm.n_fluid = (double)N3;
+      dm.fluid = one;
     }
+    HIP_OK(hipMemcpyAsync(nfl + d, &dm.n_fluid, 8, hipMemcpyHostToDevice, st));
     // open-face planes of the fluid indicator
     for (int ax = 0; ax < 3; ++ax) {
       if (!cfg.axis_open[ax]) continue;
       for (int side = 0; side < 2; ++side) {
         int face = 2 * ax + side;
         if (cfg.face_bc[face] == MPS_LBM_BC_NONE) continue;
-        std::vector<int> o = E.slice({fluid}, {ax}, {side == 0 ? 0 : N - 1});
-        fplane[face] = o[0];
+        std::vector<int> o = E.slice({dm.fluid}, {ax}, {side == 0 ? 0 : N - 1});
+        dm.fplane[face] = o[0];
       }
     }
     // initial populations
@@ -165,81 +193,105 @@ struct SimT : Sim {
       double* du = (double*)E.dalloc(8 * N3 * 3);
       HIP_OK(hipMemcpy(drho, rho, 8 * N3, hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(du, u, 8 * N3 * 3, hipMemcpyHostToDevice));
-      hipLaunchKernelGGL(k_feq_dense, dim3(dense_chunks(N3)), dim3(256), 0, st, (const double*)drho,
-                         (const double*)du, (const uint8_t*)dsolid, dd, N3, (const int*)dc,
-                         (const double*)dw);
-      HIP_OK(hipStreamSynchronize(st));
-      free_last(2);
+      hipLaunchKernelGGL(k_feq_dense, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                         (const double*)drho, (const double*)du, (const uint8_t*)dsolid, dd, N3,
+                         (const int*)cvec_dev, (const double*)w_dev);
     }
     hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(19 * N3)), dim3(256), 0,
                        st, (const double*)dd, W, n, 19, 1);
     std::vector<int> objs(19);
-    for (int i = 0; i < 19; ++i) objs[i] = f[i] = E.acquire();
+    for (int i = 0; i < 19; ++i) objs[i] = dm.f[i] = E.acquire();
     dense_to_mps(W, 19, objs, cfg.chi_max, cfg.tol);
     HIP_OK(hipStreamSynchronize(st));
-    // release the dense staging (W, dd, and the solid copy)
-    (void)hipFree(W);
-    (void)hipFree(dd);
-    if (dsolid) (void)hipFree(dsolid);
-    E.allocs.erase(std::remove_if(E.allocs.begin(), E.allocs.end(),
-                                  [&](void* p) { return p == W || p == dd || p == dsolid; }),
-                   E.allocs.end());
+    // release the dense staging
+    while (E.allocs.size() > mark) {
+      (void)hipFree(E.allocs.back());
+      E.allocs.pop_back();
+    }
   }
-  int* cvec_dev = nullptr;
 
   // ---------------------------------------------------------------- step
   void step_once() {
-    HIP_OK(hipMemsetAsync(E.stats, 0, 8, st));
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, E.stats, 0.0, 1L);
     E.roundings = 0;
     E.products = 0;
-    const double tau = cfg.tau, om = 1.0 / tau;
-    // 1. moments
-    std::vector<std::vector<Term>> S(4);
-    for (int i = 0; i < 19; ++i) S[0].push_back({Coef{1.0, 0}, f[i]});
-    for (int a = 0; a < 3; ++a)
-      for (int i = 0; i < 19; ++i)
-        if (kC[i][a]) S[1 + a].push_back({Coef{(double)kC[i][a], 0}, f[i]});
+    static const int PI[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    // 1. moments rho, j_a (4 sums per domain)
+    std::vector<std::vector<Term>> S(4 * D);
+    for (int d = 0; d < D; ++d) {
+      for (int i = 0; i < 19; ++i) S[4 * d].push_back({Coef{1.0, 0, d}, dom[d].f[i]});
+      for (int a = 0; a < 3; ++a)
+        for (int i = 0; i < 19; ++i)
+          if (kC[i][a]) S[4 * d + 1 + a].push_back({Coef{(double)kC[i][a], 0, d}, dom[d].f[i]});
+    }
     std::vector<int> mom = E.sums(S, rho0);
-    int rho = mom[0];
-    int j[3] = {mom[1], mom[2], mom[3]};
-    // 2. rho_0
-    E.inner_ones({rho}, scratch);
-    hipLaunchKernelGGL(k_div_scalar, dim3(1), dim3(64), 0, st, (const double*)scratch, n_fluid,
-                       rho0);
-    // 3. inverse density
-    int r = -1;
-    if (cfg.inv_rho_mode == MPS_LBM_INV_TAYLOR2) {
-      int e = E.sums({{{Coef{1.0, -1}, rho}, {Coef{-1.0, 0}, one}}}, rho0)[0];
-      int ee = E.prods({{e, e}})[0];
-      r = E.sums({{{Coef{1.0, -1}, one}, {Coef{-1.0, -1}, e}, {Coef{1.0, -1}, ee}}}, rho0)[0];
-      E.release(e);
-      E.release(ee);
+    std::vector<int> rho(D), j(3 * D);
+    std::vector<int> rl(D);
+    for (int d = 0; d < D; ++d) {
+      rho[d] = mom[4 * d];
+      for (int a = 0; a < 3; ++a) j[3 * d + a] = mom[4 * d + 1 + a];
+    }
+    // 2. rho_0 = <1, rho> / N_fluid
+    E.inner_ones(rho, scratch);
+    hipLaunchKernelGGL(k_div_vec, dim3(1), dim3(std::max(64, ((D + 63) / 64) * 64)), 0, st,
+                       (const double*)scratch, (const double*)nfl, rho0, D);
+    // 3. inverse density (every domain of a handle uses the same mode)
+    const mps_lbm_config& c0 = dom[0].cfg;
+    std::vector<int> r(D);
+    if (c0.inv_rho_mode == MPS_LBM_INV_TAYLOR2) {
+      std::vector<std::vector<Term>> SE(D);
+      for (int d = 0; d < D; ++d) SE[d] = {{Coef{1.0, -1, d}, rho[d]}, {Coef{-1.0, 0, d}, one}};
+      std::vector<int> e = E.sums(SE, rho0);
+      std::vector<std::pair<int, int>> pe;
+      for (int d = 0; d < D; ++d) pe.push_back({e[d], e[d]});
+      std::vector<int> ee = E.prods(pe);
+      std::vector<std::vector<Term>> SR(D);
+      for (int d = 0; d < D; ++d)
+        SR[d] = {{Coef{1.0, -1, d}, one}, {Coef{-1.0, -1, d}, e[d]}, {Coef{1.0, -1, d}, ee[d]}};
+      r = E.sums(SR, rho0);
+      for (int d = 0; d < D; ++d) {
+        E.release(e[d]);
+        E.release(ee[d]);
+      }
     } else {
-      int y = E.sums({{{Coef{2.0, -1}, one}, {Coef{-1.0, -2}, rho}}}, rho0)[0];
-      for (int it = 1; it < cfg.inv_rho_iters; ++it) {
-        int ry = E.prods({{rho, y}})[0];
-        int t = E.sums({{{Coef{2.0, 0}, one}, {Coef{-1.0, 0}, ry}}}, rho0)[0];
-        int y2 = E.prods({{y, t}})[0];
-        E.release(ry);
-        E.release(t);
-        E.release(y);
+      std::vector<std::vector<Term>> SY(D);
+      for (int d = 0; d < D; ++d) SY[d] = {{Coef{2.0, -1, d}, one}, {Coef{-1.0, -2, d}, rho[d]}};
+      std::vector<int> y = E.sums(SY, rho0);
+      for (int it = 1; it < c0.inv_rho_iters; ++it) {
+        std::vector<std::pair<int, int>> p1;
+        for (int d = 0; d < D; ++d) p1.push_back({rho[d], y[d]});
+        std::vector<int> ry = E.prods(p1);
+        std::vector<std::vector<Term>> ST(D);
+        for (int d = 0; d < D; ++d) ST[d] = {{Coef{2.0, 0, d}, one}, {Coef{-1.0, 0, d}, ry[d]}};
+        std::vector<int> t = E.sums(ST, rho0);
+        std::vector<std::pair<int, int>> p2;
+        for (int d = 0; d < D; ++d) p2.push_back({y[d], t[d]});
+        std::vector<int> y2 = E.prods(p2);
+        for (int d = 0; d < D; ++d) {
+          E.release(ry[d]);
+          E.release(t[d]);
+          E.release(y[d]);
+        }
         y = y2;
       }
       r = y;
     }
-    // 4. j_eq, u, Pi
-    int jeq[3];
+    // 4. j_eq = j + tau g rho, u = j_eq (.) r, Pi_ab = j_eq,a (.) u_b
+    std::vector<int> jeq(3 * D);
     {
       std::vector<std::vector<Term>> SJ;
       std::vector<int> which;
-      for (int a = 0; a < 3; ++a) {
-        if (cfg.g[a] != 0.0) {
-          SJ.push_back({{Coef{1.0, 0}, j[a]}, {Coef{tau * cfg.g[a], 0}, rho}});
-          which.push_back(a);
-        } else {
-          jeq[a] = j[a];
+      for (int d = 0; d < D; ++d)
+        for (int a = 0; a < 3; ++a) {
+          const double ga = dom[d].cfg.g[a];
+          if (ga != 0.0) {
+            SJ.push_back({{Coef{1.0, 0, d}, j[3 * d + a]},
+                          {Coef{dom[d].cfg.tau * ga, 0, d}, rho[d]}});
+            which.push_back(3 * d + a);
+          } else {
+            jeq[3 * d + a] = j[3 * d + a];
+          }
         }
-      }
       if (!SJ.empty()) {
         std::vector<int> o = E.sums(SJ, rho0);
         for (size_t q = 0; q < which.size(); ++q) {
@@ -248,111 +300,150 @@ struct SimT : Sim {
         }
       }
     }
-    std::vector<int> u = E.prods({{jeq[0], r}, {jeq[1], r}, {jeq[2], r}});
-    static const int PI[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
+    std::vector<std::pair<int, int>> pu;
+    for (int d = 0; d < D; ++d)
+      for (int a = 0; a < 3; ++a) pu.push_back({jeq[3 * d + a], r[d]});
+    std::vector<int> u = E.prods(pu);  // u[3 d + a]
     std::vector<std::pair<int, int>> pp;
-    for (int q = 0; q < 6; ++q) pp.push_back({jeq[PI[q][0]], u[PI[q][1]]});
-    std::vector<int> Pi = E.prods(pp);
-    int S0 = E.sums({{{Coef{1.0, 0}, rho}, {Coef{-1.5, 0}, Pi[0]}, {Coef{-1.5, 0}, Pi[1]},
-                      {Coef{-1.5, 0}, Pi[2]}}},
-                    rho0)[0];
-    // 5. BGK
-    std::vector<std::vector<Term>> SB(19);
-    for (int i = 0; i < 19; ++i) {
-      double wi = kW(i);
-      SB[i].push_back({Coef{1.0 - om, 0}, f[i]});
-      SB[i].push_back({Coef{om * wi, 0}, S0});
-      for (int a = 0; a < 3; ++a)
-        if (kC[i][a]) SB[i].push_back({Coef{3.0 * om * wi * kC[i][a], 0}, jeq[a]});
-      for (int q = 0; q < 6; ++q) {
-        int a = PI[q][0], b = PI[q][1];
-        int coef = kC[i][a] * kC[i][b] * (a == b ? 1 : 2);
-        if (coef) SB[i].push_back({Coef{4.5 * om * wi * coef, 0}, Pi[q]});
+    for (int d = 0; d < D; ++d)
+      for (int q = 0; q < 6; ++q) pp.push_back({jeq[3 * d + PI[q][0]], u[3 * d + PI[q][1]]});
+    std::vector<int> Pi = E.prods(pp);  // Pi[6 d + q]
+    std::vector<std::vector<Term>> SS(D);
+    for (int d = 0; d < D; ++d)
+      SS[d] = {{Coef{1.0, 0, d}, rho[d]}, {Coef{-1.5, 0, d}, Pi[6 * d]},
+               {Coef{-1.5, 0, d}, Pi[6 * d + 1]}, {Coef{-1.5, 0, d}, Pi[6 * d + 2]}};
+    std::vector<int> S0 = E.sums(SS, rho0);
+    // 5. BGK relaxation
+    std::vector<std::vector<Term>> SB(19 * D);
+    for (int d = 0; d < D; ++d) {
+      const double om = 1.0 / dom[d].cfg.tau;
+      for (int i = 0; i < 19; ++i) {
+        const double wi = kW(i);
+        std::vector<Term>& t = SB[19 * d + i];
+        t.push_back({Coef{1.0 - om, 0, d}, dom[d].f[i]});
+        t.push_back({Coef{om * wi, 0, d}, S0[d]});
+        for (int a = 0; a < 3; ++a)
+          if (kC[i][a]) t.push_back({Coef{3.0 * om * wi * kC[i][a], 0, d}, jeq[3 * d + a]});
+        for (int q = 0; q < 6; ++q) {
+          const int a = PI[q][0], b = PI[q][1];
+          const int coef = kC[i][a] * kC[i][b] * (a == b ? 1 : 2);
+          if (coef) t.push_back({Coef{4.5 * om * wi * coef, 0, d}, Pi[6 * d + q]});
+        }
       }
     }
-    std::vector<int> fpost = E.sums(SB, rho0);
-    for (int i = 0; i < 19; ++i) E.release(f[i]);
-    E.release(rho);
-    E.release(r);
-    E.release(S0);
-    for (int q = 0; q < 6; ++q) E.release(Pi[q]);
-    for (int a = 0; a < 3; ++a) E.release(jeq[a]);
-    // 7a. open-face boundary terms (need post-collision f_ihat and u)
-    std::vector<std::vector<Term>> bterms(19);
+    std::vector<int> fpost = E.sums(SB, rho0);  // fpost[19 d + i]
+    for (int d = 0; d < D; ++d) {
+      for (int i = 0; i < 19; ++i) E.release(dom[d].f[i]);
+      E.release(rho[d]);
+      E.release(r[d]);
+      E.release(S0[d]);
+      for (int q = 0; q < 6; ++q) E.release(Pi[6 * d + q]);
+      for (int a = 0; a < 3; ++a) E.release(jeq[3 * d + a]);
+    }
+    // 7a. open-face boundary terms (post-collision f_ihat and u)
+    std::vector<std::vector<Term>> bterms(19 * D);
     std::vector<int> btemp;
-    for (int ax = 0; ax < 3; ++ax) {
-      if (!cfg.axis_open[ax]) continue;
-      for (int side = 0; side < 2; ++side) {
-        int face = 2 * ax + side;
-        int typ = cfg.face_bc[face];
-        if (typ == MPS_LBM_BC_NONE) continue;
-        int idx = side == 0 ? 0 : N - 1;
-        int entering = side == 0 ? 1 : -1;
-        int fp = fplane[face];
-        std::vector<int> uu;
-        if (typ == MPS_LBM_BC_PRESSURE) {
-          std::vector<int> uB = E.slice({u[0], u[1], u[2]}, {ax, ax, ax}, {idx, idx, idx});
-          E.round(uB);
-          std::vector<std::pair<int, int>> pq;
-          for (int q = 0; q < 6; ++q) pq.push_back({uB[PI[q][0]], uB[PI[q][1]]});
-          uu = E.prods(pq);
-          for (int o : uB) E.release(o);
-          for (int o : uu) btemp.push_back(o);
+    {
+      struct Face { int d, ax, side, typ, idx; };
+      std::vector<Face> faces;
+      for (int d = 0; d < D; ++d)
+        for (int ax = 0; ax < 3; ++ax) {
+          if (!dom[d].cfg.axis_open[ax]) continue;
+          for (int side = 0; side < 2; ++side) {
+            const int typ = dom[d].cfg.face_bc[2 * ax + side];
+            if (typ != MPS_LBM_BC_NONE) faces.push_back({d, ax, side, typ, side == 0 ? 0 : N - 1});
+          }
         }
-        std::vector<int> ent;
+      // u restricted to the pressure faces, rounded; then the uu products
+      std::vector<int> us, uax, uid;
+      for (const Face& F : faces)
+        if (F.typ == MPS_LBM_BC_PRESSURE)
+          for (int a = 0; a < 3; ++a) {
+            us.push_back(u[3 * F.d + a]);
+            uax.push_back(F.ax);
+            uid.push_back(F.idx);
+          }
+      std::vector<int> uB;
+      if (!us.empty()) {
+        uB = E.slice(us, uax, uid);
+        E.round(uB);
+      }
+      std::vector<std::pair<int, int>> pq;
+      for (size_t fp = 0; fp * 3 < uB.size(); ++fp)
+        for (int q = 0; q < 6; ++q) pq.push_back({uB[3 * fp + PI[q][0]], uB[3 * fp + PI[q][1]]});
+      std::vector<int> uu = pq.empty() ? std::vector<int>() : E.prods(pq);
+      for (int o : uB) E.release(o);
+      for (int o : uu) btemp.push_back(o);
+      // plane slices of the incoming populations
+      std::vector<int> src, axs, ids, fent;
+      for (size_t q = 0; q < faces.size(); ++q) {
+        const Face& F = faces[q];
+        const int entering = F.side == 0 ? 1 : -1;
         for (int i = 0; i < 19; ++i)
-          if (kC[i][ax] == entering) ent.push_back(i);
-        std::vector<int> src, axs, ids;
-        for (int i : ent) {
-          src.push_back(fpost[kOpp[i]]);
-          axs.push_back(ax);
-          ids.push_back(idx);
-        }
-        std::vector<int> fo = E.slice(src, axs, ids);
-        for (int o : fo) btemp.push_back(o);
-        for (size_t q = 0; q < ent.size(); ++q) {
-          int i = ent[q];
-          double c[3] = {(double)kC[i][0], (double)kC[i][1], (double)kC[i][2]};
-          if (typ == MPS_LBM_BC_VELOCITY) {
-            const double* ub = cfg.face_val[face];
-            double cu = c[0] * ub[0] + c[1] * ub[1] + c[2] * ub[2];
-            bterms[i].push_back({Coef{1.0, 0}, fo[q]});
-            bterms[i].push_back({Coef{6.0 * kW(i) * cu, cu == 0.0 ? 0 : 1}, fp});
-          } else {
-            double rb = cfg.face_val[face][0];
-            double kk = 2.0 * kW(i) * rb;
-            bterms[i].push_back({Coef{-1.0, 0}, fo[q]});
-            bterms[i].push_back({Coef{kk, 0}, fp});
-            for (int p = 0; p < 6; ++p) {
-              int a = PI[p][0], b = PI[p][1];
-              double coef = (a == b) ? kk * (4.5 * c[a] * c[a] - 1.5) : kk * 9.0 * c[a] * c[b];
-              if (coef != 0.0) bterms[i].push_back({Coef{coef, 0}, uu[p]});
-            }
+          if (kC[i][F.ax] == entering) {
+            src.push_back(fpost[19 * F.d + kOpp[i]]);
+            axs.push_back(F.ax);
+            ids.push_back(F.idx);
+            fent.push_back((int)q * 19 + i);
+          }
+      }
+      std::vector<int> fo = src.empty() ? std::vector<int>() : E.slice(src, axs, ids);
+      for (int o : fo) btemp.push_back(o);
+      int pface = 0;  // running index of pressure faces (order of uB / uu)
+      std::vector<int> pidx(faces.size(), -1);
+      for (size_t q = 0; q < faces.size(); ++q)
+        if (faces[q].typ == MPS_LBM_BC_PRESSURE) pidx[q] = pface++;
+      for (size_t t = 0; t < fent.size(); ++t) {
+        const int q = fent[t] / 19, i = fent[t] % 19;
+        const Face& F = faces[q];
+        const Domain& dm = dom[F.d];
+        const int face = 2 * F.ax + F.side;
+        const int fp = dm.fplane[face];
+        const double c[3] = {(double)kC[i][0], (double)kC[i][1], (double)kC[i][2]};
+        std::vector<Term>& bt = bterms[19 * F.d + i];
+        if (F.typ == MPS_LBM_BC_VELOCITY) {
+          const double* ub = dm.cfg.face_val[face];
+          const double cu = c[0] * ub[0] + c[1] * ub[1] + c[2] * ub[2];
+          bt.push_back({Coef{1.0, 0, F.d}, fo[t]});
+          bt.push_back({Coef{6.0 * kW(i) * cu, cu == 0.0 ? 0 : 1, F.d}, fp});
+        } else {
+          const double rb = dm.cfg.face_val[face][0];
+          const double kk = 2.0 * kW(i) * rb;
+          bt.push_back({Coef{-1.0, 0, F.d}, fo[t]});
+          bt.push_back({Coef{kk, 0, F.d}, fp});
+          for (int p = 0; p < 6; ++p) {
+            const int a = PI[p][0], b = PI[p][1];
+            const double coef = (a == b) ? kk * (4.5 * c[a] * c[a] - 1.5) : kk * 9.0 * c[a] * c[b];
+            if (coef != 0.0) bt.push_back({Coef{coef, 0, F.d}, uu[6 * pidx[q] + p]});
           }
         }
       }
     }
     // 6. streaming (f_0 does not move)
     std::vector<int> src;
-    std::vector<const int*> cv;
-    for (int i = 1; i < 19; ++i) {
-      src.push_back(fpost[i]);
-      cv.push_back(kC[i]);
+    std::vector<const int*> cv, ao;
+    for (int d = 0; d < D; ++d)
+      for (int i = 1; i < 19; ++i) {
+        src.push_back(fpost[19 * d + i]);
+        cv.push_back(kC[i]);
+        ao.push_back(dom[d].cfg.axis_open);
+      }
+    std::vector<int> fs1 = E.stream(src, cv, ao);
+    std::vector<int> fs(19 * D);
+    for (int d = 0; d < D; ++d) {
+      fs[19 * d] = fpost[19 * d];
+      for (int i = 1; i < 19; ++i) fs[19 * d + i] = fs1[18 * d + i - 1];
     }
-    std::vector<int> fs1 = E.stream(src, cv, cfg.axis_open);
-    int fs[19];
-    fs[0] = fpost[0];
-    for (int i = 1; i < 19; ++i) fs[i] = fs1[i - 1];
-    // 7b. add boundary terms
+    // 7b. add the boundary terms
     {
       std::vector<std::vector<Term>> SBC;
       std::vector<int> which;
-      for (int i = 0; i < 19; ++i) {
-        if (bterms[i].empty()) continue;
-        std::vector<Term> t{{Coef{1.0, 0}, fs[i]}};
-        t.insert(t.end(), bterms[i].begin(), bterms[i].end());
+      for (int q = 0; q < 19 * D; ++q) {
+        if (bterms[q].empty()) continue;
+        std::vector<Term> t{{Coef{1.0, 0, q / 19}, fs[q]}};
+        t.insert(t.end(), bterms[q].begin(), bterms[q].end());
         SBC.push_back(t);
-        which.push_back(i);
+        which.push_back(q);
       }
       if (!SBC.empty()) {
         std::vector<int> o = E.sums(SBC, rho0);
@@ -363,49 +454,124 @@ struct SimT : Sim {
       }
     }
     for (int o : btemp) E.release(o);
-    for (int i = 1; i < 19; ++i) E.release(fpost[i]);
-    for (int a = 0; a < 3; ++a) E.release(u[a]);
+    for (int d = 0; d < D; ++d) {
+      for (int i = 1; i < 19; ++i) E.release(fpost[19 * d + i]);
+      for (int a = 0; a < 3; ++a) E.release(u[3 * d + a]);
+    }
     // 8. obstacle bounce-back
-    if (mask >= 0) {
-      std::vector<std::pair<int, int>> pm;
-      for (int i = 1; i < 19; ++i) pm.push_back({fs[i], mask});
-      std::vector<int> g1 = E.prods(pm);
-      int g[19];
-      g[0] = -1;
-      for (int i = 1; i < 19; ++i) g[i] = g1[i - 1];
-      std::vector<int> hs;
-      std::vector<const int*> hc;
-      for (int i = 1; i < 19; ++i) {
-        hs.push_back(g[kOpp[i]]);
-        hc.push_back(kC[i]);
-      }
-      std::vector<int> h = E.stream(hs, hc, cfg.axis_open);
-      std::vector<std::vector<Term>> SO;
-      for (int i = 1; i < 19; ++i)
-        SO.push_back({{Coef{1.0, 0}, fs[i]}, {Coef{-1.0, 0}, g[i]}, {Coef{1.0, 0}, h[i - 1]}});
-      std::vector<int> o = E.sums(SO, rho0);
-      for (int i = 1; i < 19; ++i) {
-        E.release(fs[i]);
-        E.release(g[i]);
-        E.release(h[i - 1]);
-        fs[i] = o[i - 1];
+    {
+      std::vector<int> dd;
+      for (int d = 0; d < D; ++d)
+        if (dom[d].mask >= 0) dd.push_back(d);
+      if (!dd.empty()) {
+        std::vector<std::pair<int, int>> pm;
+        for (int d : dd)
+          for (int i = 1; i < 19; ++i) pm.push_back({fs[19 * d + i], dom[d].mask});
+        std::vector<int> g1 = E.prods(pm);  // g1[18 k + i - 1]
+        std::vector<int> hs;
+        std::vector<const int*> hc, ha;
+        for (size_t k = 0; k < dd.size(); ++k)
+          for (int i = 1; i < 19; ++i) {
+            hs.push_back(g1[18 * k + kOpp[i] - 1]);
+            hc.push_back(kC[i]);
+            ha.push_back(dom[dd[k]].cfg.axis_open);
+          }
+        std::vector<int> h = E.stream(hs, hc, ha);
+        std::vector<std::vector<Term>> SO;
+        for (size_t k = 0; k < dd.size(); ++k) {
+          const int d = dd[k];
+          for (int i = 1; i < 19; ++i)
+            SO.push_back({{Coef{1.0, 0, d}, fs[19 * d + i]},
+                          {Coef{-1.0, 0, d}, g1[18 * k + i - 1]},
+                          {Coef{1.0, 0, d}, h[18 * k + i - 1]}});
+        }
+        std::vector<int> o = E.sums(SO, rho0);
+        for (size_t k = 0; k < dd.size(); ++k) {
+          const int d = dd[k];
+          for (int i = 1; i < 19; ++i) {
+            E.release(fs[19 * d + i]);
+            E.release(g1[18 * k + i - 1]);
+            E.release(h[18 * k + i - 1]);
+            fs[19 * d + i] = o[18 * k + i - 1];
+          }
+        }
       }
     }
-    for (int i = 0; i < 19; ++i) f[i] = fs[i];
+    for (int d = 0; d < D; ++d)
+      for (int i = 0; i < 19; ++i) dom[d].f[i] = fs[19 * d + i];
     last_roundings = E.roundings;
     last_products = E.products;
   }
-  long long last_roundings = 0, last_products = 0;
 
   void step(int nsteps) override {
     for (int s = 0; s < nsteps; ++s) {
-      step_once();
+      if (gexec) {
+        HIP_OK(hipGraphLaunch(gexec, st));
+      } else {
+        step_once();
+      }
       ++steps;
     }
     HIP_OK(hipGetLastError());
   }
 
-  void to_dense(int what, double* out) override {
+  // Graph mode: one eager step brings the MPS pool to its peak size, then
+  // the next step is recorded into a HIP graph followed by copies that move
+  // the new populations back into the slots the step read from, so that the
+  // recorded launches (fixed pointers) are valid for every later step.
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+
+  void capture() override {
+    if (gexec) return;
+    if (!st) throw Error(-1, "graph capture needs a non-default stream");
+    step(1);
+    HIP_OK(hipStreamSynchronize(st));
+    std::vector<std::array<int, 19>> home(D);
+    for (int d = 0; d < D; ++d)
+      for (int i = 0; i < 19; ++i) home[d][i] = dom[d].f[i];
+    // the step releases its input populations half-way; during recording
+    // their slots are pinned so that no result or temporary lands in them
+    // and the final copies cannot overwrite a source still to be copied
+    E.pinned.assign(E.pool.size(), 0);
+    for (int d = 0; d < D; ++d)
+      for (int i = 0; i < 19; ++i) E.pinned[home[d][i]] = 1;
+    const int tk = E.tkind;
+    E.tkind = 0;
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      step_once();
+      for (int d = 0; d < D; ++d)
+        for (int i = 0; i < 19; ++i) {
+          const int now = dom[d].f[i], h = home[d][i];
+          const long tot = E.pool[now].total;
+          hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(tot)), dim3(256), 0, st,
+                             (const T*)E.pool[now].data, E.pool[h].data, tot);
+          hipLaunchKernelGGL(k_copy_ranks<T>, dim3(1), dim3(64), 0, st, E.D(h),
+                             (const MpsDev<T>*)E.D(now));
+          E.release(now);
+          dom[d].f[i] = h;
+        }
+    } catch (...) {
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      E.tkind = tk;
+      E.pinned.clear();
+      throw;
+    }
+    HIP_OK(hipStreamEndCapture(st, &graph));
+    E.tkind = tk;
+    E.pinned.clear();
+    HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+
+  ~SimT() {
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+  }
+
+  void to_dense(int d, int what, double* out) override {
     T* buf = nullptr;
     T* work = nullptr;
     double* mom = nullptr;
@@ -413,7 +579,7 @@ struct SimT : Sim {
     size_t bytes = sizeof(T) * N3 * 19;
     HIP_OK(hipMalloc(&buf, bytes));
     HIP_OK(hipMalloc(&work, bytes));
-    std::vector<int> objs(f, f + 19);
+    std::vector<int> objs(dom[d].f, dom[d].f + 19);
     E.to_dense(objs, buf, work);
     long nout = (what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3);
     HIP_OK(hipMalloc(&res, 8 * nout));
@@ -422,10 +588,10 @@ struct SimT : Sim {
                          st, (const T*)buf, res, n, 19, 0);
     } else {
       HIP_OK(hipMalloc(&mom, 8 * nout));
-      hipLaunchKernelGGL(k_moments_dense<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)buf, mom,
-                         N3, what, (const int*)cvec_dev);
-      hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(nout)), dim3(256), 0, st,
-                         (const double*)mom, res, n, (int)(nout / N3), 0);
+      hipLaunchKernelGGL(k_moments_dense<T>, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                         (const T*)buf, mom, N3, what, (const int*)cvec_dev);
+      hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(nout)), dim3(256), 0,
+                         st, (const double*)mom, res, n, (int)(nout / N3), 0);
     }
     HIP_OK(hipMemcpyAsync(out, res, 8 * nout, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
@@ -435,22 +601,22 @@ struct SimT : Sim {
     if (mom) (void)hipFree(mom);
   }
 
-  int get_mps(int which, double* out, size_t out_len, int* bonds) override {
-    int idx = which < 19 ? f[which] : mask;
+  int get_mps(int d, int which, double* out, size_t out_len, int* bonds) override {
+    int idx = which < 19 ? dom[d].f[which] : dom[d].mask;
     if (idx < 0) return fail(MPS_LBM_EINVAL, "no obstacle mask in this simulation");
-    MpsDev<T> d;
-    HIP_OK(hipMemcpyAsync(&d, E.D(idx), sizeof(d), hipMemcpyDeviceToHost, st));
+    MpsDev<T> md;
+    HIP_OK(hipMemcpyAsync(&md, E.D(idx), sizeof(md), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     size_t need = 0;
-    for (int k = 0; k <= n; ++k) bonds[k] = d.r[k];
-    for (int k = 0; k < n; ++k) need += (size_t)d.r[k] * PHYS * d.r[k + 1];
+    for (int k = 0; k <= n; ++k) bonds[k] = md.r[k];
+    for (int k = 0; k < n; ++k) need += (size_t)md.r[k] * PHYS * md.r[k + 1];
     if (!out) return MPS_LBM_OK;
     if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
     std::vector<T> tmp(need);
     size_t pos = 0;
     for (int k = 0; k < n; ++k) {
-      size_t cnt = (size_t)d.r[k] * PHYS * d.r[k + 1];
-      HIP_OK(hipMemcpyAsync(tmp.data() + pos, d.data + d.off[k], sizeof(T) * cnt,
+      size_t cnt = (size_t)md.r[k] * PHYS * md.r[k + 1];
+      HIP_OK(hipMemcpyAsync(tmp.data() + pos, md.data + md.off[k], sizeof(T) * cnt,
                             hipMemcpyDeviceToHost, st));
       pos += cnt;
     }
@@ -470,9 +636,10 @@ struct SimT : Sim {
     o->flops = fl;
   }
 
-  void observables(mps_lbm_obs* o) override {
+  void observables(int d, mps_lbm_obs* o) override {
     memset(o, 0, sizeof(*o));
-    std::vector<int> objs(f, f + 19);
+    const Domain& dm = dom[d];
+    std::vector<int> objs(dm.f, dm.f + 19);
     E.inner_ones(objs, scratch);
     double s[19];
     double stat[2] = {0, 0};
@@ -481,12 +648,12 @@ struct SimT : Sim {
     HIP_OK(hipMemcpyAsync(stat, E.stats, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(ist, E.istats, 16, hipMemcpyDeviceToHost, st));
     double r0 = 0.0;
-    HIP_OK(hipMemcpyAsync(&r0, rho0, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(&r0, rho0 + d, 8, hipMemcpyDeviceToHost, st));
     std::vector<MpsDev<T>> descs(19);
     for (int i = 0; i < 19; ++i)
-      HIP_OK(hipMemcpyAsync(&descs[i], E.D(f[i]), sizeof(MpsDev<T>), hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(&descs[i], E.D(dm.f[i]), sizeof(MpsDev<T>), hipMemcpyDeviceToHost, st));
     MpsDev<T> md;
-    if (mask >= 0) HIP_OK(hipMemcpyAsync(&md, E.D(mask), sizeof(md), hipMemcpyDeviceToHost, st));
+    if (dm.mask >= 0) HIP_OK(hipMemcpyAsync(&md, E.D(dm.mask), sizeof(md), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     o->step = steps;
     for (int i = 0; i < 19; ++i) {
@@ -494,7 +661,7 @@ struct SimT : Sim {
       for (int a = 0; a < 3; ++a) o->momentum[a] += kC[i][a] * s[i];
     }
     o->rho0 = r0;
-    o->n_fluid = n_fluid;
+    o->n_fluid = dm.n_fluid;
     double nv = 0.0;
     int mb = 1;
     for (int i = 0; i < 19; ++i) {
@@ -509,10 +676,10 @@ struct SimT : Sim {
     o->compression = nv > 0 ? 19.0 * (double)N3 / nv : 0.0;
     o->max_discarded = stat[0];
     int mk = 1;
-    if (mask >= 0)
+    if (dm.mask >= 0)
       for (int k = 1; k < n; ++k) mk = std::max(mk, md.r[k]);
-    o->mask_bond = mask >= 0 ? mk : 0;
-    o->mask_trunc_err = mask_err;
+    o->mask_bond = dm.mask >= 0 ? mk : 0;
+    o->mask_trunc_err = dm.mask_err;
     o->roundings = last_roundings;
     o->products = last_products;
     o->svd_failures = ist[0];
@@ -575,14 +742,9 @@ static int validate(const mps_lbm_config* c) {
   return MPS_LBM_OK;
 }
 
-int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const double* u,
-                            const double* f, const uint8_t* solid, void* hip_stream,
-                            mps_lbm_t** out) {
-  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
-  *out = nullptr;
-  int v = validate(cfg);
-  if (v) return v;
-  if (!f && (!rho || !u)) return fail(MPS_LBM_EINVAL, "need f or both rho and u");
+static int create(const mps_lbm_config* cfgs, int count, const double* const* rho,
+                  const double* const* u, const double* const* f, const uint8_t* const* solid,
+                  void* hip_stream, mps_lbm_t** out) {
   try {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -591,14 +753,18 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const 
     }
     std::unique_ptr<mps_lbm> h(new mps_lbm());
     hipStream_t st = (hipStream_t)hip_stream;
-    if (cfg->precision == MPS_LBM_FP64) {
-      auto* s = new SimT<double>(*cfg, st);
+    if (cfgs[0].precision == MPS_LBM_FP64) {
+      auto* s = new SimT<double>(cfgs, count, st);
       h->sim.reset(s);
-      s->init(rho, u, f, solid);
+      for (int d = 0; d < count; ++d)
+        s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
+                       solid ? solid[d] : nullptr);
     } else {
-      auto* s = new SimT<float>(*cfg, st);
+      auto* s = new SimT<float>(cfgs, count, st);
       h->sim.reset(s);
-      s->init(rho, u, f, solid);
+      for (int d = 0; d < count; ++d)
+        s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
+                       solid ? solid[d] : nullptr);
     }
     *out = h.release();
     g_last_error.clear();
@@ -608,6 +774,57 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const 
   } catch (const std::exception& e) {
     return fail(MPS_LBM_EHIP, e.what());
   }
+}
+
+int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const double* u,
+                            const double* f, const uint8_t* solid, void* hip_stream,
+                            mps_lbm_t** out) {
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int v = validate(cfg);
+  if (v) return v;
+  if (!f && (!rho || !u)) return fail(MPS_LBM_EINVAL, "need f or both rho and u");
+  return create(cfg, 1, &rho, &u, &f, &solid, hip_stream, out);
+}
+
+int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* const* rho,
+                       const double* const* u, const uint8_t* const* solid, void* hip_stream,
+                       mps_lbm_t** out) {
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!cfgs || count < 1) return fail(MPS_LBM_EINVAL, "need count >= 1 configurations");
+  if (!rho || !u) return fail(MPS_LBM_EINVAL, "rho and u are NULL");
+  for (int d = 0; d < count; ++d) {
+    int v = validate(cfgs + d);
+    if (v) return v;
+    if (!rho[d] || !u[d]) return fail(MPS_LBM_EINVAL, "rho[d] or u[d] is NULL");
+    const mps_lbm_config& a = cfgs[0];
+    const mps_lbm_config& b = cfgs[d];
+    if (a.n != b.n || a.chi_max != b.chi_max || a.precision != b.precision ||
+        a.tol != b.tol || a.sweeps != b.sweeps || a.inv_rho_mode != b.inv_rho_mode ||
+        a.inv_rho_iters != b.inv_rho_iters)
+      return fail(MPS_LBM_EINVAL,
+                  "batched domains must share n, chi_max, precision, tol, sweeps and the "
+                  "inverse-density mode");
+  }
+  return create(cfgs, count, rho, u, nullptr, solid, hip_stream, out);
+}
+
+int mps_lbm_capture_step(mps_lbm_t* h) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  try {
+    h->sim->capture();
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(MPS_LBM_EHIP, e.what());
+  }
+}
+
+int mps_lbm_domains(const mps_lbm_t* h) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  return h->sim->domains();
 }
 
 int mps_lbm_step(mps_lbm_t* h, int nsteps) {
@@ -623,17 +840,16 @@ int mps_lbm_step(mps_lbm_t* h, int nsteps) {
   }
 }
 
-int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len) {
+int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, size_t out_len) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
   if (what < MPS_LBM_POPS || what > MPS_LBM_VEL) return fail(MPS_LBM_EINVAL, "bad what");
-  SimT<double>* sd = dynamic_cast<SimT<double>*>(h->sim.get());
-  SimT<float>* sf = dynamic_cast<SimT<float>*>(h->sim.get());
-  long N3 = sd ? sd->N3 : sf->N3;
+  if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
+  const long N3 = h->sim->cells();
   size_t need = (size_t)((what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3));
   if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
   try {
-    h->sim->to_dense(what, out);
+    h->sim->to_dense(domain, what, out);
     return MPS_LBM_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());
@@ -642,12 +858,30 @@ int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len) {
   }
 }
 
+int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len) {
+  return mps_lbm_to_dense_domain(h, 0, what, out, out_len);
+}
+
 int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* bonds) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!bonds) return fail(MPS_LBM_EINVAL, "bonds is NULL");
   if (which < 0 || which > MPS_LBM_MPS_MASK) return fail(MPS_LBM_EINVAL, "bad which");
   try {
-    return h->sim->get_mps(which, out, out_len, bonds);
+    return h->sim->get_mps(0, which, out, out_len, bonds);
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::exception& e) {
+    return fail(MPS_LBM_EHIP, e.what());
+  }
+}
+
+int mps_lbm_observables_domain(mps_lbm_t* h, int domain, mps_lbm_obs* out) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
+  try {
+    h->sim->observables(domain, out);
+    return MPS_LBM_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());
   } catch (const std::exception& e) {
@@ -656,16 +890,7 @@ int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* b
 }
 
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out) {
-  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
-  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
-  try {
-    h->sim->observables(out);
-    return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  return mps_lbm_observables_domain(h, 0, out);
 }
 
 int mps_lbm_kernel_timing(mps_lbm_t* h, int kind) {

@@ -31,7 +31,9 @@ MPS_MASK = 19
 EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm_step",
                    "mps_lbm_to_dense", "mps_lbm_observables", "mps_lbm_destroy",
                    "mps_lbm_last_error", "mps_lbm_version", "mps_lbm_kernel_timing",
-                   "mps_lbm_kernel_stats", "mps_lbm_get_mps"])
+                   "mps_lbm_kernel_stats", "mps_lbm_get_mps", "mps_lbm_init_batch",
+                   "mps_lbm_domains", "mps_lbm_to_dense_domain",
+                   "mps_lbm_observables_domain", "mps_lbm_capture_step"])
 
 
 class Config(C.Structure):
@@ -97,6 +99,17 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_kernel_stats.restype = C.c_int
     lib.mps_lbm_get_mps.argtypes = [P, C.c_int, DP, C.c_size_t, C.POINTER(C.c_int)]
     lib.mps_lbm_get_mps.restype = C.c_int
+    lib.mps_lbm_init_batch.argtypes = [C.POINTER(Config), C.c_int, C.POINTER(DP), C.POINTER(DP),
+                                       C.POINTER(C.POINTER(C.c_uint8)), P, C.POINTER(P)]
+    lib.mps_lbm_init_batch.restype = C.c_int
+    lib.mps_lbm_capture_step.argtypes = [P]
+    lib.mps_lbm_capture_step.restype = C.c_int
+    lib.mps_lbm_domains.argtypes = [P]
+    lib.mps_lbm_domains.restype = C.c_int
+    lib.mps_lbm_to_dense_domain.argtypes = [P, C.c_int, C.c_int, DP, C.c_size_t]
+    lib.mps_lbm_to_dense_domain.restype = C.c_int
+    lib.mps_lbm_observables_domain.argtypes = [P, C.c_int, C.POINTER(Obs)]
+    lib.mps_lbm_observables_domain.restype = C.c_int
     _lib = lib
     return lib
 
@@ -166,6 +179,59 @@ def mps_lbm_kernel_stats(h) -> KStats:
     return k
 
 
+def mps_lbm_init_batch(cfgs, rhos, us, solids=None, hip_stream: Optional[int] = None):
+    """One handle advancing len(cfgs) domains together (see the C header)."""
+    lib = load()
+    cnt = len(cfgs)
+    carr = (Config * cnt)(*cfgs)
+    keep = []
+    def darr(fields):
+        out = (C.POINTER(C.c_double) * cnt)()
+        for d, a in enumerate(fields):
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            keep.append(a)
+            out[d] = a.ctypes.data_as(C.POINTER(C.c_double))
+        return out
+    r, u = darr(rhos), darr(us)
+    sarr = None
+    if solids is not None:
+        sarr = (C.POINTER(C.c_uint8) * cnt)()
+        for d, m in enumerate(solids):
+            if m is None:
+                sarr[d] = None
+            else:
+                m = np.ascontiguousarray(m, dtype=np.uint8)
+                keep.append(m)
+                sarr[d] = m.ctypes.data_as(C.POINTER(C.c_uint8))
+    h = C.c_void_p()
+    _check(lib.mps_lbm_init_batch(carr, cnt, r, u, sarr, C.c_void_p(hip_stream or 0), C.byref(h)))
+    return h
+
+
+def mps_lbm_capture_step(h):
+    _check(load().mps_lbm_capture_step(h))
+
+
+def mps_lbm_domains(h) -> int:
+    v = load().mps_lbm_domains(h)
+    if v < 0:
+        _check(v)
+    return v
+
+
+def mps_lbm_to_dense_domain(h, domain: int, what: int, N: int) -> np.ndarray:
+    shape = {POPS: (19, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
+    out = np.empty(shape, dtype=np.float64)
+    _check(load().mps_lbm_to_dense_domain(h, int(domain), int(what), _dp(out), out.size))
+    return out
+
+
+def mps_lbm_observables_domain(h, domain: int) -> Obs:
+    o = Obs()
+    _check(load().mps_lbm_observables_domain(h, int(domain), C.byref(o)))
+    return o
+
+
 def mps_lbm_get_mps(h, which: int, n: int):
     """One MPS of the state as a list of FP64 cores [r_k][8][r_{k+1}]."""
     lib = load()
@@ -213,6 +279,50 @@ def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_
     return c
 
 
+class BatchSimulation:
+    """Several domains (workloads.Case, equal n / chi / precision / tol)
+    advanced together by one handle."""
+
+    def __init__(self, cases, precision=None, hip_stream=None, **kw):
+        self.cases = list(cases)
+        cfgs = [config_from_case(c, precision, **kw) for c in self.cases]
+        self.h = mps_lbm_init_batch(cfgs, [c.rho0_field() for c in self.cases],
+                                    [c.u0_field() for c in self.cases],
+                                    [c.solid for c in self.cases], hip_stream=hip_stream)
+
+    def step(self, n=1):
+        mps_lbm_step(self.h, n)
+
+    def dense(self, domain, what=POPS):
+        return mps_lbm_to_dense_domain(self.h, domain, what, self.cases[domain].N)
+
+    def observables(self, domain=0):
+        return mps_lbm_observables_domain(self.h, domain)
+
+    def domains(self):
+        return mps_lbm_domains(self.h)
+
+    def capture(self):
+        mps_lbm_capture_step(self.h)
+
+    def kernel_timing(self, kind):
+        mps_lbm_kernel_timing(self.h, kind)
+
+    def kernel_stats(self):
+        return mps_lbm_kernel_stats(self.h)
+
+    def close(self):
+        if self.h:
+            mps_lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Simulation:
     """Convenience wrapper owning one handle."""
 
@@ -239,6 +349,9 @@ class Simulation:
 
     def mps(self, which):
         return mps_lbm_get_mps(self.h, which, self.case.n)
+
+    def capture(self):
+        mps_lbm_capture_step(self.h)
 
     def close(self):
         if self.h:

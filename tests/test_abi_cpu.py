@@ -104,3 +104,34 @@ def test_null_handle_calls_fail_cleanly():
     assert so.mps_lbm_observables(None, C.byref(o)) == L.EINVAL
     so.mps_lbm_destroy(None)
     assert so.mps_lbm_version().decode().startswith("mps-lbm")
+
+
+def test_batch_init_validation_before_device_use():
+    L = lib()
+    so = L.load()
+    h = C.c_void_p()
+    c0 = L.mps_lbm_default_config()
+    c1 = L.mps_lbm_default_config()
+    arr = (L.Config * 2)(c0, c1)
+    rho = np.ones((16, 16, 16))
+    u = np.zeros((3, 16, 16, 16))
+    dp = C.POINTER(C.c_double)
+    R = (dp * 2)(rho.ctypes.data_as(dp), rho.ctypes.data_as(dp))
+    U = (dp * 2)(u.ctypes.data_as(dp), u.ctypes.data_as(dp))
+    # count < 1, NULL fields
+    assert so.mps_lbm_init_batch(arr, 0, R, U, None, None, C.byref(h)) == L.EINVAL
+    assert so.mps_lbm_init_batch(arr, 2, None, U, None, None, C.byref(h)) == L.EINVAL
+    # domains that differ in a shared field (n, chi_max, precision, tol)
+    for field, value in [("n", 5), ("chi_max", 8), ("precision", L.FP32), ("tol", 1e-6)]:
+        arr = (L.Config * 2)(L.mps_lbm_default_config(), L.mps_lbm_default_config())
+        setattr(arr[1], field, value)
+        assert so.mps_lbm_init_batch(arr, 2, R, U, None, None, C.byref(h)) == L.EINVAL
+        assert "share" in so.mps_lbm_last_error().decode()
+    # an invalid member configuration
+    arr = (L.Config * 2)(L.mps_lbm_default_config(), L.mps_lbm_default_config())
+    arr[1].tau = 0.4
+    assert so.mps_lbm_init_batch(arr, 2, R, U, None, None, C.byref(h)) == L.EINVAL
+    assert not h.value
+    assert so.mps_lbm_domains(None) == L.EINVAL
+    o = L.Obs()
+    assert so.mps_lbm_observables_domain(None, 0, C.byref(o)) == L.EINVAL
