@@ -32,6 +32,10 @@ def make_case(name):
         return WL.case_porous(n=5, chi=32, tau=0.6, tol=1e-8, precision="fp32")
     if name == "channel16":
         return WL.case_channel()
+    if name == "vascular128":
+        # 128^3 branching tube tree, velocity inlet 0.02 / pressure outlet,
+        # chi = 128, BF16 contractions (FP32 storage and factorisations)
+        return WL.case_vascular(n=7, chi=128, tau=0.55, tol=1e-8, precision="bf16")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -111,7 +115,8 @@ def roofline(kind, ks, prec):
     flops_per_launch = ks.flops / max(ks.launches, 1)
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     if kind == "prodgemm":
-        bound, peak = "mfma", PEAK["fp32_tflops"] if prec == "fp32" else PEAK["fp64_tflops"]
+        bound = "mfma"
+        peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"]}.get(prec, PEAK["fp64_tflops"])
     else:
         # FP64 vector ALU: 256 CUs x 2.4 GHz x 128 FP64 flops/clock/CU
         bound, peak = "alu", PEAK["fp64_tflops"]
@@ -133,6 +138,8 @@ def main():
                     help="also time this many domains of the workload advanced together "
                          "(0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--mfma-steps", type=int, default=2,
+                    help="steps timed for the MFMA utilisation of the product GEMMs")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue the step kernel by kernel instead of replaying a HIP graph")
     ap.add_argument("--roofline-kernel", default="cholesky",
@@ -145,11 +152,18 @@ def main():
     import torch
     from paper_2512_07615_amd import mps_lbm as L
 
+    def progress(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     case = make_case(args.workload)
     stream = torch.cuda.Stream()
+    t_init = time.perf_counter()
     sim = L.Simulation(case, hip_stream=stream.cuda_stream)
+    progress(f"{case.name}: initialised in {time.perf_counter() - t_init:.1f} s")
     for _ in range(args.warmup):
         sim.step(1)
+        torch.cuda.synchronize()
+        progress("warm-up step done")
     torch.cuda.synchronize()
     kind = {"jacobi": L.K_JACOBI, "householder": L.K_HOUSEHOLDER,
             "prodgemm": L.K_PRODGEMM, "cholesky": L.K_CHOLESKY}[args.roofline_kernel]
@@ -162,6 +176,7 @@ def main():
     e1.record(stream)
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.steps
+    progress(f"timed {args.steps} steps: {ms:.1f} ms/step")
     ks = sim.kernel_stats()
     obs = sim.observables()
     sps = 1000.0 / ms
@@ -170,7 +185,8 @@ def main():
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32" if case.precision == "fp32" else "f64", "data": "synthetic",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mfma/f32"}[case.precision],
+        "data": "synthetic",
         "config": {"workload": case.name, "n": case.n, "chi": case.chi, "tau": case.tau,
                    "tol": case.tol, "geometry": case.meta,
                    "equiv_mlups": N3 * sps / 1e6, "max_bond": obs.max_bond,
@@ -182,6 +198,18 @@ def main():
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)
     out["roofline"]["share_of_step"] = ks.total_ms / (ms * args.steps)
+    if args.mfma_steps > 0:
+        # MFMA utilisation of the product contractions, timed the same way
+        sim.kernel_timing(L.K_PRODGEMM)
+        e0.record(stream)
+        for _ in range(args.mfma_steps):
+            sim.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        mms = e0.elapsed_time(e1) / args.mfma_steps
+        kp = sim.kernel_stats()
+        out["roofline_mfma"] = roofline("prodgemm", kp, case.precision)
+        out["roofline_mfma"]["share_of_step"] = kp.total_ms / (mms * args.mfma_steps)
     if not args.no_graph:
         # the same step recorded once as a HIP graph and replayed (the timed
         # region above issues it kernel by kernel, with per-launch events)

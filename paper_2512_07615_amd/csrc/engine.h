@@ -6,6 +6,7 @@
 // waits for the device.  MPS objects come from a pool of capacity-sized
 // buffers and are referred to by pool index on the host.
 #pragma once
+#include <type_traits>
 #include <algorithm>
 #include <cstring>
 #include <string>
@@ -1049,6 +1050,21 @@ class Engine {
     return l;
   }
 
+  // Product contractions: in the working type, or (BF16 policy, FP32
+  // storage) with operands rounded to BF16 on a BF16 MFMA, FP32 accumulate.
+  bool bf16_products = false;
+  template <typename F>
+  void pgemm(const F& f, int nprob, int mcap, int ncap, int bcap, hipStream_t s,
+             double* flops = nullptr) {
+    if constexpr (std::is_same<T, float>::value) {
+      if (bf16_products) {
+        launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops);
+        return;
+      }
+    }
+    launch_gemm<T, T, T, Tacc>(f, nprob, mcap, ncap, bcap, s, flops);
+  }
+
   // ------------------------------------------------------------ QR op
   template <typename F>
   void qr(const F& f, int nprob, int mcap, int scap) {
@@ -1352,7 +1368,7 @@ class Engine {
         hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)qtmp, qslot,
                            p);
         tbegin(3);
-        launch_gemm<T, T, T, Tacc>(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
+        pgemm(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
                                    cpb[p + 1] * cpb[p + 1], 1, st, kf(3));
         tend(3);
       } else {
@@ -1369,30 +1385,30 @@ class Engine {
 
   void local_update(const ProdCtx<T>& c, int p, int cnt) {
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st,
+    pgemm(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st,
                                kf(3));
     tend(3);
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1], PHYS * cpb[p],
+    pgemm(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1], PHYS * cpb[p],
                                st, kf(3));
     tend(3);
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st,
+    pgemm(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st,
                                kf(3));
     tend(3);
   }
 
   void right_env(const ProdCtx<T>& c, int p, int cnt) {
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], PHYS * cpb[p], cpb[p + 1],
+    pgemm(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], PHYS * cpb[p], cpb[p + 1],
                                st, kf(3));
     tend(3);
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st,
+    pgemm(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st,
                                kf(3));
     tend(3);
     tbegin(3);
-    launch_gemm<T, T, T, Tacc>(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3));
+    pgemm(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3));
     tend(3);
   }
 

@@ -66,7 +66,20 @@ template <> struct MfmaT<float> {
 constexpr int GT = 64;   // tile edge
 constexpr int GK = 16;   // K step
 
-template <typename TA, typename TB, typename TC, typename Tacc, typename F>
+// BF16 operands for v_mfma_f32_16x16x16bf16_1k: lane l supplies
+// A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j = 0..3 (one
+// K tile of 16 per instruction); the accumulator layout is that of the FP32
+// 16x16x4 MFMA (checked on gfx950 with a one-wave probe).
+typedef short bf4 __attribute__((ext_vector_type(4)));
+__device__ inline short bf16_bits(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return (short)(u >> 16);
+}
+
+// MODE 0: MFMA in the accumulation type; MODE 1 (Tacc = float): operands
+// rounded to BF16, BF16 MFMA with FP32 accumulation.
+template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
 __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops) {
   typedef typename MfmaT<Tacc>::V V;
   __shared__ Tacc As[GK][GT + 1];
@@ -115,17 +128,33 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       Bs[kb][nn] = u;
     }
     __syncthreads();
+    if constexpr (MODE == 1) {
+      bf4 a0, a1, b0, b1;
 #pragma unroll
-    for (int ks = 0; ks < GK / 4; ++ks) {
-      int kr = ks * 4 + (lane >> 4);
-      Tacc a0 = As[kr][wm * 32 + (lane & 15)];
-      Tacc a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-      Tacc bb0 = Bs[kr][wn * 32 + (lane & 15)];
-      Tacc bb1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
-      acc[0][0] = MfmaT<Tacc>::op(a0, bb0, acc[0][0]);
-      acc[0][1] = MfmaT<Tacc>::op(a0, bb1, acc[0][1]);
-      acc[1][0] = MfmaT<Tacc>::op(a1, bb0, acc[1][0]);
-      acc[1][1] = MfmaT<Tacc>::op(a1, bb1, acc[1][1]);
+      for (int j = 0; j < 4; ++j) {
+        const int kr = 4 * (lane >> 4) + j;
+        a0[j] = bf16_bits(As[kr][wm * 32 + (lane & 15)]);
+        a1[j] = bf16_bits(As[kr][wm * 32 + 16 + (lane & 15)]);
+        b0[j] = bf16_bits(Bs[kr][wn * 32 + (lane & 15)]);
+        b1[j] = bf16_bits(Bs[kr][wn * 32 + 16 + (lane & 15)]);
+      }
+      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int ks = 0; ks < GK / 4; ++ks) {
+        int kr = ks * 4 + (lane >> 4);
+        Tacc a0 = As[kr][wm * 32 + (lane & 15)];
+        Tacc a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+        Tacc bb0 = Bs[kr][wn * 32 + (lane & 15)];
+        Tacc bb1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+        acc[0][0] = MfmaT<Tacc>::op(a0, bb0, acc[0][0]);
+        acc[0][1] = MfmaT<Tacc>::op(a0, bb1, acc[0][1]);
+        acc[1][0] = MfmaT<Tacc>::op(a1, bb0, acc[1][0]);
+        acc[1][1] = MfmaT<Tacc>::op(a1, bb1, acc[1][1]);
+      }
     }
     __syncthreads();
   }
@@ -148,14 +177,14 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
 }
 
 // Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps).
-template <typename TA, typename TB, typename TC, typename Tacc, typename F>
+template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
 inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap,
                         hipStream_t s, double* flops = nullptr) {
   if (nprob <= 0 || mcap <= 0 || ncap <= 0 || batch_cap <= 0) return;
   int tiles = ceil_div(mcap, GT) * ceil_div(ncap, GT);
   long grid = (long)nprob * batch_cap * tiles;
   if (grid <= 0) return;
-  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F>), dim3((unsigned)grid), dim3(256), 0, s,
+  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE>), dim3((unsigned)grid), dim3(256), 0, s,
                      f, tiles, batch_cap, flops);
   HIP_OK(hipGetLastError());
 }

@@ -96,6 +96,7 @@ struct SimT : Sim {
       for (int i = 0; i < 6; ++i) dom[d].fplane[i] = -1;
     }
     E.sweeps = c.sweeps;
+    E.bf16_products = (c.precision == MPS_LBM_BF16);
     E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
     rho0 = (double*)E.dalloc(8 * (D + 8));
     nfl = (double*)E.dalloc(8 * (D + 8));
@@ -726,7 +727,8 @@ static int validate(const mps_lbm_config* c) {
     return fail(MPS_LBM_EINVAL, "unknown inverse-density mode");
   if (c->inv_rho_mode == MPS_LBM_INV_NEWTON && c->inv_rho_iters < 1)
     return fail(MPS_LBM_EINVAL, "inv_rho_iters < 1");
-  if (c->precision != MPS_LBM_FP64 && c->precision != MPS_LBM_FP32)
+  if (c->precision != MPS_LBM_FP64 && c->precision != MPS_LBM_FP32 &&
+      c->precision != MPS_LBM_BF16)
     return fail(MPS_LBM_EINVAL, "unknown precision");
   if (c->sweeps < 1) return fail(MPS_LBM_EINVAL, "sweeps < 1");
   for (int a = 0; a < 3; ++a) {
