@@ -1155,7 +1155,8 @@ class Engine {
                                        sus, rdelta, rdisc, chi_cap, istats},
                          ep, cnt);
       tbegin(1);
-      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
+      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024),
+                         (size_t)lds_elems * 8, st,
                          (const EigProb*)ep, lds_elems, 40, kf(1));
       tend(1);
       launch_gemm<double, T, T, double>(FUtM<T>{L, ep, qtmp, qslot, k}, cnt, scap, ccap, 1, st);
@@ -1174,8 +1175,8 @@ class Engine {
                                        rdelta, rdisc, chi_cap, istats, nullptr, 0},
                          sp, cnt);
       tbegin(1);
-      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
-                         (const SvdProb*)sp, lds_elems, 40, kf(1));
+      hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), dim3(scap <= 64 ? 512 : 1024),
+                         (size_t)lds_elems * 8, st, (const SvdProb*)sp, lds_elems, 40, kf(1));
       tend(1);
       launch_gemm<T, double, T, double>(FnCoreTimesUS<T>{L, qp, svdUS, sus, ctmp, maxcore, k},
                                         cnt, capb[k - 1] * PHYS, scap, 1, st);

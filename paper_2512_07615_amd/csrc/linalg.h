@@ -737,6 +737,7 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
   const int G = jacobi_group_lanes(n, nwaves);
   const int gpw = 64 / G, gl = lane % G, grp = lane / G;
   const int par = nwaves * gpw;
+  const bool inreg = m <= 8 * G;
   int sweep = 0;
   for (; sweep < max_sweeps && n > 1; ++sweep) {
     if (tid == 0) *flag = 0;
@@ -745,21 +746,39 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
     for (int t = 0; t < P - 1; ++t) {
       for (int base = 0; base < P / 2; base += par) {
         const int k = base + wv * gpw + grp;
+        // round-robin pairing; both indices stay below 2 (P - 1), so a
+        // conditional subtraction replaces the modulo
         int i1 = n, i2 = n;
         if (k < P / 2) {
-          if (k == 0) { i1 = t; i2 = P - 1; }
-          else { i1 = (t + k) % (P - 1); i2 = (t - k + (P - 1)) % (P - 1); }
+          if (k == 0) {
+            i1 = t; i2 = P - 1;
+          } else {
+            i1 = t + k;
+            if (i1 >= P - 1) i1 -= P - 1;
+            i2 = t - k;
+            if (i2 < 0) i2 += P - 1;
+          }
         }
         const bool act = i1 < n && i2 < n;
         const int a = act ? (i1 < i2 ? i1 : i2) : 0, b = act ? (i1 < i2 ? i2 : i1) : 0;
         double* ca = A + (long)a * m;
         double* cb = A + (long)b * m;
         double al = 0.0, be = 0.0, ga = 0.0;
-        if (act)
+        double xr[8], yr[8];  // the group's rows when m <= 8 G
+        if (inreg) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = gl + q * G;
+            xr[q] = (act && r < m) ? ca[r] : 0.0;
+            yr[q] = (act && r < m) ? cb[r] : 0.0;
+            al += xr[q] * xr[q]; be += yr[q] * yr[q]; ga += xr[q] * yr[q];
+          }
+        } else if (act) {
           for (int r = gl; r < m; r += G) {
             double x = ca[r], y = cb[r];
             al += x * x; be += y * y; ga += x * y;
           }
+        }
         al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
         if (!act) continue;
         if (gl == 0) work += 6.0 * m;
@@ -768,13 +787,44 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
         // (norm^2 <= small2) is numerically zero and is not rotated
         if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
         if (al <= small2 || be <= small2) continue;
-        double zeta = (be - al) / (2.0 * ga);
-        double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        double cs = 1.0 / sqrt(1.0 + tt * tt), sn = cs * tt;
-        for (int r = gl; r < m; r += G) {
-          double x = ca[r], y = cb[r];
-          ca[r] = cs * x - sn * y;
-          cb[r] = sn * x + cs * y;
+        // rotation angle (Rutishauser's formulas); reciprocals and reciprocal
+        // square roots from the hardware estimates refined by two
+        // Newton-Raphson steps each, accurate to a few ulp, which keeps the
+        // rotation orthogonal to working precision
+        const double g2 = 2.0 * ga;
+        double ig = __builtin_amdgcn_rcp(g2);
+        ig = ig * (2.0 - g2 * ig);
+        ig = ig * (2.0 - g2 * ig);
+        const double zeta = (be - al) * ig;
+        const double q1 = 1.0 + zeta * zeta;
+        double rq = __builtin_amdgcn_rsq(q1);
+        rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+        rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+        const double den = fabs(zeta) + q1 * rq;
+        double id = __builtin_amdgcn_rcp(den);
+        id = id * (2.0 - den * id);
+        id = id * (2.0 - den * id);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+        const double q2 = 1.0 + tt * tt;
+        double cs = __builtin_amdgcn_rsq(q2);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        const double sn = cs * tt;
+        if (inreg) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = gl + q * G;
+            if (r < m) {
+              ca[r] = cs * xr[q] - sn * yr[q];
+              cb[r] = sn * xr[q] + cs * yr[q];
+            }
+          }
+        } else {
+          for (int r = gl; r < m; r += G) {
+            double x = ca[r], y = cb[r];
+            ca[r] = cs * x - sn * y;
+            cb[r] = sn * x + cs * y;
+          }
         }
         if (W) {
           double* wa = W + (long)a * nw;
