@@ -831,6 +831,9 @@ class Engine {
   int* cq_n = nullptr;  // [2 * MAXB] dims of the two Cholesky passes
   EigProb* ep = nullptr;
   double eps_rank = 1e-14;
+  // second Cholesky-QR pass skipped when the first already left the Gram
+  // within this distance of the identity (far below FP32 resolution)
+  double cq_skip = 1e-9;
   int pbatch = 1;
   int sweeps = 2;
   long roundings = 0, products = 0;
@@ -1101,7 +1104,7 @@ class Engine {
     tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)(cq_n + MAXB), 1,
                        w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob, 1,
-                       kf(4));
+                       kf(4), cq_skip);
     tend(4);
     hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 1);
     launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);

@@ -640,7 +640,8 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
                                                   long sq, double* Bbase, double* Rbase,
                                                   int* rank_out, double eps_rank, int lds_elems,
                                                   int nprob, int want_b = 1,
-                                                  double* flops = nullptr) {
+                                                  double* flops = nullptr,
+                                                  double skip_tol = 0.0) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[8];
@@ -656,6 +657,31 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
   const int n = dims[pr * dim_stride];
   if (n <= 0 || n > 1024) return;
   double* Gg = Gbase + pr * sq;
+  if (skip_tol > 0.0) {
+    // a Gram that is the identity to within skip_tol (the second pass of
+    // Cholesky-QR after a well-conditioned first pass) is taken as exactly
+    // the identity: B = I, R = I, full rank
+    double dev = 0.0;
+    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x)
+      dev = fmax(dev, fabs(Gg[e] - ((e / n) == (e % n) ? 1.0 : 0.0)));
+    for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
+    __syncthreads();
+    double m = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) m = fmax(m, red[w]);
+    if (m <= skip_tol) {
+      double* B = Bbase + pr * sq;
+      double* Rp = Rbase + pr * sq;
+      for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) {
+        const double v = ((e / n) == (e % n)) ? 1.0 : 0.0;
+        B[e] = v;
+        Rp[e] = v;
+      }
+      if (threadIdx.x == 0) rank_out[pr] = n;
+      return;
+    }
+    __syncthreads();
+  }
   if ((long)n * n <= lds_elems) {
     for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) sh[e] = Gg[e];
     chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
