@@ -142,6 +142,9 @@ def main():
                     help="steps timed for the MFMA utilisation of the product GEMMs")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue the step kernel by kernel instead of replaying a HIP graph")
+    ap.add_argument("--predictor-steps", type=int, default=3,
+                    help="steps timed with the rank-predicted randomized truncation "
+                         "(0 = skip; FP32/BF16 workloads)")
     ap.add_argument("--roofline-kernel", default="cholesky",
                     choices=["jacobi", "householder", "prodgemm", "cholesky"])
     args = ap.parse_args()
@@ -224,6 +227,29 @@ def main():
         gms = e0.elapsed_time(e1) / args.steps
         out["config"]["hip_graph_steps_per_s"] = 1000.0 / gms
     sim.close()
+    if args.predictor_steps > 0 and case.precision != "fp64":
+        # the same workload with the rank predictor on: two steps to seed the
+        # predictions, then timed steps; acceptance counts are totals
+        simp = L.Simulation(case, hip_stream=stream.cuda_stream, rank_predictor=1)
+        for _ in range(2):
+            simp.step(1)
+        torch.cuda.synchronize()
+        o0 = simp.observables()
+        e0.record(stream)
+        for _ in range(args.predictor_steps):
+            simp.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pms = e0.elapsed_time(e1) / args.predictor_steps
+        o1 = simp.observables()
+        att = o1.rs_attempted - o0.rs_attempted
+        out["config"]["rank_predictor"] = {
+            "steps_per_s": 1000.0 / pms, "speedup": ms / pms,
+            "sketches_per_step": att / args.predictor_steps,
+            "accepted_frac": (o1.rs_accepted - o0.rs_accepted) / att if att else 0.0,
+            "max_bond": o1.max_bond}
+        simp.close()
+        progress(f"rank predictor: {pms:.1f} ms/step")
     if args.fp64_steps > 0 and case.precision != "fp64":
         sim64 = L.Simulation(case, precision="fp64", hip_stream=stream.cuda_stream)
         sim64.step(1)

@@ -88,7 +88,12 @@ typedef struct {
   int axis_open[3]; /* 0 = periodic (cyclic shift), 1 = open (non-cyclic)  */
   int face_bc[6];   /* faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi            */
   double face_val[6][3]; /* velocity faces: u_b; pressure faces: {rho_b,0,0} */
-  unsigned long long seed; /* reserved for randomized sketches            */
+  unsigned long long seed; /* draws the Gaussian test matrix of the sketches */
+  int rank_predictor;  /* 1: truncations are first tried on a randomized
+                          sketch sized by the rank the same truncation chose
+                          in the previous step, with exact-error acceptance
+                          and full fallback (FP32/BF16 only); 0: off        */
+  int rank_oversample; /* sketch width = predicted rank + this (>= 1)       */
 } mps_lbm_config;
 
 typedef struct {
@@ -111,10 +116,13 @@ typedef struct {
   int nonfinite;           /* 1 if a NaN/Inf was seen in the state           */
   double jacobi_sweeps;    /* mean Jacobi sweeps per truncation problem (total) */
   int lds_bytes;           /* LDS per workgroup the factorisation kernels use */
+  long long rs_attempted;  /* truncations tried on a randomized sketch (total) */
+  long long rs_accepted;   /* of those, accepted without fallback (total)    */
 } mps_lbm_obs;
 
 /* Fill *cfg with defaults: D3Q19, FP64, TAYLOR2, 2 sweeps, tol 1e-10,
-   tol_mask 1e-12, tau 0.8, periodic, no force, chi_max 16. */
+   tol_mask 1e-12, tau 0.8, periodic, no force, chi_max 16, no rank
+   predictor (oversampling 16). */
 void mps_lbm_default_config(mps_lbm_config* cfg);
 
 /*

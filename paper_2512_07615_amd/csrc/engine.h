@@ -14,6 +14,7 @@
 
 #include "linalg.h"
 #include "mpsops.h"
+#include "rsvd.h"
 
 namespace mpslbm {
 
@@ -646,12 +647,14 @@ template <typename T>
 struct FnEigTrunc {
   MpsList<T> L; int k; double* Rp; long sq; const int* crank; double* US; double* Ut; long sus;
   const double* delta2; double* disc; int chi; int* fail;
+  const int* s0 = nullptr;    // bond sizes before truncation (randomized path on)
+  const int* skip = nullptr;  // problems already truncated by the randomized path
   __device__ EigProb get(int i) const {
     EigProb p;
     p.A = Rp + i * sq;  // R P^T (c x s, row-major) read as its transpose
-    p.s = L.p[i]->r[k];
+    p.s = s0 ? s0[i] : L.p[i]->r[k];
     p.c = crank[i];
-    p.valid = 1;
+    p.valid = (skip && skip[i]) ? 0 : 1;
     p.delta2 = delta2[i];
     p.chi = chi;
     p.rank_out = &L.p[i]->r[k];
@@ -837,6 +840,83 @@ class Engine {
   int pbatch = 1;
   int sweeps = 2;
   long roundings = 0, products = 0;
+  // rank-predicted randomized truncation (FP32/BF16): predictions are the
+  // ranks chosen in the previous step by the same rounding call, problem
+  // slot and bond (the step's schedule is fixed)
+  static constexpr int RS_CALLS = 1024;
+  bool rsvd = false;
+  int rs_over = 16;
+  int rs_call = 0;
+  int* rs_pred = nullptr;   // [RS_CALLS][MAXN + 1][MAXB]
+  int* rs_dims = nullptr;
+  EigProb* rs_ep = nullptr;
+  RsWork rw;
+  void enable_rsvd(int oversample, unsigned long long seed) {
+    if (rs_pred) return;
+    rsvd = true;
+    rs_over = oversample > 0 ? oversample : 16;
+    const long sq = cw.sq;
+    rw.sq = sq;
+    double** mats[] = {&rw.Y, &rw.T, &rw.B, &rw.R, &rw.B2, &rw.R2,
+                       &rw.Q, &rw.Q2, &rw.W, &rw.USt, &rw.Utt};
+    for (double** m : mats) *m = (double*)dalloc(8 * sq * MAXB);
+    // one Gaussian test matrix, drawn once from the seed and shared by all
+    // problems and calls: read as c x l with leading dimension l, any
+    // prefix of it is an i.i.d. Gaussian matrix of that shape
+    rw.som = (long)PHYS * sq;
+    rw.Om = (double*)dalloc(8 * rw.som);
+    hipLaunchKernelGGL(k_gauss<double>, dim3((unsigned)std::min<long>(1024, (rw.som + 255) / 256)),
+                       dim3(256), 0, st, rw.Om, rw.som,
+                       (uint64_t)(0x9E3779B97F4A7C15ull ^ (uint64_t)seed));
+    int** ints[] = {&rw.s0, &rw.ell, &rw.rank1, &rw.rank2, &rw.rankT, &rw.rsel, &rw.acc};
+    for (int** v : ints) *v = (int*)dalloc(4 * MAXB);
+    rw.tries = (int*)dalloc(4 * 4);
+    rw.budget = (double*)dalloc(8 * MAXB);
+    rw.disc = (double*)dalloc(8 * MAXB);
+    rw.trG = (double*)dalloc(8 * MAXB);
+    rs_dims = (int*)dalloc(4 * MAXB);
+    rs_ep = (EigProb*)dalloc(sizeof(EigProb) * MAXB);
+    rs_pred = (int*)dalloc(4L * RS_CALLS * (MAXN + 1) * MAXB);
+    HIP_OK(hipMemset(rs_pred, 0xFF, 4L * RS_CALLS * (MAXN + 1) * MAXB));  // -1: no prediction
+    HIP_OK(hipMemset(rw.tries, 0, 16));
+  }
+
+  // randomized attempt at bond k of one rounding call (see rsvd.h)
+  void rs_attempt(MpsList<T> L, int k, int cnt, int* predk, int scap, int chi_cap) {
+    const long sq = rw.sq;
+    const int lds = lds_elems * 8;
+    hipLaunchKernelGGL(k_rs_plan<T>, dim3(cnt), dim3(256), 0, st, L, k, (const int*)predk, rs_over,
+                       (const double*)cw.G, rw, cnt);
+    typedef double D;
+    launch_gemm<T, D, D, D>(FRsMOm<T>{L, k, rw}, cnt, scap, scap, 1, st);
+    launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Y, rw.T, rw.ell, sq}, cnt, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rw.ell, 1, rw.T, sq,
+                       rw.B, rw.R, rw.rank1, eps_rank, lds_elems, cnt, 1, (double*)nullptr, 0.0);
+    launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Y, rw.B, rw.Q, rw.ell, rw.rank1, sq}, cnt, scap,
+                            scap, 1, st);
+    launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Q, rw.T, rw.rank1, sq}, cnt, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rw.rank1, 1, rw.T,
+                       sq, rw.B2, rw.R2, rw.rank2, 1e-28, lds_elems, cnt, 1, (double*)nullptr,
+                       cq_skip);
+    launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Q, rw.B2, rw.Q2, rw.rank1, rw.rank2, sq}, cnt, scap,
+                            scap, 1, st);
+    launch_gemm<D, D, D, D>(FRsGQ<T>{L, k, cw.G, rw}, cnt, scap, scap, 1, st);
+    launch_gemm<D, D, D, D>(FRsQtW<T>{L, k, rw}, cnt, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_rs_budget, dim3(cnt), dim3(256), 0, st, (const double*)rdelta, rw, cnt);
+    hipLaunchKernelGGL(k_rs_dims_T, dim3(1), dim3(64), 0, st, rw, rs_dims, cnt);
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rs_dims, 1, rw.T, sq,
+                       rw.B, rw.R, rw.rankT, eps_rank, lds_elems, cnt, 0, (double*)nullptr, 0.0);
+    hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st, FnRsEig{rw, chi_cap, istats},
+                       rs_ep, cnt);
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024), lds, st,
+                       (const EigProb*)rs_ep, lds_elems, 40, (double*)nullptr);
+    hipLaunchKernelGGL(k_rs_accept<T>, dim3(1), dim3(64), 0, st, L, k, (const double*)rdelta,
+                       chi_cap, rw, rdisc, cnt);
+    launch_gemm<D, D, D, D>(FRsUS{rw, svdUS, sus}, cnt, scap, scap, 1, st);
+    launch_gemm<D, D, D, D>(FRsUt{rw, svdWk, sus}, cnt, scap, scap, 1, st);
+    hipLaunchKernelGGL(k_rs_dims_full<T>, dim3(1), dim3(64), 0, st, L, k, rw, cq_n, cnt);
+    HIP_OK(hipGetLastError());
+  }
   // timing of one kernel class: HIP events around each of its launches
   int tkind = 0;
   std::vector<hipEvent_t> evs;
@@ -1144,10 +1224,16 @@ class Engine {
     }
     hipLaunchKernelGGL(k_round_threshold<T>, dim3(cnt), blk, 0, st, L, tol_r, rdelta, rnorm, cnt);
     hipLaunchKernelGGL(k_fill_f64, dim3(3), dim3(256), 0, st, rdisc, 0.0, (long)MAXB * (MAXN + 1));
+    const int call = rs_call++;
+    const bool rs_now = fast && rsvd && call < RS_CALLS;
     for (int k = n - 1; k >= 1 && fast; --k) {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
+      int* predk = rs_now ? rs_pred + ((long)call * (MAXN + 1) + k) * MAXB : nullptr;
       launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
-      hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
+      if (rs_now)
+        rs_attempt(L, k, cnt, predk, scap, chi_cap);
+      else
+        hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
       tbegin(4);
       hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
                          (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
@@ -1155,7 +1241,9 @@ class Engine {
       tend(4);
       hipLaunchKernelGGL(k_eig_prep<FnEigTrunc<T>>, dim3(1), dim3(64), 0, st,
                          FnEigTrunc<T>{L, k, cw.R1, cw.sq, (const int*)cw.rank, svdUS, svdWk,
-                                       sus, rdelta, rdisc, chi_cap, istats},
+                                       sus, rdelta, rdisc, chi_cap, istats,
+                                       rs_now ? (const int*)rw.s0 : nullptr,
+                                       rs_now ? (const int*)rw.acc : nullptr},
                          ep, cnt);
       tbegin(1);
       hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024),
@@ -1169,6 +1257,7 @@ class Engine {
                          qslot, k);
       hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp,
                          maxcore, k - 1);
+      if (rs_now) hipLaunchKernelGGL(k_rs_store<T>, dim3(1), dim3(64), 0, st, L, k, predk, cnt);
     }
     for (int k = n - 1; k >= 1 && !fast; --k) {
       int mcap = PHYS * capb[k + 1], scap = capb[k];

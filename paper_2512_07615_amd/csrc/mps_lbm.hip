@@ -98,6 +98,7 @@ struct SimT : Sim {
     E.sweeps = c.sweeps;
     E.bf16_products = (c.precision == MPS_LBM_BF16);
     E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
+    if (c.rank_predictor) E.enable_rsvd(c.rank_oversample, c.seed);
     rho0 = (double*)E.dalloc(8 * (D + 8));
     nfl = (double*)E.dalloc(8 * (D + 8));
     scratch = (double*)E.dalloc(8 * (19 * D + 64));
@@ -214,6 +215,7 @@ struct SimT : Sim {
   // ---------------------------------------------------------------- step
   void step_once() {
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, E.stats, 0.0, 1L);
+    E.rs_call = 0;
     E.roundings = 0;
     E.products = 0;
     static const int PI[6][2] = {{0, 0}, {1, 1}, {2, 2}, {0, 1}, {0, 2}, {1, 2}};
@@ -687,6 +689,12 @@ struct SimT : Sim {
     o->nonfinite = ist[1];
     o->jacobi_sweeps = ist[3] > 0 ? (double)ist[2] / ist[3] : 0.0;
     o->lds_bytes = E.lds_elems * 8;
+    if (E.rs_pred) {
+      int t[2] = {0, 0};
+      HIP_OK(hipMemcpy(t, E.rw.tries, 8, hipMemcpyDeviceToHost));
+      o->rs_attempted = t[0];
+      o->rs_accepted = t[1];
+    }
   }
 };
 
@@ -713,6 +721,8 @@ void mps_lbm_default_config(mps_lbm_config* c) {
   c->precision = MPS_LBM_FP64;
   c->sweeps = 2;
   c->seed = 2512;
+  c->rank_predictor = 0;
+  c->rank_oversample = 16;
 }
 
 static int validate(const mps_lbm_config* c) {
@@ -731,6 +741,12 @@ static int validate(const mps_lbm_config* c) {
       c->precision != MPS_LBM_BF16)
     return fail(MPS_LBM_EINVAL, "unknown precision");
   if (c->sweeps < 1) return fail(MPS_LBM_EINVAL, "sweeps < 1");
+  if (c->rank_predictor != 0 && c->rank_predictor != 1)
+    return fail(MPS_LBM_EINVAL, "rank_predictor must be 0 or 1");
+  if (c->rank_predictor && c->rank_oversample < 1)
+    return fail(MPS_LBM_EINVAL, "rank_oversample < 1");
+  if (c->rank_predictor && c->precision == MPS_LBM_FP64)
+    return fail(MPS_LBM_EUNSUPPORTED, "the rank predictor runs with the FP32 and BF16 policies");
   for (int a = 0; a < 3; ++a) {
     if (c->axis_open[a] != 0 && c->axis_open[a] != 1) return fail(MPS_LBM_EINVAL, "axis_open");
     for (int s = 0; s < 2; ++s) {
@@ -804,7 +820,8 @@ int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* cons
     const mps_lbm_config& b = cfgs[d];
     if (a.n != b.n || a.chi_max != b.chi_max || a.precision != b.precision ||
         a.tol != b.tol || a.sweeps != b.sweeps || a.inv_rho_mode != b.inv_rho_mode ||
-        a.inv_rho_iters != b.inv_rho_iters)
+        a.inv_rho_iters != b.inv_rho_iters || a.rank_predictor != b.rank_predictor ||
+        a.rank_oversample != b.rank_oversample)
       return fail(MPS_LBM_EINVAL,
                   "batched domains must share n, chi_max, precision, tol, sweeps and the "
                   "inverse-density mode");

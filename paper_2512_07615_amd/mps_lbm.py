@@ -43,7 +43,7 @@ class Config(C.Structure):
         ("g", C.c_double * 3), ("inv_rho_mode", C.c_int), ("inv_rho_iters", C.c_int),
         ("precision", C.c_int), ("sweeps", C.c_int), ("axis_open", C.c_int * 3),
         ("face_bc", C.c_int * 6), ("face_val", (C.c_double * 3) * 6),
-        ("seed", C.c_ulonglong),
+        ("seed", C.c_ulonglong), ("rank_predictor", C.c_int), ("rank_oversample", C.c_int),
     ]
 
 
@@ -56,6 +56,7 @@ class Obs(C.Structure):
         ("mask_trunc_err", C.c_double), ("roundings", C.c_longlong),
         ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
         ("jacobi_sweeps", C.c_double), ("lds_bytes", C.c_int),
+        ("rs_attempted", C.c_longlong), ("rs_accepted", C.c_longlong),
     ]
 
 
@@ -254,7 +255,8 @@ def mps_lbm_destroy(h):
 
 
 def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_TAYLOR2,
-                     inv_iters: int = 2, seed: int = 2512) -> Config:
+                     inv_iters: int = 2, seed: int = 2512, rank_predictor: int = 0,
+                     rank_oversample: int = 16) -> Config:
     """Config from a workloads.Case."""
     c = mps_lbm_default_config()
     c.n = case.n
@@ -276,6 +278,8 @@ def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_
     c.inv_rho_mode = inv_mode
     c.inv_rho_iters = inv_iters
     c.seed = seed
+    c.rank_predictor = rank_predictor
+    c.rank_oversample = rank_oversample
     return c
 
 

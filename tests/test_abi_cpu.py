@@ -45,7 +45,8 @@ def test_config_struct_layout_matches_header():
     c = L.Config
     assert c.n.offset == 0
     assert c.tol.offset % 8 == 0
-    assert C.sizeof(c) == c.seed.offset + 8
+    assert c.rank_predictor.offset == c.seed.offset + 8
+    assert C.sizeof(c) == c.rank_oversample.offset + 4
 
 
 def test_default_config_values():
@@ -58,7 +59,7 @@ def test_default_config_values():
 @pytest.mark.parametrize("field,value,code", [
     ("tau", 0.5, -1), ("tau", 0.3, -1), ("n", 1, -1), ("n", 11, -1), ("chi_max", 0, -1),
     ("lattice", 15, -1), ("precision", 7, -1), ("inv_rho_mode", 9, -1), ("sweeps", 0, -1),
-    ("chi_max", 4096, -5),
+    ("chi_max", 4096, -5), ("rank_predictor", 2, -1), ("rank_predictor", 1, -5),
 ])
 def test_invalid_config_rejected_before_device_use(field, value, code):
     L = lib()

@@ -249,3 +249,52 @@ def test_bf16_contraction_policy(which):
     print(which, "bf16 vs dense", rel(gb, d.f), "fp32 vs dense", rel(gf, d.f), flush=True)
     assert rel(gb, d.f) < 1e-2
     assert rel(gf, d.f) < 5e-5
+
+
+def test_rank_predictor_randomized_truncation():
+    """Rank-predicted randomized truncation (FP32 policy) on a
+    tolerance-limited 32^3 flow: sketches are attempted from the second step
+    on and some are accepted; every accepted truncation meets the same
+    tolerance rule with its exact discarded weight, so the populations stay
+    within a few tolerances of the run without the predictor."""
+    L = lib()
+    case = _case_with_flow(WL.case_channel(n=5, chi=64, tol=1e-5), seed=3)
+    on = L.Simulation(case, precision="fp32", rank_predictor=1)
+    off = L.Simulation(case, precision="fp32")
+    for _ in range(3):
+        on.step(1)
+        off.step(1)
+    a, b = on.dense(L.POPS), off.dense(L.POPS)
+    o = on.observables()
+    on.close()
+    off.close()
+    d = float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+    print("attempted", o.rs_attempted, "accepted", o.rs_accepted, "rel L2 on/off", d, flush=True)
+    assert o.rs_attempted > 0 and o.rs_accepted > 0
+    assert d < 50 * case.tol
+
+
+def test_rank_predictor_cap_bound():
+    """Bonds held at chi (porous 32^3, chi 16): sketches of width 16 + 8 are
+    accepted only where their discarded weight is provably within 5% of the
+    optimal rank-chi truncation's, so the error against the untruncated
+    dense oracle stays that of the run without the predictor."""
+    L = lib()
+    case = _case_with_flow(WL.case_porous(n=5, chi=16, tol=1e-6), seed=3)
+    on = L.Simulation(case, precision="fp32", rank_predictor=1, rank_oversample=8)
+    off = L.Simulation(case, precision="fp32")
+    d = DenseLBM(case)
+    for _ in range(3):
+        on.step(1)
+        off.step(1)
+        d.step()
+    a, b = on.dense(L.POPS), off.dense(L.POPS)
+    o = on.observables()
+    on.close()
+    off.close()
+    e_on = float(np.sqrt(((a - d.f) ** 2).sum() / (d.f ** 2).sum()))
+    e_off = float(np.sqrt(((b - d.f) ** 2).sum() / (d.f ** 2).sum()))
+    print("attempted", o.rs_attempted, "accepted", o.rs_accepted, "error vs dense: on", e_on,
+          "off", e_off, flush=True)
+    assert o.rs_attempted > 0
+    assert e_on <= 1.5 * e_off + 1e-6
