@@ -77,6 +77,27 @@ __device__ inline float wave_sum(float v) {
 }
 
 // Block-wide sum for a 256-thread workgroup; `red` has >= 4 entries.
+// Block-wide copy of cnt doubles.  Each thread issues eight loads before
+// its stores, so that the latencies of global loads overlap instead of
+// adding up one iteration at a time.
+__device__ __forceinline__ void block_copy(double* dst, const double* src, long cnt) {
+  constexpr int U = 8;
+  const long st = blockDim.x;
+  for (long e0 = threadIdx.x; e0 < cnt; e0 += U * st) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = e0 + u * st;
+      v[u] = e < cnt ? src[e] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const long e = e0 + u * st;
+      if (e < cnt) dst[e] = v[u];
+    }
+  }
+}
+
 __device__ inline double block_sum(double v, double* red) {
   v = wave_sum(v);
   int lane = threadIdx.x & 63, w = threadIdx.x >> 6;

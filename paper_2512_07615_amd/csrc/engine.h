@@ -846,6 +846,10 @@ class Engine {
   static constexpr int RS_CALLS = 1024;
   bool rsvd = false;
   int rs_over = 16;
+  // Jacobi of the FP32 truncation: column pairs count as orthogonal at a
+  // relative 1e-12, four orders below FP32 rounding (the eigenvalues are then
+  // exact to about 1e-24 relative, the vectors orthonormal to 1e-12)
+  double eig_orth_tol = 1e-12;
   int rs_call = 0;
   int* rs_pred = nullptr;   // [RS_CALLS][MAXN + 1][MAXB]
   int* rs_dims = nullptr;
@@ -890,12 +894,12 @@ class Engine {
     typedef double D;
     launch_gemm<T, D, D, D>(FRsMOm<T>{L, k, rw}, cnt, scap, scap, 1, st);
     launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Y, rw.T, rw.ell, sq}, cnt, scap, scap, 1, st);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rw.ell, 1, rw.T, sq,
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rw.ell, 1, rw.T, sq,
                        rw.B, rw.R, rw.rank1, eps_rank, lds_elems, cnt, 1, (double*)nullptr, 0.0);
     launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Y, rw.B, rw.Q, rw.ell, rw.rank1, sq}, cnt, scap,
                             scap, 1, st);
     launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Q, rw.T, rw.rank1, sq}, cnt, scap, scap, 1, st);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rw.rank1, 1, rw.T,
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rw.rank1, 1, rw.T,
                        sq, rw.B2, rw.R2, rw.rank2, 1e-28, lds_elems, cnt, 1, (double*)nullptr,
                        cq_skip);
     launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Q, rw.B2, rw.Q2, rw.rank1, rw.rank2, sq}, cnt, scap,
@@ -904,12 +908,12 @@ class Engine {
     launch_gemm<D, D, D, D>(FRsQtW<T>{L, k, rw}, cnt, scap, scap, 1, st);
     hipLaunchKernelGGL(k_rs_budget, dim3(cnt), dim3(256), 0, st, (const double*)rdelta, rw, cnt);
     hipLaunchKernelGGL(k_rs_dims_T, dim3(1), dim3(64), 0, st, rw, rs_dims, cnt);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), lds, st, (const int*)rs_dims, 1, rw.T, sq,
+    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rs_dims, 1, rw.T, sq,
                        rw.B, rw.R, rw.rankT, eps_rank, lds_elems, cnt, 0, (double*)nullptr, 0.0);
     hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st, FnRsEig{rw, chi_cap, istats},
                        rs_ep, cnt);
     hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024), lds, st,
-                       (const EigProb*)rs_ep, lds_elems, 40, (double*)nullptr);
+                       (const EigProb*)rs_ep, lds_elems, 40, (double*)nullptr, eig_orth_tol);
     hipLaunchKernelGGL(k_rs_accept<T>, dim3(1), dim3(64), 0, st, L, k, (const double*)rdelta,
                        chi_cap, rw, rdisc, cnt);
     launch_gemm<D, D, D, D>(FRsUS{rw, svdUS, sus}, cnt, scap, scap, 1, st);
@@ -1173,7 +1177,7 @@ class Engine {
     hipLaunchKernelGGL(k_cq_dims<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp, cq_n, nprob);
     launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st);
     tbegin(4);
-    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)cq_n, 1, w.G,
+    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)cq_n, 1, w.G,
                        w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4));
     tend(4);
     hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 0);
@@ -1182,7 +1186,7 @@ class Engine {
     hipLaunchKernelGGL(k_cq_dims2<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp,
                        (const int*)w.rank, cq_n + MAXB, nprob);
     tbegin(4);
-    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(256), lds, st, (const int*)(cq_n + MAXB), 1,
+    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)(cq_n + MAXB), 1,
                        w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob, 1,
                        kf(4), cq_skip);
     tend(4);
@@ -1235,7 +1239,7 @@ class Engine {
       else
         hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
       tbegin(4);
-      hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
+      hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), (size_t)lds_elems * 8, st,
                          (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
                          lds_elems, cnt, 0, kf(4));
       tend(4);
@@ -1248,7 +1252,7 @@ class Engine {
       tbegin(1);
       hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024),
                          (size_t)lds_elems * 8, st,
-                         (const EigProb*)ep, lds_elems, 40, kf(1));
+                         (const EigProb*)ep, lds_elems, 40, kf(1), eig_orth_tol);
       tend(1);
       launch_gemm<double, T, T, double>(FUtM<T>{L, ep, qtmp, qslot, k}, cnt, scap, ccap, 1, st);
       launch_gemm<T, double, T, double>(FCoreUS2<T>{L, ep, ctmp, maxcore, k}, cnt,

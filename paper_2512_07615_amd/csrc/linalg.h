@@ -153,7 +153,7 @@ __global__ __launch_bounds__(256) void k_chol_inv(const QrProb<T>* qp, QrWork w,
   double* Ri = w.Rinv + blockIdx.x * w.sq;
   double* G = (s * s <= lds_elems) ? sh : Gg;
   if (G != Gg)
-    for (int e = tid; e < s * s; e += blockDim.x) G[e] = Gg[e];
+    block_copy(G, Gg, (long)s * s);
   __syncthreads();
   double tr = 0.0;
   for (int e = tid; e < s; e += blockDim.x) tr += G[e * s + e];
@@ -424,6 +424,8 @@ struct CholWork {
 // the back substitution in its "lower" part.
 constexpr int CPB = 16;     // panel width of the blocked pivoted Cholesky
 constexpr int CPB_MAXN = 128;  // largest order factored by the blocked variant
+constexpr int LPS = CPB + 1;   // row stride of the panel: odd, so that lanes
+                               // reading one column hit distinct LDS banks
 
 // Blocked pivoted Cholesky for n <= CPB_MAXN with G in LDS.  Wave 0 factors
 // a panel of CPB columns (left-looking inside the panel, pivots chosen on
@@ -455,9 +457,9 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
         if (!(best > thr) || !(best > 0.0)) break;  // the same decision in every lane
         if (bi != j) {
           if (lane < k) {
-            const double t = Lp[j * CPB + lane];
-            Lp[j * CPB + lane] = Lp[bi * CPB + lane];
-            Lp[bi * CPB + lane] = t;
+            const double t = Lp[j * LPS + lane];
+            Lp[j * LPS + lane] = Lp[bi * LPS + lane];
+            Lp[bi * LPS + lane] = t;
           }
           if (lane == 0) {
             const int t = perm[j]; perm[j] = perm[bi]; perm[bi] = t;
@@ -469,13 +471,13 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
         const int pj = perm[j];
         const double r = sqrt(best), invr = 1.0 / r;
         for (int i = j + 1 + lane; i < n; i += 64) {
-          double acc = G[(long)perm[i] * n + pj];
-          for (int q = 0; q < k; ++q) acc -= Lp[i * CPB + q] * Lp[j * CPB + q];
+          double acc = G[(long)pj * n + perm[i]];  // row pj: G is kept symmetric
+          for (int q = 0; q < k; ++q) acc -= Lp[i * LPS + q] * Lp[j * LPS + q];
           const double l = acc * invr;
-          Lp[i * CPB + k] = l;
+          Lp[i * LPS + k] = l;
           dg[i] -= l * l;
         }
-        if (lane == 0) Lp[j * CPB + k] = r;
+        if (lane == 0) Lp[j * LPS + k] = r;
         __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
         __builtin_amdgcn_wave_barrier();
       }
@@ -489,7 +491,7 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
     // rows of R for the finished panel columns
     for (int k = 0; k < kd; ++k) {
       const int j = j0 + k, pj = perm[j];
-      for (int c = j + tid; c < n; c += blockDim.x) G[(long)pj * n + perm[c]] = Lp[c * CPB + k];
+      for (int c = j + tid; c < n; c += blockDim.x) G[(long)pj * n + perm[c]] = Lp[c * LPS + k];
     }
     if (kd < bw) {
       __syncthreads();
@@ -501,12 +503,12 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
       const int pa = perm[a];
       double la[CPB];
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) la[q] = q < bw ? Lp[a * CPB + q] : 0.0;
+      for (int q = 0; q < CPB; ++q) la[q] = q < bw ? Lp[a * LPS + q] : 0.0;
       double* ga = G + (long)pa * n;
       for (int b = t0 + lane; b < n; b += 64) {
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < CPB; ++q) acc += la[q] * Lp[b * CPB + q];
+        for (int q = 0; q < CPB; ++q) acc += la[q] * Lp[b * LPS + q];
         ga[perm[b]] -= acc;
       }
     }
@@ -603,40 +605,122 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
         (rho > 0 && c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
   }
   if (!want_b) return;
-  // B = P[:, :rho] R11^{-1}.  R11 is first brought into position order
-  // (staged through B), stored with leading dimension rho; column c of the
-  // inverse is then found by back substitution, its entries x_k (k < c)
-  // kept in the unused lower part (row c) and x_c in xd[c].
-  for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
-    const int r = (int)(e / rho), c = (int)(e % rho);
-    B[e] = (c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
+  // B = P[:, :rho] R11^{-1}.  R11 is brought into position order (staged
+  // through B) and stored skewed, entry (r, c) at r rho + (c + r) mod rho, so
+  // that lanes walking a row or a column hit distinct LDS banks.  The inverse
+  // X (upper triangular) keeps its strict upper part X[i][c] in the unused
+  // lower slot (c, i) and its diagonal 1 / R[c][c] in xd[c].  It is formed
+  // by recursive doubling: every wave inverts diagonal blocks of 16 (right-
+  // looking, one wave-local step per row); then, level by level with blocks
+  // of b = 16, 32, 64, ..., the coupling block of each pair of inverted
+  // diagonal blocks follows from X12 = -X11 R12 X22.  U = X11 R12 is staged
+  // through B and then replaces R12, which no later level reads.
+  auto sk = [rho](int v) { return v < rho ? v : v - rho; };
+  // orders up to 128 with 1024 threads stage through registers (at most 16
+  // entries of R11 and 4 of each U per thread); larger ones through B
+  const bool regs = rho <= 128 && blockDim.x == 1024;
+  if (regs) {
+    double v[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 1024;
+      if (e < rho * rho) {
+        const int r = e / rho, c = e - r * rho;
+        v[u] = (c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int e = tid + u * 1024;
+      if (e < rho * rho) {
+        const int r = e / rho, c = e - r * rho;
+        G[(long)r * rho + sk(c + r)] = v[u];
+        if (c == r) xd[c] = 1.0 / v[u];
+      }
+    }
+  } else {
+    for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
+      const int r = (int)(e / rho), c = (int)(e % rho);
+      B[e] = (c >= r) ? G[(long)perm[r] * n + perm[c]] : 0.0;
+    }
+    __syncthreads();
+    for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
+      const int r = (int)(e / rho), c = (int)(e % rho);
+      G[(long)r * rho + sk(c + r)] = (c >= r) ? B[e] : 0.0;
+    }
+    for (int c = tid; c < rho; c += blockDim.x) xd[c] = 1.0 / B[(long)c * rho + c];
   }
   __syncthreads();
-  for (long e = tid; e < (long)rho * rho; e += blockDim.x) G[e] = B[e];
-  __syncthreads();
-  for (long e = tid; e < (long)n * rr; e += blockDim.x) B[e] = 0.0;
-  __syncthreads();
-  for (int c = tid; c < rho; c += blockDim.x) {
-    const double* Rc = G + (long)c * rho;  // row c: x_k at k < c
-    double* Xc = G + (long)c * rho;
-    const double xc = 1.0 / Rc[c];
-    xd[c] = xc;
-    for (int i = c - 1; i >= 0; --i) {
-      const double* Ri = G + (long)i * rho;
-      double acc = Ri[c] * xc;
-      for (int k = i + 1; k < c; ++k) acc += Ri[k] * Xc[k];
-      Xc[i] = -acc / Ri[i];
+  constexpr int IB = 16;
+  for (int p = wv * IB; p < rho; p += nw * IB) {
+    const int bs = rho - p < IB ? rho - p : IB;
+    for (int k = bs - 1; k >= 1; --k) {
+      // entries i < k <= c of the block: k (bs - k) <= 64, one per lane
+      if (lane < k * (bs - k)) {
+        const int i = p + lane % k, c = p + k + lane / k, kg = p + k;
+        const double xkc = (c == kg) ? xd[kg] : G[(long)c * rho + sk(kg + c)];
+        double a = G[(long)c * rho + sk(i + c)] + G[(long)i * rho + sk(kg + i)] * xkc;
+        if (i == kg - 1) a = -a * xd[kg - 1];
+        G[(long)c * rho + sk(i + c)] = a;
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
   }
   __syncthreads();
+  for (int b = IB; b < rho; b *= 2) {
+    // U = X11 R12 (rows [p, p+b), columns [p+b, p+b+bc)); at most rho b / 2
+    // entries, so at most 4 per thread when staged through registers
+    double u[4];
+    int q = 0;
+    for (int p = 0; p + b < rho; p += 2 * b) {
+      const int bc = rho - p - b < b ? rho - p - b : b;
+      for (int e = tid; e < b * bc; e += blockDim.x) {
+        const int ig = p + e / bc, c = p + b + e % bc;
+        double a = xd[ig] * G[(long)ig * rho + sk(c + ig)];
+        for (int t = ig + 1; t < p + b; ++t)
+          a += G[(long)t * rho + sk(ig + t)] * G[(long)t * rho + sk(c + t)];
+        if (!regs) B[(long)ig * rho + c] = a;
+        else if (q < 4) u[q++] = a;
+      }
+    }
+    __syncthreads();
+    q = 0;
+    for (int p = 0; p + b < rho; p += 2 * b) {
+      const int bc = rho - p - b < b ? rho - p - b : b;
+      for (int e = tid; e < b * bc; e += blockDim.x) {
+        const int ig = p + e / bc, c = p + b + e % bc;
+        if (!regs) G[(long)ig * rho + sk(c + ig)] = B[(long)ig * rho + c];
+        else if (q < 4) G[(long)ig * rho + sk(c + ig)] = u[q++];
+      }
+    }
+    __syncthreads();
+    // X12 = -U X22, into the lower slots (c, i)
+    for (int p = 0; p + b < rho; p += 2 * b) {
+      const int bc = rho - p - b < b ? rho - p - b : b;
+      for (int e = tid; e < b * bc; e += blockDim.x) {
+        const int ig = p + e / bc, c = p + b + e % bc;
+        double a = G[(long)ig * rho + sk(c + ig)] * xd[c];
+        for (int t = p + b; t < c; ++t)
+          a += G[(long)ig * rho + sk(t + ig)] * G[(long)c * rho + sk(t + c)];
+        G[(long)c * rho + sk(ig + c)] = -a;
+      }
+    }
+    __syncthreads();
+  }
+  for (long e = tid; e < (long)n * rr; e += blockDim.x) B[e] = 0.0;
+  __syncthreads();
   for (long e = tid; e < (long)rho * rho; e += blockDim.x) {
     const int c = (int)(e / rho), k = (int)(e % rho);
-    if (k < c) B[(long)perm[k] * rr + c] = G[(long)c * rho + k];
+    if (k < c) B[(long)perm[k] * rr + c] = G[(long)c * rho + sk(k + c)];
     else if (k == c) B[(long)perm[c] * rr + c] = xd[c];
   }
 }
 
-__global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
+constexpr int CHOL_THREADS = 1024;  // threads of k_chol_piv: 16 waves hide the
+                                    // LDS latency of the parallel phases
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
                                                   long sq, double* Bbase, double* Rbase,
                                                   int* rank_out, double eps_rank, int lds_elems,
                                                   int nprob, int want_b = 1,
@@ -644,13 +728,13 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
                                                   double skip_tol = 0.0) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
-  __shared__ double red[8];
-  __shared__ int ired[8];
+  __shared__ double red[16];
+  __shared__ int ired[16];
   __shared__ int rho_s;
   __shared__ double dmax0;
   __shared__ double dpiv;
   __shared__ double xd[1024];
-  __shared__ double Lp[CPB_MAXN * CPB];
+  __shared__ double Lp[CPB_MAXN * LPS];
   __shared__ int kdone;
   const int pr = blockIdx.x;
   if (pr >= nprob) return;
@@ -662,8 +746,17 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
     // Cholesky-QR after a well-conditioned first pass) is taken as exactly
     // the identity: B = I, R = I, full rank
     double dev = 0.0;
-    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x)
-      dev = fmax(dev, fabs(Gg[e] - ((e / n) == (e % n) ? 1.0 : 0.0)));
+    const long nn = (long)n * n, st = blockDim.x;
+    for (long e0 = threadIdx.x; e0 < nn; e0 += 8 * st) {
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = e0 + u * st < nn ? Gg[e0 + u * st] : 0.0;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const long e = e0 + u * st;
+        if (e < nn) dev = fmax(dev, fabs(v[u] - ((e / n) == (e % n) ? 1.0 : 0.0)));
+      }
+    }
     for (int o = 32; o > 0; o >>= 1) dev = fmax(dev, __shfl_xor(dev, o, 64));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = dev;
     __syncthreads();
@@ -683,7 +776,7 @@ __global__ __launch_bounds__(256) void k_chol_piv(const int* dims, int dim_strid
     __syncthreads();
   }
   if ((long)n * n <= lds_elems) {
-    for (long e = threadIdx.x; e < (long)n * n; e += blockDim.x) sh[e] = Gg[e];
+    block_copy(sh, Gg, (long)n * n);
     chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone);
   } else {
@@ -968,7 +1061,7 @@ __global__ void k_eig_prep(F f, EigProb* ep, int nprob) {
 // a pointer of known address space so that LDS is reached by ds_* ops).
 __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sweeps, double* flops,
                                          int* flag, int* nonfin, int* rsel, int* perm,
-                                         double* nrm, double* red) {
+                                         double* nrm, double* red, double orth_tol) {
   const int s = p.s, c = p.c, tid = threadIdx.x;
   const long sc = (long)s * c;
   double fro2 = 0.0;
@@ -976,8 +1069,8 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   fro2 = block_sum(fro2, red);
   const double eps = 2.220446049250313e-16;
   double work = 0.0;
-  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, eps * sqrt((double)(s > 1 ? s : 1)),
-                               eps * eps * fro2, work, flag);
+  const double tol = orth_tol > 0.0 ? orth_tol : eps * sqrt((double)(s > 1 ? s : 1));
+  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2, work, flag);
   if (tid == 0 && p.fail) {
     if (sw >= max_sweeps) atomicAdd(p.fail, 1);
     atomicAdd(p.fail + 2, sw);
@@ -1008,8 +1101,11 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   }
 }
 
+// orth_tol: relative orthogonality at which a column pair counts as
+// converged (<= 0: FP64 rounding, eps sqrt(s)).
 __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_elems,
-                                                     int max_sweeps, double* flops) {
+                                                     int max_sweeps, double* flops,
+                                                     double orth_tol) {
   extern __shared__ double sh[];
   __shared__ int flag, nonfin, rsel;
   __shared__ int perm[1024];
@@ -1024,11 +1120,11 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
   }
   const long sc = (long)s * c;
   if (sc <= lds_elems) {
-    for (long e = tid; e < sc; e += blockDim.x) sh[e] = p.A[e];
+    block_copy(sh, p.A, sc);
     __syncthreads();
-    eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
+    eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol);
   } else {
-    eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
+    eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol);
   }
 }
 
@@ -1124,10 +1220,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_svd(const SvdProb* sp, int lds_
   }
   const long mn = (long)m * n, nn = (long)n * n;
   if (mn + nn <= lds_elems) {
-    for (long e = tid; e < mn; e += blockDim.x) sh[e] = p.L[e];
+    block_copy(sh, p.L, mn);
     svd_body(p, sh, sh + mn, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
   } else if (mn <= lds_elems) {
-    for (long e = tid; e < mn; e += blockDim.x) sh[e] = p.L[e];
+    block_copy(sh, p.L, mn);
     svd_body(p, sh, p.W, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red);
   } else {
     for (long e = tid; e < mn; e += blockDim.x) p.Lw[e] = p.L[e];
