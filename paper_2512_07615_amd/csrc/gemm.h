@@ -7,7 +7,8 @@
 // the actual problem exit at once.
 //
 // Tiles are 64x64 per 256-thread workgroup (four waves, 32x32 each = 2x2
-// MFMA 16x16 blocks), K staged through LDS 16 at a time.  Operands are read
+// MFMA 16x16 blocks), K staged through LDS 64 at a time, the next slice
+// loaded into registers while the current one is multiplied.  Operands are read
 // through arbitrary element strides and converted to the accumulation type
 // Tacc on the way into LDS; Tacc = double uses v_mfma_f64_16x16x4f64,
 // Tacc = float uses v_mfma_f32_16x16x4f32.
@@ -64,7 +65,7 @@ template <> struct MfmaT<float> {
 };
 
 constexpr int GT = 64;   // tile edge
-constexpr int GK = 16;   // K step
+constexpr int GK = 64;   // K slice staged through LDS per step
 
 // BF16 operands for v_mfma_f32_16x16x16bf16_1k: lane l supplies
 // A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j = 0..3 (one
@@ -110,50 +111,73 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
   const bool a_k_contig = (d.sAk == 1);
   const bool b_n_contig = (d.sBn == 1);
+  // Software pipeline: the operands of the next K slice are loaded into
+  // registers while the MFMAs work on the slice in LDS, so global latency
+  // is paid once per GK = 64 columns of K rather than per instruction.
+  constexpr int LQ = GT * GK / 256;  // elements of each operand per thread
+  Tacc ra[LQ], rb[LQ];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < LQ; ++q) {
+      const int e = tid + 256 * q;
+      int mm, kk;
+      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
+      const int gm = m0 + mm, gk = k0 + kk;
+      ra[q] = (gm < d.M && gk < d.K) ? (Tacc)A[gm * d.sAm + gk * d.sAk] : (Tacc)0;
+      int nn, kb;
+      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
+      const int gn = n0 + nn, gk2 = k0 + kb;
+      rb[q] = (gn < d.N && gk2 < d.K) ? (Tacc)B[gk2 * d.sBk + gn * d.sBn] : (Tacc)0;
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < d.K; k0 += GK) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = tid + 256 * q;
+    for (int q = 0; q < LQ; ++q) {
+      const int e = tid + 256 * q;
       int mm, kk;
-      if (a_k_contig) { mm = e >> 4; kk = e & 15; } else { mm = e & 63; kk = e >> 6; }
-      int gm = m0 + mm, gk = k0 + kk;
-      Tacc v = 0;
-      if (gm < d.M && gk < d.K) v = (Tacc)A[gm * d.sAm + gk * d.sAk];
-      As[kk][mm] = v;
+      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
+      As[kk][mm] = ra[q];
       int nn, kb;
-      if (b_n_contig) { kb = e >> 6; nn = e & 63; } else { nn = e >> 4; kb = e & 15; }
-      int gn = n0 + nn, gk2 = k0 + kb;
-      Tacc u = 0;
-      if (gn < d.N && gk2 < d.K) u = (Tacc)B[gk2 * d.sBk + gn * d.sBn];
-      Bs[kb][nn] = u;
+      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
+      Bs[kb][nn] = rb[q];
     }
     __syncthreads();
+    if (k0 + GK < d.K) fetch(k0 + GK);
+    const int kvalid = d.K - k0;  // K columns of this slice that are not padding
     if constexpr (MODE == 1) {
-      bf4 a0, a1, b0, b1;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int kr = 4 * (lane >> 4) + j;
-        a0[j] = bf16_bits(As[kr][wm * 32 + (lane & 15)]);
-        a1[j] = bf16_bits(As[kr][wm * 32 + 16 + (lane & 15)]);
-        b0[j] = bf16_bits(Bs[kr][wn * 32 + (lane & 15)]);
-        b1[j] = bf16_bits(Bs[kr][wn * 32 + 16 + (lane & 15)]);
+      for (int ks = 0; ks < GK / 16; ++ks) {
+        if (ks * 16 < kvalid) {
+          bf4 a0, a1, b0, b1;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int kr = ks * 16 + 4 * (lane >> 4) + j;
+            a0[j] = bf16_bits(As[kr][wm * 32 + (lane & 15)]);
+            a1[j] = bf16_bits(As[kr][wm * 32 + 16 + (lane & 15)]);
+            b0[j] = bf16_bits(Bs[kr][wn * 32 + (lane & 15)]);
+            b1[j] = bf16_bits(Bs[kr][wn * 32 + 16 + (lane & 15)]);
+          }
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+        }
       }
-      acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-      acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-      acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-      acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
     } else {
 #pragma unroll
       for (int ks = 0; ks < GK / 4; ++ks) {
-        int kr = ks * 4 + (lane >> 4);
-        Tacc a0 = As[kr][wm * 32 + (lane & 15)];
-        Tacc a1 = As[kr][wm * 32 + 16 + (lane & 15)];
-        Tacc bb0 = Bs[kr][wn * 32 + (lane & 15)];
-        Tacc bb1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
-        acc[0][0] = MfmaT<Tacc>::op(a0, bb0, acc[0][0]);
-        acc[0][1] = MfmaT<Tacc>::op(a0, bb1, acc[0][1]);
-        acc[1][0] = MfmaT<Tacc>::op(a1, bb0, acc[1][0]);
-        acc[1][1] = MfmaT<Tacc>::op(a1, bb1, acc[1][1]);
+        if (ks * 4 < kvalid) {
+          int kr = ks * 4 + (lane >> 4);
+          Tacc a0 = As[kr][wm * 32 + (lane & 15)];
+          Tacc a1 = As[kr][wm * 32 + 16 + (lane & 15)];
+          Tacc bb0 = Bs[kr][wn * 32 + (lane & 15)];
+          Tacc bb1 = Bs[kr][wn * 32 + 16 + (lane & 15)];
+          acc[0][0] = MfmaT<Tacc>::op(a0, bb0, acc[0][0]);
+          acc[0][1] = MfmaT<Tacc>::op(a0, bb1, acc[0][1]);
+          acc[1][0] = MfmaT<Tacc>::op(a1, bb0, acc[1][0]);
+          acc[1][1] = MfmaT<Tacc>::op(a1, bb1, acc[1][1]);
+        }
       }
     }
     __syncthreads();
