@@ -1142,14 +1142,33 @@ class Engine {
   bool bf16_products = false;
   template <typename F>
   void pgemm(const F& f, int nprob, int mcap, int ncap, int bcap, hipStream_t s,
-             double* flops = nullptr) {
+             double* flops = nullptr, int kcap = 0) {
+    const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap);
     if constexpr (std::is_same<T, float>::value) {
       if (bf16_products) {
-        launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops);
+        launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops, ks);
         return;
       }
     }
-    launch_gemm<T, T, T, Tacc>(f, nprob, mcap, ncap, bcap, s, flops);
+    launch_gemm<T, T, T, Tacc>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+  }
+
+  // Split of K for contractions whose K capacity is long: one share per 256
+  // columns of K, at most 8; the partial tiles go to a workspace that grows
+  // on demand (the first, eager step reaches its peak before any capture).
+  double* kws = nullptr;
+  size_t kws_bytes = 0;
+  KSplit ksplit(int nprob, int mcap, int ncap, int bcap, int kcap) {
+    int sp = kcap / 256;
+    if (sp > 8) sp = 8;
+    if (sp < 2 || nprob <= 0 || mcap <= 0 || ncap <= 0 || bcap <= 0) return KSplit{nullptr, 1};
+    const size_t need = (size_t)nprob * bcap * ceil_div(mcap, GT) * ceil_div(ncap, GT) * sp *
+                        GT * GT * sizeof(double);
+    if (need > kws_bytes) {
+      kws = (double*)dalloc(need);
+      kws_bytes = need;
+    }
+    return KSplit{kws, sp};
   }
 
   // ------------------------------------------------------------ QR op
@@ -1175,14 +1194,16 @@ class Engine {
     size_t lds = (size_t)lds_elems * 8;
     CholWork w = cw;
     hipLaunchKernelGGL(k_cq_dims<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp, cq_n, nprob);
-    launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st);
+    launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st, nullptr,
+                                      ksplit(nprob, scap, scap, 1, mcap));
     tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)cq_n, 1, w.G,
                        w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4));
     tend(4);
     hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 0);
     launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
-    launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st);
+    launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st,
+                                                nullptr, ksplit(nprob, scap, scap, 1, mcap));
     hipLaunchKernelGGL(k_cq_dims2<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp,
                        (const int*)w.rank, cq_n + MAXB, nprob);
     tbegin(4);
@@ -1233,7 +1254,8 @@ class Engine {
     for (int k = n - 1; k >= 1 && fast; --k) {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
       int* predk = rs_now ? rs_pred + ((long)call * (MAXN + 1) + k) * MAXB : nullptr;
-      launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st);
+      launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st,
+                                        nullptr, ksplit(cnt, scap, scap, 1, ccap));
       if (rs_now)
         rs_attempt(L, k, cnt, predk, scap, chi_cap);
       else
@@ -1491,7 +1513,7 @@ class Engine {
     tend(3);
     tbegin(3);
     pgemm(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st,
-                               kf(3));
+                               kf(3), cpb[p + 1] * cpb[p + 1]);
     tend(3);
   }
 

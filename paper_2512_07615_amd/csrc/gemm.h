@@ -80,12 +80,23 @@ __device__ inline short bf16_bits(float f) {
 
 // MODE 0: MFMA in the accumulation type; MODE 1 (Tacc = float): operands
 // rounded to BF16, BF16 MFMA with FP32 accumulation.
+// Split K: with split > 1 each of `split` workgroups of a tile multiplies
+// one contiguous share of K (a multiple of GK) and stores its partial tile
+// in ws; k_gemm_reduce then sums the shares in a fixed order.
+struct KSplit {
+  double* ws;
+  int split;
+};
+
 template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
-__global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops) {
+__global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops,
+                                              KSplit ks) {
   typedef typename MfmaT<Tacc>::V V;
   __shared__ Tacc As[GK][GT + 1];
   __shared__ Tacc Bs[GK][GT + 1];
   long wg = blockIdx.x;
+  const int kseg = (int)(wg % ks.split);
+  wg /= ks.split;
   int tile = (int)(wg % tiles_cap);
   long rest = wg / tiles_cap;
   int b = (int)(rest % batch_cap);
@@ -96,7 +107,10 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   int tn = (d.N + GT - 1) / GT;
   int tm = (d.M + GT - 1) / GT;
   if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
-  if (flops && tile == 0 && threadIdx.x == 0) atomicAdd(flops, 2.0 * d.M * d.N * d.K);
+  if (flops && tile == 0 && kseg == 0 && threadIdx.x == 0) atomicAdd(flops, 2.0 * d.M * d.N * d.K);
+  // share of K: [kb, ke)
+  const int kc = ((d.K + ks.split - 1) / ks.split + GK - 1) / GK * GK;
+  const int kb = kseg * kc, ke = d.K < kb + kc ? d.K : kb + kc;
   int ti = tile / tn, tj = tile % tn;
   int b1 = b % d.nb1, b2 = b / d.nb1;
   const TA* A = d.A + b1 * d.bA1 + b2 * d.bA2;
@@ -123,15 +137,15 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       int mm, kk;
       if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
       const int gm = m0 + mm, gk = k0 + kk;
-      ra[q] = (gm < d.M && gk < d.K) ? (Tacc)A[gm * d.sAm + gk * d.sAk] : (Tacc)0;
+      ra[q] = (gm < d.M && gk < ke) ? (Tacc)A[gm * d.sAm + gk * d.sAk] : (Tacc)0;
       int nn, kb;
       if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
       const int gn = n0 + nn, gk2 = k0 + kb;
-      rb[q] = (gn < d.N && gk2 < d.K) ? (Tacc)B[gk2 * d.sBk + gn * d.sBn] : (Tacc)0;
+      rb[q] = (gn < d.N && gk2 < ke) ? (Tacc)B[gk2 * d.sBk + gn * d.sBn] : (Tacc)0;
     }
   };
-  fetch(0);
-  for (int k0 = 0; k0 < d.K; k0 += GK) {
+  if (kb < ke) fetch(kb);
+  for (int k0 = kb; k0 < ke; k0 += GK) {
 #pragma unroll
     for (int q = 0; q < LQ; ++q) {
       const int e = tid + 256 * q;
@@ -143,8 +157,8 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       Bs[kb][nn] = rb[q];
     }
     __syncthreads();
-    if (k0 + GK < d.K) fetch(k0 + GK);
-    const int kvalid = d.K - k0;  // K columns of this slice that are not padding
+    if (k0 + GK < ke) fetch(k0 + GK);
+    const int kvalid = ke - k0;  // K columns of this slice that are not padding
     if constexpr (MODE == 1) {
 #pragma unroll
       for (int ks = 0; ks < GK / 16; ++ks) {
@@ -182,6 +196,21 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
     }
     __syncthreads();
   }
+  if (ks.split > 1) {
+    double* W = ks.ws + ((((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split + kseg) *
+                            (GT * GT);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = wm * 32 + i * 16 + MfmaT<Tacc>::row(lane, v);
+          const int col = wn * 32 + j * 16 + (lane & 15);
+          W[row * GT + col] = (double)acc[i][j][v];
+        }
+    return;
+  }
   const double alpha = d.alpha, beta = d.beta;
 #pragma unroll
   for (int i = 0; i < 2; ++i)
@@ -200,16 +229,52 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       }
 }
 
-// Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps).
+// Sum of the split-K partial tiles in share order, then C = alpha sum + beta C.
+template <typename TA, typename TB, typename TC, typename F>
+__global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int batch_cap, KSplit ks) {
+  long wg = blockIdx.x;
+  int tile = (int)(wg % tiles_cap);
+  long rest = wg / tiles_cap;
+  int b = (int)(rest % batch_cap);
+  int prob = (int)(rest / batch_cap);
+  GemmDesc<TA, TB, TC> d = f.get(prob);
+  if (!d.valid) return;
+  if (b >= d.nb1 * d.nb2) return;
+  int tn = (d.N + GT - 1) / GT;
+  int tm = (d.M + GT - 1) / GT;
+  if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
+  int ti = tile / tn, tj = tile % tn;
+  int b1 = b % d.nb1, b2 = b / d.nb1;
+  TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
+  const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (GT * GT);
+  for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
+    const int row = ti * GT + e / GT, col = tj * GT + e % GT;
+    if (row >= d.M || col >= d.N) continue;
+    double sum = 0.0;
+    for (int q = 0; q < ks.split; ++q) sum += W[(long)q * (GT * GT) + e];
+    TC* p = C + row * d.sCm + col * d.sCn;
+    double val = d.alpha * sum;
+    if (d.beta != 0.0) val += d.beta * (double)(*p);
+    *p = (TC)val;
+  }
+}
+
+// Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps),
+// times ks.split when K is split (ks.ws then holds
+// nprob * batch_cap * tiles_cap * split tiles of GT x GT doubles).
 template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
 inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap,
-                        hipStream_t s, double* flops = nullptr) {
+                        hipStream_t s, double* flops = nullptr, KSplit ks = KSplit{nullptr, 1}) {
   if (nprob <= 0 || mcap <= 0 || ncap <= 0 || batch_cap <= 0) return;
+  if (ks.split < 1 || !ks.ws) ks.split = 1;
   int tiles = ceil_div(mcap, GT) * ceil_div(ncap, GT);
   long grid = (long)nprob * batch_cap * tiles;
   if (grid <= 0) return;
-  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE>), dim3((unsigned)grid), dim3(256), 0, s,
-                     f, tiles, batch_cap, flops);
+  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE>), dim3((unsigned)(grid * ks.split)),
+                     dim3(256), 0, s, f, tiles, batch_cap, flops, ks);
+  if (ks.split > 1)
+    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, F>), dim3((unsigned)grid), dim3(256), 0, s, f,
+                       tiles, batch_cap, ks);
   HIP_OK(hipGetLastError());
 }
 
