@@ -968,6 +968,130 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
   return sweep;
 }
 
+// Ring variant of the sweeps (no W; every row of a column held in registers,
+// m <= 8 G with G the lanes per pair for P = the power of two >= n columns,
+// n > 1, and at least P / 2 groups of G lanes in the workgroup).  The ordering halves the column set recursively: in a phase on a
+// set of S columns each group keeps one column of the first half in
+// registers and meets the S / 2 columns of the second half in turn (round t
+// pairs resident u with travelling (u + t) mod S / 2); then both halves
+// recurse side by side.  Every pair meets once in P - 1 rounds, as in the
+// round-robin ordering, but only the travelling column passes through LDS
+// in a round, which halves its LDS traffic.  Columns with an index >= n are
+// absent (pairs with them are skipped), so orders somewhat below a power of
+// two can use it too.
+__device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int max_sweeps,
+                                                  double tol, double small2, double& work,
+                                                  int* flag) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  int P = 1;
+  while (P < n) P <<= 1;
+  const int G = jacobi_group_lanes(P, nwaves);
+  const int gpw = 64 / G, gl = lane % G, grp = lane / G;
+  const int g = wv * gpw + grp;  // groups >= P / 2 stay idle
+  const bool live = g < P / 2;
+  int sweep = 0;
+  for (; sweep < max_sweeps; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    int rot = 0;
+    for (int S = P; S >= 2; S >>= 1) {
+      const int h = S / 2, j = g / h, u = g % h;
+      const int ri = j * S + u;  // resident column of this phase
+      const bool hr = live && ri < n;
+      double* ca = A + (long)(hr ? ri : 0) * m;
+      double xr[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = gl + q * G;
+        xr[q] = (hr && r < m) ? ca[r] : 0.0;
+      }
+      double al = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) al += xr[q] * xr[q];
+      al = group_sum(al, G);
+      for (int t = 0; t < h; ++t) {
+        int v = u + t;
+        if (v >= h) v -= h;
+        const int ti = j * S + h + v;
+        const bool act = hr && ti < n;
+        double* cb = A + (long)(act ? ti : 0) * m;
+        double yr[8];
+        double be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int r = gl + q * G;
+          yr[q] = (act && r < m) ? cb[r] : 0.0;
+          be += yr[q] * yr[q];
+          ga += xr[q] * yr[q];
+        }
+        be = group_sum(be, G);
+        ga = group_sum(ga, G);
+        if (act && gl == 0) work += 6.0 * m;
+        // same test and rotation as the round-robin sweeps, with the column
+        // of smaller index as the first of the pair
+        if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be) && al > small2 &&
+            be > small2) {
+          const bool rfirst = ri < ti;
+          const double aa = rfirst ? al : be, bb = rfirst ? be : al;
+          const double g2 = 2.0 * ga;
+          double ig = __builtin_amdgcn_rcp(g2);
+          ig = ig * (2.0 - g2 * ig);
+          ig = ig * (2.0 - g2 * ig);
+          const double zeta = (bb - aa) * ig;
+          const double q1 = 1.0 + zeta * zeta;
+          double rq = __builtin_amdgcn_rsq(q1);
+          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+          const double den = fabs(zeta) + q1 * rq;
+          double id = __builtin_amdgcn_rcp(den);
+          id = id * (2.0 - den * id);
+          id = id * (2.0 - den * id);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+          const double q2 = 1.0 + tt * tt;
+          double cs = __builtin_amdgcn_rsq(q2);
+          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+          const double sn = cs * tt;
+          // first' = cs first - sn second, second' = sn first + cs second
+          const double sx = rfirst ? -sn : sn;  // resident' = cs x + sx y
+          const double sy = rfirst ? sn : -sn;  // travelling' = sy x + cs y
+          double nal = 0.0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const double x = xr[q], y = yr[q];
+            xr[q] = cs * x + sx * y;
+            yr[q] = sy * x + cs * y;
+            nal += xr[q] * xr[q];
+          }
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int r = gl + q * G;
+            if (r < m) cb[r] = yr[q];
+          }
+          // the resident's new norm (all lanes of the group take this branch)
+          al = group_sum(nal, G);
+          if (gl == 0) work += 6.0 * m;
+          rot = 1;
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int r = gl + q * G;
+        if (hr && r < m) ca[r] = xr[q];
+      }
+      __syncthreads();
+    }
+    if (rot) *flag = 1;  // every writer stores the same value
+    __syncthreads();
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  return sweep;
+}
+
 // Column norms of A into nrm (a non-finite norm becomes -1 and sets
 // *nonfin), then perm = indices sorted by decreasing norm (ties by index),
 // a permutation whatever the values.
@@ -1070,7 +1194,16 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   const double eps = 2.220446049250313e-16;
   double work = 0.0;
   const double tol = orth_tol > 0.0 ? orth_tol : eps * sqrt((double)(s > 1 ? s : 1));
-  const int sw = jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2, work, flag);
+  // the ring ordering when its padding to a power of two costs less than the
+  // LDS traffic it saves (c > 4/5 of that power) and the rows fit registers
+  int P2 = 1;
+  while (P2 < c) P2 <<= 1;
+  const int Gr = jacobi_group_lanes(P2, blockDim.x >> 6);
+  const bool ring = c > 1 && 5 * c > 4 * P2 && s <= 8 * Gr &&
+                    P2 / 2 <= (int)(blockDim.x >> 6) * (64 / Gr);  // one pair per group
+  const int sw = ring ? jacobi_sweeps_ring(A, s, c, max_sweeps, tol, eps * eps * fro2, work, flag)
+                      : jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2, work,
+                                      flag);
   if (tid == 0 && p.fail) {
     if (sw >= max_sweeps) atomicAdd(p.fail, 1);
     atomicAdd(p.fail + 2, sw);
