@@ -250,8 +250,14 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
   for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
     const int row = ti * GT + e / GT, col = tj * GT + e % GT;
     if (row >= d.M || col >= d.N) continue;
+    // the shares' loads are issued together, then summed in share order
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = q < ks.split ? W[(long)q * (GT * GT) + e] : 0.0;
     double sum = 0.0;
-    for (int q = 0; q < ks.split; ++q) sum += W[(long)q * (GT * GT) + e];
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (q < ks.split) sum += v[q];
     TC* p = C + row * d.sCm + col * d.sCn;
     double val = d.alpha * sum;
     if (d.beta != 0.0) val += d.beta * (double)(*p);

@@ -427,6 +427,35 @@ constexpr int CPB_MAXN = 128;  // largest order factored by the blocked variant
 constexpr int LPS = CPB + 1;   // row stride of the panel: odd, so that lanes
                                // reading one column hit distinct LDS banks
 
+// Wave-wide maximum (FP64) and minimum (int) with every lane of the wave
+// active: DPP steps inside rows of 16 lanes, then the four row results.
+template <int CTRL>
+__device__ inline double dpp_mov_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ inline double readlane_f64(double v, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                          __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ inline double wave_max_f64(double v) {
+  v = fmax(v, dpp_mov_f64<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dpp_mov_f64<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dpp_mov_f64<0x141>(v));  // row_half_mirror
+  v = fmax(v, dpp_mov_f64<0x140>(v));  // row_mirror
+  return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
+              fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
+}
+__device__ inline int wave_min_i32(int v) {
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));
+  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
+
 // Blocked pivoted Cholesky for n <= CPB_MAXN with G in LDS.  Wave 0 factors
 // a panel of CPB columns (left-looking inside the panel, pivots chosen on
 // the running Schur-complement diagonal dg); then every wave applies the
@@ -435,85 +464,129 @@ constexpr int LPS = CPB + 1;   // row stride of the panel: odd, so that lanes
 __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* perm, double* dg,
                                              double* Lp, int* rho_s, int* kdone) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
-  for (int i = tid; i < n; i += blockDim.x) dg[i] = G[(long)i * n + i];
+  constexpr double DONE = -1e300;  // diagonal mark of a pivoted (or absent) row
+  int* posn = perm + 512;          // pivot position of each physical row (n: not yet)
+  for (int i = tid; i < n; i += blockDim.x) {
+    dg[i] = G[(long)i * n + i];
+    posn[i] = n;
+  }
   __syncthreads();
+  int rho = n;
   for (int j0 = 0; j0 < n; j0 += CPB) {
     const int bw = n - j0 < CPB ? n - j0 : CPB;
     if (wv == 0) {
-      int k = 0;
-      for (; k < bw; ++k) {
-        const int j = j0 + k;
-        double best = -1.0;
-        int bi = j;
-        for (int i = j + lane; i < n; i += 64) {
-          const double v = dg[i];
-          if (v > best) { best = v; bi = i; }
-        }
-        for (int o = 32; o > 0; o >>= 1) {
-          const double ob = __shfl_xor(best, o, 64);
-          const int oi = __shfl_xor(bi, o, 64);
-          if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-        }
-        if (!(best > thr) || !(best > 0.0)) break;  // the same decision in every lane
-        if (bi != j) {
-          if (lane < k) {
-            const double t = Lp[j * LPS + lane];
-            Lp[j * LPS + lane] = Lp[bi * LPS + lane];
-            Lp[bi * LPS + lane] = t;
-          }
-          if (lane == 0) {
-            const int t = perm[j]; perm[j] = perm[bi]; perm[bi] = t;
-            const double u = dg[j]; dg[j] = dg[bi]; dg[bi] = u;
-          }
-        }
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const int pj = perm[j];
-        const double r = sqrt(best), invr = 1.0 / r;
-        for (int i = j + 1 + lane; i < n; i += 64) {
-          double acc = G[(long)pj * n + perm[i]];  // row pj: G is kept symmetric
-          for (int q = 0; q < k; ++q) acc -= Lp[i * LPS + q] * Lp[j * LPS + q];
-          const double l = acc * invr;
-          Lp[i * LPS + k] = l;
-          dg[i] -= l * l;
-        }
-        if (lane == 0) Lp[j * LPS + k] = r;
-        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-        __builtin_amdgcn_wave_barrier();
+      // The panel in registers: lane l owns the physical rows l and l + 64,
+      // their running diagonal and their CPB entries of L, so rows are never
+      // swapped; the pivot is the largest remaining diagonal (lowest row on
+      // ties) and the pivot row of L is read from its owner lane.
+      const int i0 = lane, i1 = lane + 64;
+      double d0 = i0 < n && posn[i0] == n ? dg[i0] : DONE;
+      double d1 = i1 < n && posn[i1] == n ? dg[i1] : DONE;
+      double L0[CPB], L1[CPB];
+#pragma unroll
+      for (int q = 0; q < CPB; ++q) {
+        L0[q] = 0.0;
+        L1[q] = 0.0;
       }
-      if (lane == 0) {
-        *kdone = k;
-        if (k < bw) *rho_s = j0 + k;
+      int kd = 0;
+      bool stop = false;
+#pragma unroll
+      for (int k = 0; k < CPB; ++k) {
+        if (k < bw && !stop) {
+          double cand = d0;
+          int ci = i0;
+          if (d1 > cand) { cand = d1; ci = i1; }
+          const double best = wave_max_f64(cand);
+          const int bi = wave_min_i32(cand == best ? ci : 0x7FFFFFFF);
+          if (!(best > thr) || !(best > 0.0)) {
+            stop = true;  // the same decision in every lane
+          } else {
+            const int p = bi, pl = p & 63;
+            const bool phi = p >= 64;
+            double lp[CPB];
+#pragma unroll
+            for (int q = 0; q < k; ++q) {
+              const double v = phi ? L1[q] : L0[q];
+              lp[q] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), pl),
+                                       __builtin_amdgcn_readlane(__double2loint(v), pl));
+            }
+            const double r = sqrt(best), invr = 1.0 / r;
+            const double* gp = G + (long)p * n;  // row p (G is kept symmetric)
+            if (d0 > DONE && i0 != p) {
+              double acc = gp[i0];
+#pragma unroll
+              for (int q = 0; q < k; ++q) acc -= L0[q] * lp[q];
+              const double l = acc * invr;
+              L0[k] = l;
+              d0 -= l * l;
+            }
+            if (d1 > DONE && i1 != p) {
+              double acc = gp[i1];
+#pragma unroll
+              for (int q = 0; q < k; ++q) acc -= L1[q] * lp[q];
+              const double l = acc * invr;
+              L1[k] = l;
+              d1 -= l * l;
+            }
+            if (i0 == p) { L0[k] = r; d0 = DONE; }
+            if (i1 == p) { L1[k] = r; d1 = DONE; }
+            if (lane == 0) {
+              perm[j0 + k] = p;
+              posn[p] = j0 + k;
+            }
+            kd = k + 1;
+          }
+        }
       }
+#pragma unroll
+      for (int q = 0; q < CPB; ++q) {
+        if (i0 < n) Lp[i0 * LPS + q] = L0[q];
+        if (i1 < n) Lp[i1 * LPS + q] = L1[q];
+      }
+      if (i0 < n) dg[i0] = d0;
+      if (i1 < n) dg[i1] = d1;
+      if (lane == 0) *kdone = kd;
     }
     __syncthreads();
     const int kd = *kdone;
-    // rows of R for the finished panel columns
+    // row j of R (by physical column): L[i][j - j0] for every row i pivoted
+    // at or after j
     for (int k = 0; k < kd; ++k) {
       const int j = j0 + k, pj = perm[j];
-      for (int c = j + tid; c < n; c += blockDim.x) G[(long)pj * n + perm[c]] = Lp[c * LPS + k];
+      for (int i = tid; i < n; i += blockDim.x)
+        if (posn[i] >= j) G[(long)pj * n + i] = Lp[i * LPS + k];
     }
     if (kd < bw) {
+      rho = j0 + kd;
       __syncthreads();
       break;
     }
-    // trailing update G[a][b] -= sum_q L[a][q] L[b][q] over positions >= j0 + bw
-    const int t0 = j0 + bw;
-    for (int a = t0 + wv; a < n; a += nw) {
-      const int pa = perm[a];
+    // trailing update of the rows and columns not pivoted yet
+    for (int a = wv; a < n; a += nw) {
+      if (posn[a] < n) continue;
       double la[CPB];
 #pragma unroll
       for (int q = 0; q < CPB; ++q) la[q] = q < bw ? Lp[a * LPS + q] : 0.0;
-      double* ga = G + (long)pa * n;
-      for (int b = t0 + lane; b < n; b += 64) {
+      double* ga = G + (long)a * n;
+      for (int b = lane; b < n; b += 64) {
+        if (posn[b] < n) continue;
         double acc = 0.0;
 #pragma unroll
         for (int q = 0; q < CPB; ++q) acc += la[q] * Lp[b * LPS + q];
-        ga[perm[b]] -= acc;
+        ga[b] -= acc;
       }
     }
     __syncthreads();
   }
+  // positions rho.. hold the rows never pivoted, in increasing order
+  for (int i = tid; i < n; i += blockDim.x) {
+    if (posn[i] < n) continue;
+    int c = 0;
+    for (int i2 = 0; i2 < i; ++i2) c += posn[i2] == n ? 1 : 0;
+    perm[rho + c] = i;
+  }
+  if (tid == 0) *rho_s = rho;
+  __syncthreads();
 }
 
 // Body of k_chol_piv for G in LDS or in global memory.
