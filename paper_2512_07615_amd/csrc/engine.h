@@ -885,6 +885,15 @@ class Engine {
     HIP_OK(hipMemset(rw.tries, 0, 16));
   }
 
+  // Threads of the truncation's Jacobi at bond k: the columns it rotates
+  // number at most the rank of the unfolding, which the full bound of the
+  // bond caps below the storage capacity (twice the bond for sums); up to 64
+  // columns, 512 threads give 16 lanes per pair, which keep every row of a
+  // column up to 128 in registers.
+  int eig_threads(int scap, int k) const {
+    return std::min(scap, full_bound(n, k)) <= 64 ? 512 : 1024;
+  }
+
   // randomized attempt at bond k of one rounding call (see rsvd.h)
   void rs_attempt(MpsList<T> L, int k, int cnt, int* predk, int scap, int chi_cap) {
     const long sq = rw.sq;
@@ -912,7 +921,7 @@ class Engine {
                        rw.B, rw.R, rw.rankT, eps_rank, lds_elems, cnt, 0, (double*)nullptr, 0.0);
     hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st, FnRsEig{rw, chi_cap, istats},
                        rs_ep, cnt);
-    hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024), lds, st,
+    hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)), lds, st,
                        (const EigProb*)rs_ep, lds_elems, 40, (double*)nullptr, eig_orth_tol);
     hipLaunchKernelGGL(k_rs_accept<T>, dim3(1), dim3(64), 0, st, L, k, (const double*)rdelta,
                        chi_cap, rw, rdisc, cnt);
@@ -1272,7 +1281,7 @@ class Engine {
                                        rs_now ? (const int*)rw.acc : nullptr},
                          ep, cnt);
       tbegin(1);
-      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(scap <= 64 ? 512 : 1024),
+      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)),
                          (size_t)lds_elems * 8, st,
                          (const EigProb*)ep, lds_elems, 40, kf(1), eig_orth_tol);
       tend(1);
