@@ -1078,7 +1078,7 @@ class Engine {
     cw.B2 = (double*)dalloc(8 * sq * MAXB);
     cw.R2 = (double*)dalloc(8 * sq * MAXB);
     cw.Q1 = (double*)dalloc(8 * mq * MAXB);
-    cw.rank = (int*)dalloc(4 * 4 * MAXB);  // [0, 2 MAXB): per-problem pairs; [2 MAXB, 3 MAXB): pass 2
+    cw.rank = (int*)dalloc(4 * 4 * MAXB);  // [0, 2 MAXB): per-problem pairs (pass 1, pass 2)
     cq_n = (int*)dalloc(4 * 2 * MAXB);
     ep = (EigProb*)dalloc(sizeof(EigProb) * MAXB);
     envL = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
@@ -1206,10 +1206,10 @@ class Engine {
     launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st, nullptr,
                                       ksplit(nprob, scap, scap, 1, mcap));
     tbegin(4);
+    // ranks land interleaved: pass 1 in rank[2 i], pass 2 in rank[2 i + 1]
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)cq_n, 1, w.G,
-                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4));
+                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4), 0.0, 2);
     tend(4);
-    hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 0);
     launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st,
                                                 nullptr, ksplit(nprob, scap, scap, 1, mcap));
@@ -1217,10 +1217,9 @@ class Engine {
                        (const int*)w.rank, cq_n + MAXB, nprob);
     tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)(cq_n + MAXB), 1,
-                       w.G, w.sq, w.B2, w.R2, w.rank + 2 * MAXB, 1e-28, lds_elems, nprob, 1,
-                       kf(4), cq_skip);
+                       w.G, w.sq, w.B2, w.R2, w.rank + 1, 1e-28, lds_elems, nprob, 1,
+                       kf(4), cq_skip, 2);
     tend(4);
-    hipLaunchKernelGGL(k_cq_spread, dim3(1), dim3(64), 0, st, w.rank, nprob, 1);
     launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqR<T>{qp, w}, nprob, scap, scap, 1, st);
     hipLaunchKernelGGL(k_cq_finish<T>, dim3(nprob), dim3(256), 0, st, qp, (const int*)w.rank,

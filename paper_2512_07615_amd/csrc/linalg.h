@@ -416,12 +416,13 @@ struct CholWork {
 };
 
 // Pivoted Cholesky of G (n x n, row-major, FP64) with threshold; writes
-// B = P[:, :rho] R11^{-1} (n x rho, ld rho, when want_b) and Rp = R P^T
-// (rho x n, ld n).  Right-looking, with the permutation kept as an index
-// array (no row/column swaps) and the scaling of each pivot row deferred to
-// the next step, so a step costs three barriers.  The stored matrix ends up
-// holding R in its "upper" part (position order) and serves as scratch for
-// the back substitution in its "lower" part.
+// B = P[:, :rho] R11^{-1} (n x rho, ld rho, when want_b), Rp = R P^T
+// (rho x n, ld n) and the rank rho to rank_out[problem * rank_stride].
+// Orders up to CPB_MAXN held in LDS are factored blockwise (chol_blocked);
+// larger ones right-looking in global memory, with the permutation kept as
+// an index array and the scaling of each pivot row deferred to the next
+// step (three barriers a step).  Row perm[j] of the stored matrix ends up
+// holding row j of R.
 constexpr int CPB = 16;     // panel width of the blocked pivoted Cholesky
 constexpr int CPB_MAXN = 128;  // largest order factored by the blocked variant
 constexpr int LPS = CPB + 1;   // row stride of the panel: odd, so that lanes
@@ -594,7 +595,7 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
                                           double* Rbase, int* rank_out, double eps_rank,
                                           int want_b, int* perm, double* red, int* ired,
                                           int* rho_s, double* dmax0, double* dpiv, double* xd,
-                                          double* Lp, int* kdone) {
+                                          double* Lp, int* kdone, int rank_stride) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < n; i += blockDim.x) perm[i] = i;
   __syncthreads();
@@ -670,7 +671,7 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
   const int rr = rho > 0 ? rho : 1;
   double* B = Bbase + pr * sq;  // n x rr
   double* Rp = Rbase + pr * sq; // rr x n
-  if (tid == 0) rank_out[pr] = rr;
+  if (tid == 0) rank_out[(long)pr * rank_stride] = rr;
   // Rp[r][perm[c]] = R[r][c] (upper trapezoid), zero rank -> zero row
   for (long e = tid; e < (long)rr * n; e += blockDim.x) {
     int r = (int)(e / n), c = (int)(e % n);
@@ -798,7 +799,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
                                                   int* rank_out, double eps_rank, int lds_elems,
                                                   int nprob, int want_b = 1,
                                                   double* flops = nullptr,
-                                                  double skip_tol = 0.0) {
+                                                  double skip_tol = 0.0,
+                                                  int rank_stride = 1) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[16];
@@ -843,7 +845,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
         B[e] = v;
         Rp[e] = v;
       }
-      if (threadIdx.x == 0) rank_out[pr] = n;
+      if (threadIdx.x == 0) rank_out[(long)pr * rank_stride] = n;
       return;
     }
     __syncthreads();
@@ -851,10 +853,10 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
   if ((long)n * n <= lds_elems) {
     block_copy(sh, Gg, (long)n * n);
     chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
-              &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone);
+              &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone, rank_stride);
   } else {
     chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
-              &dmax0, &dpiv, xd, nullptr, &kdone);
+              &dmax0, &dpiv, xd, nullptr, &kdone, rank_stride);
   }
   if (flops && threadIdx.x == 0) {
     // factorisation: per pivot j a column scaling and a symmetric rank-1
@@ -864,17 +866,6 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
     for (int j = 0; j < rho; ++j) f += 2.0 * (n - j - 1) * (n - j - 1) + (n - j - 1);
     if (want_b) f += (double)rho * rho * rho / 3.0;
     atomicAdd(flops, f);
-  }
-}
-
-// k_chol_piv writes its ranks densely (pass 1 into rank[0..n), pass 2 into
-// rank[2 MAXB ..)); this moves them to rank[2 i + pass].
-__global__ void k_cq_spread(int* rank, int nprob, int pass) {
-  if (threadIdx.x != 0) return;
-  if (pass == 0) {
-    for (int i = nprob - 1; i >= 0; --i) rank[2 * i] = rank[i];
-  } else {
-    for (int i = 0; i < nprob; ++i) rank[2 * i + 1] = rank[2 * MAXB + i];
   }
 }
 
