@@ -495,11 +495,6 @@ __global__ void k_div_scalar(const double* a, double b, double* out) {
 // ============================================================================
 // FP32 policy: rank-revealing Cholesky-QR2 and Gram-eigen truncation.
 template <typename T>
-__global__ void k_cq_dims(const QrProb<T>* qp, int* n1, int nprob) {
-  int i = threadIdx.x;
-  if (i < nprob) n1[i] = (qp[i].valid && qp[i].m > qp[i].s) ? qp[i].s : 0;
-}
-template <typename T>
 struct FCqGram1 {  // G = A^T A
   const QrProb<T>* qp; CholWork w;
   __device__ GemmDesc<T, T, double> get(int i) const {
@@ -544,11 +539,6 @@ struct FCqGram2 {  // G = Q1^T Q1 (rho1 x rho1)
     return d;
   }
 };
-template <typename T>
-__global__ void k_cq_dims2(const QrProb<T>* qp, const int* rank, int* n2, int nprob) {
-  int i = threadIdx.x;
-  if (i < nprob) n2[i] = (qp[i].valid && qp[i].m > qp[i].s) ? rank[2 * i] : 0;
-}
 template <typename T>
 struct FCqQ {  // Q = Q1 B2 (m x rho2) -> output
   const QrProb<T>* qp; CholWork w;
@@ -1184,7 +1174,8 @@ class Engine {
   template <typename F>
   void qr(const F& f, int nprob, int mcap, int scap) {
     if (nprob <= 0) return;
-    hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob);
+    hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob,
+                       fast ? cq_n : (int*)nullptr);
     hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
                        (const QrProb<T>*)qp);
     if (fast) {
@@ -1202,19 +1193,17 @@ class Engine {
   void qr_cholesky(int nprob, int mcap, int scap) {
     size_t lds = (size_t)lds_elems * 8;
     CholWork w = cw;
-    hipLaunchKernelGGL(k_cq_dims<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp, cq_n, nprob);
     launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st, nullptr,
                                       ksplit(nprob, scap, scap, 1, mcap));
     tbegin(4);
     // ranks land interleaved: pass 1 in rank[2 i], pass 2 in rank[2 i + 1]
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)cq_n, 1, w.G,
-                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4), 0.0, 2);
+                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4), 0.0, 2,
+                       cq_n + MAXB);
     tend(4);
     launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st,
                                                 nullptr, ksplit(nprob, scap, scap, 1, mcap));
-    hipLaunchKernelGGL(k_cq_dims2<T>, dim3(1), dim3(64), 0, st, (const QrProb<T>*)qp,
-                       (const int*)w.rank, cq_n + MAXB, nprob);
     tbegin(4);
     hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)(cq_n + MAXB), 1,
                        w.G, w.sq, w.B2, w.R2, w.rank + 1, 1e-28, lds_elems, nprob, 1,

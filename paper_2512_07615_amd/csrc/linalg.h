@@ -36,12 +36,14 @@ struct QrWork {
 };
 
 template <typename T, typename F>
-__global__ void k_qr_prep(F f, QrProb<T>* qp, int nprob) {
+__global__ void k_qr_prep(F f, QrProb<T>* qp, int nprob, int* n1 = nullptr) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nprob) return;
   QrProb<T> q = f.get(i);
   if (q.valid) q.p = q.m < q.s ? q.m : q.s;
   qp[i] = q;
+  // order of the first Cholesky-QR pass (0: not factored that way)
+  if (n1) n1[i] = (q.valid && q.m > q.s) ? q.s : 0;
 }
 
 // ---- GEMM functors over materialised QR problems -------------------------
@@ -800,7 +802,8 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
                                                   int nprob, int want_b = 1,
                                                   double* flops = nullptr,
                                                   double skip_tol = 0.0,
-                                                  int rank_stride = 1) {
+                                                  int rank_stride = 1,
+                                                  int* dims_next = nullptr) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[16];
@@ -814,7 +817,11 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
   const int pr = blockIdx.x;
   if (pr >= nprob) return;
   const int n = dims[pr * dim_stride];
-  if (n <= 0 || n > 1024) return;
+  // dims_next[pr]: the order of a following pass on the factor (its rank)
+  if (n <= 0 || n > 1024) {
+    if (dims_next && threadIdx.x == 0) dims_next[pr] = 0;
+    return;
+  }
   double* Gg = Gbase + pr * sq;
   if (skip_tol > 0.0) {
     // a Gram that is the identity to within skip_tol (the second pass of
@@ -858,6 +865,7 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
     chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, nullptr, &kdone, rank_stride);
   }
+  if (dims_next && threadIdx.x == 0) dims_next[pr] = rank_out[(long)pr * rank_stride];
   if (flops && threadIdx.x == 0) {
     // factorisation: per pivot j a column scaling and a symmetric rank-1
     // update of the trailing (n-j-1)^2 block; inverse of R11: rho^3 / 3
