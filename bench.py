@@ -145,7 +145,7 @@ def main():
     ap.add_argument("--predictor-steps", type=int, default=3,
                     help="steps timed with the rank-predicted randomized truncation "
                          "(0 = skip; FP32/BF16 workloads)")
-    ap.add_argument("--roofline-kernel", default="cholesky",
+    ap.add_argument("--roofline-kernel", default="jacobi",
                     choices=["jacobi", "householder", "prodgemm", "cholesky"])
     args = ap.parse_args()
     if args.gpus != 1:
