@@ -909,6 +909,14 @@ __device__ inline double group_sum(double v, int G) {
   return v;
 }
 
+// Relative orthogonality test of a column pair, |ga| > tol sqrt(al) sqrt(be),
+// with the hardware reciprocal square roots: the threshold needs only a few
+// digits, and the product of the two factors neither overflows nor
+// underflows for norms in range (a zero norm gives NaN, i.e. not coupled).
+__device__ inline bool pair_coupled(double ga, double al, double be, double tol) {
+  return fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be) > tol;
+}
+
 __device__ inline int jacobi_group_lanes(int n, int nwaves) {
   int pairs = ((n % 2) ? n + 1 : n) / 2;
   int G = 64;
@@ -973,10 +981,10 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
         al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
         if (!act) continue;
         if (gl == 0) work += 6.0 * m;
-        // relative orthogonality test; sqrt(al) sqrt(be) avoids underflow of
-        // al * be; a column below the rounding level of the whole matrix
-        // (norm^2 <= small2) is numerically zero and is not rotated
-        if (ga == 0.0 || !(fabs(ga) > tol * sqrt(al) * sqrt(be))) continue;
+        // relative orthogonality test; a column below the rounding level of
+        // the whole matrix (norm^2 <= small2) is numerically zero and is not
+        // rotated
+        if (ga == 0.0 || !pair_coupled(ga, al, be, tol)) continue;
         if (al <= small2 || be <= small2) continue;
         // rotation angle (Rutishauser's formulas); reciprocals and reciprocal
         // square roots from the hardware estimates refined by two
@@ -1102,8 +1110,7 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
         if (act && gl == 0) work += 6.0 * m;
         // same test and rotation as the round-robin sweeps, with the column
         // of smaller index as the first of the pair
-        if (act && ga != 0.0 && fabs(ga) > tol * sqrt(al) * sqrt(be) && al > small2 &&
-            be > small2) {
+        if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
           const bool rfirst = ri < ti;
           const double aa = rfirst ? al : be, bb = rfirst ? be : al;
           const double g2 = 2.0 * ga;
