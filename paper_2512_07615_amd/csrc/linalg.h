@@ -1113,23 +1113,22 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
         if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
           const bool rfirst = ri < ti;
           const double aa = rfirst ? al : be, bb = rfirst ? be : al;
+          // one Newton-Raphson step on each hardware estimate (relative
+          // error about 5e-8, measured on gfx950) leaves it within 5e-15,
+          // ample for the FP32 truncation this ordering serves
           const double g2 = 2.0 * ga;
           double ig = __builtin_amdgcn_rcp(g2);
-          ig = ig * (2.0 - g2 * ig);
           ig = ig * (2.0 - g2 * ig);
           const double zeta = (bb - aa) * ig;
           const double q1 = 1.0 + zeta * zeta;
           double rq = __builtin_amdgcn_rsq(q1);
           rq = rq * (1.5 - 0.5 * q1 * rq * rq);
-          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
           const double den = fabs(zeta) + q1 * rq;
           double id = __builtin_amdgcn_rcp(den);
-          id = id * (2.0 - den * id);
           id = id * (2.0 - den * id);
           const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
           const double q2 = 1.0 + tt * tt;
           double cs = __builtin_amdgcn_rsq(q2);
-          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
           cs = cs * (1.5 - 0.5 * q2 * cs * cs);
           const double sn = cs * tt;
           // first' = cs first - sn second, second' = sn first + cs second
