@@ -513,7 +513,12 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
               lp[q] = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), pl),
                                        __builtin_amdgcn_readlane(__double2loint(v), pl));
             }
-            const double r = sqrt(best), invr = 1.0 / r;
+            // 1 / sqrt(best) from the hardware estimate and two Newton steps
+            // (within a few ulp), then sqrt(best) = best / sqrt(best)
+            double invr = __builtin_amdgcn_rsq(best);
+            invr = invr * (1.5 - 0.5 * best * invr * invr);
+            invr = invr * (1.5 - 0.5 * best * invr * invr);
+            const double r = best * invr;
             const double* gp = G + (long)p * n;  // row p (G is kept symmetric)
             if (d0 > DONE && i0 != p) {
               double acc = gp[i0];
@@ -553,30 +558,32 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
     __syncthreads();
     const int kd = *kdone;
     // row j of R (by physical column): L[i][j - j0] for every row i pivoted
-    // at or after j
-    for (int k = 0; k < kd; ++k) {
-      const int j = j0 + k, pj = perm[j];
-      for (int i = tid; i < n; i += blockDim.x)
-        if (posn[i] >= j) G[(long)pj * n + i] = Lp[i * LPS + k];
+    // at or after j (all rows of the panel at once; the trailing update
+    // below touches only rows not pivoted yet)
+    for (int e = tid; e < kd * n; e += blockDim.x) {
+      const int k = e / n, i = e - k * n, j = j0 + k;
+      if (posn[i] >= j) G[(long)perm[j] * n + i] = Lp[i * LPS + k];
     }
     if (kd < bw) {
       rho = j0 + kd;
       __syncthreads();
       break;
     }
-    // trailing update of the rows and columns not pivoted yet
-    for (int a = wv; a < n; a += nw) {
-      if (posn[a] < n) continue;
-      double la[CPB];
+    // trailing update of the rows and columns not pivoted yet: each lane
+    // keeps the panel row of its column b in registers, and the panel row of
+    // each updated row a is a broadcast read (entries of L beyond the
+    // panel's pivots are zero)
+    for (int b = lane; b < n; b += 64) {
+      const bool ub = posn[b] == n;
+      double lb[CPB];
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) la[q] = q < bw ? Lp[a * LPS + q] : 0.0;
-      double* ga = G + (long)a * n;
-      for (int b = lane; b < n; b += 64) {
-        if (posn[b] < n) continue;
+      for (int q = 0; q < CPB; ++q) lb[q] = ub ? Lp[b * LPS + q] : 0.0;
+      for (int a = wv; a < n; a += nw) {
+        if (posn[a] < n) continue;
         double acc = 0.0;
 #pragma unroll
-        for (int q = 0; q < CPB; ++q) acc += la[q] * Lp[b * LPS + q];
-        ga[b] -= acc;
+        for (int q = 0; q < CPB; ++q) acc += Lp[a * LPS + q] * lb[q];
+        if (ub) G[(long)a * n + b] -= acc;
       }
     }
     __syncthreads();
@@ -754,9 +761,17 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
       const int bc = rho - p - b < b ? rho - p - b : b;
       for (int e = tid; e < b * bc; e += blockDim.x) {
         const int ig = p + e / bc, c = p + b + e % bc;
-        double a = xd[ig] * G[(long)ig * rho + sk(c + ig)];
-        for (int t = ig + 1; t < p + b; ++t)
-          a += G[(long)t * rho + sk(ig + t)] * G[(long)t * rho + sk(c + t)];
+        // four partial sums keep several LDS loads in flight
+        double a0 = xd[ig] * G[(long)ig * rho + sk(c + ig)], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int t = ig + 1;
+        for (; t + 3 < p + b; t += 4) {
+          a0 += G[(long)t * rho + sk(ig + t)] * G[(long)t * rho + sk(c + t)];
+          a1 += G[(long)(t + 1) * rho + sk(ig + t + 1)] * G[(long)(t + 1) * rho + sk(c + t + 1)];
+          a2 += G[(long)(t + 2) * rho + sk(ig + t + 2)] * G[(long)(t + 2) * rho + sk(c + t + 2)];
+          a3 += G[(long)(t + 3) * rho + sk(ig + t + 3)] * G[(long)(t + 3) * rho + sk(c + t + 3)];
+        }
+        for (; t < p + b; ++t) a0 += G[(long)t * rho + sk(ig + t)] * G[(long)t * rho + sk(c + t)];
+        const double a = (a0 + a1) + (a2 + a3);
         if (!regs) B[(long)ig * rho + c] = a;
         else if (q < 4) u[q++] = a;
       }
@@ -777,10 +792,16 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
       const int bc = rho - p - b < b ? rho - p - b : b;
       for (int e = tid; e < b * bc; e += blockDim.x) {
         const int ig = p + e / bc, c = p + b + e % bc;
-        double a = G[(long)ig * rho + sk(c + ig)] * xd[c];
-        for (int t = p + b; t < c; ++t)
-          a += G[(long)ig * rho + sk(t + ig)] * G[(long)c * rho + sk(t + c)];
-        G[(long)c * rho + sk(ig + c)] = -a;
+        double a0 = G[(long)ig * rho + sk(c + ig)] * xd[c], a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int t = p + b;
+        for (; t + 3 < c; t += 4) {
+          a0 += G[(long)ig * rho + sk(t + ig)] * G[(long)c * rho + sk(t + c)];
+          a1 += G[(long)ig * rho + sk(t + 1 + ig)] * G[(long)c * rho + sk(t + 1 + c)];
+          a2 += G[(long)ig * rho + sk(t + 2 + ig)] * G[(long)c * rho + sk(t + 2 + c)];
+          a3 += G[(long)ig * rho + sk(t + 3 + ig)] * G[(long)c * rho + sk(t + 3 + c)];
+        }
+        for (; t < c; ++t) a0 += G[(long)ig * rho + sk(t + ig)] * G[(long)c * rho + sk(t + c)];
+        G[(long)c * rho + sk(ig + c)] = -((a0 + a1) + (a2 + a3));
       }
     }
     __syncthreads();
