@@ -34,8 +34,9 @@ def make_case(name):
         return WL.case_channel()
     if name == "vascular128":
         # 128^3 branching tube tree, velocity inlet 0.02 / pressure outlet,
-        # chi = 128, BF16 contractions (FP32 storage and factorisations)
-        return WL.case_vascular(n=7, chi=128, tau=0.55, tol=1e-8, precision="bf16")
+        # chi = 128, contractions on BF16 MFMA with three-term operand
+        # splitting and FP32 accumulation (FP32 storage and factorisations)
+        return WL.case_vascular(n=7, chi=128, tau=0.55, tol=1e-8, precision="bf16x3")
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -116,7 +117,8 @@ def roofline(kind, ks, prec):
     achieved = flops_per_launch / (avg_ms * 1e-3) / 1e12 if avg_ms > 0 else 0.0
     if kind == "prodgemm":
         bound = "mfma"
-        peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"]}.get(prec, PEAK["fp64_tflops"])
+        peak = {"fp32": PEAK["fp32_tflops"], "bf16": PEAK["bf16_tflops"],
+                "bf16x3": PEAK["bf16_tflops"]}.get(prec, PEAK["fp64_tflops"])
     else:
         # FP64 vector ALU: 256 CUs x 2.4 GHz x 128 FP64 flops/clock/CU
         bound, peak = "alu", PEAK["fp64_tflops"]
@@ -188,7 +190,8 @@ def main():
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mfma/f32"}[case.precision],
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16-mfma/f32",
+                  "bf16x3": "bf16x3-mfma/f32"}[case.precision],
         "data": "synthetic",
         "config": {"workload": case.name, "n": case.n, "chi": case.chi, "tau": case.tau,
                    "tol": case.tol, "geometry": case.meta,

@@ -46,10 +46,14 @@ extern "C" {
    rank selection and 1/rho coefficients are FP64 under every policy.
    BF16: FP32 storage and factorisations as MPS_LBM_FP32, with the
    contractions of the variational products (Section 2.3) run on BF16 MFMA
-   (operands rounded to BF16, FP32 accumulation). */
+   (operands rounded to BF16, FP32 accumulation).  BF16X3: as BF16, but each
+   FP32 operand is split exactly into three BF16 terms and the six products
+   of significant order are accumulated, which keeps the contractions at
+   about FP32 accuracy on the BF16 matrix units. */
 #define MPS_LBM_FP64 0
 #define MPS_LBM_FP32 1
 #define MPS_LBM_BF16 2
+#define MPS_LBM_BF16X3 3
 
 /* inverse density: second-order Taylor expansion about the mean density
    rho_0 (Section 3.2), or k Newton-Schulz steps from 1/rho_0 (k steps equal
@@ -83,7 +87,7 @@ typedef struct {
   double g[3];      /* body acceleration; force density F = rho g          */
   int inv_rho_mode; /* MPS_LBM_INV_TAYLOR2 | MPS_LBM_INV_NEWTON            */
   int inv_rho_iters;/* Newton-Schulz steps (>= 1) when mode is NEWTON      */
-  int precision;    /* MPS_LBM_FP64 | MPS_LBM_FP32 | MPS_LBM_BF16          */
+  int precision;    /* MPS_LBM_FP64 | MPS_LBM_FP32 | MPS_LBM_BF16 | ..X3   */
   int sweeps;       /* variational-product sweeps 1->n->1 (the paper: 2)   */
   int axis_open[3]; /* 0 = periodic (cyclic shift), 1 = open (non-cyclic)  */
   int face_bc[6];   /* faces x-lo, x-hi, y-lo, y-hi, z-lo, z-hi            */

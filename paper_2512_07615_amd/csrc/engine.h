@@ -1138,14 +1138,20 @@ class Engine {
 
   // Product contractions: in the working type, or (BF16 policy, FP32
   // storage) with operands rounded to BF16 on a BF16 MFMA, FP32 accumulate.
-  bool bf16_products = false;
+  // product contractions: 0 in the storage type, 1 on BF16 MFMA (operands
+  // rounded), 2 on BF16 MFMA with three-term operand splitting
+  int bf16_products = 0;
   template <typename F>
   void pgemm(const F& f, int nprob, int mcap, int ncap, int bcap, hipStream_t s,
              double* flops = nullptr, int kcap = 0) {
     const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap);
     if constexpr (std::is_same<T, float>::value) {
-      if (bf16_products) {
+      if (bf16_products == 1) {
         launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+        return;
+      }
+      if (bf16_products == 2) {
+        launch_gemm<T, T, T, float, F, 2>(f, nprob, mcap, ncap, bcap, s, flops, ks);
         return;
       }
     }

@@ -77,9 +77,27 @@ __device__ inline short bf16_bits(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
   return (short)(u >> 16);
 }
+__device__ inline float bf16_value(short b) {
+  return __uint_as_float(((unsigned)(unsigned short)b) << 16);
+}
+// x = h + m + l with h, m, l BF16: each term the nearest BF16 to what the
+// earlier terms leave; the remainders are exact in FP32, and the three
+// terms hold 24 significant bits, so the split is exact for normal x
+// whose remainders stay normal
+__device__ inline void bf16_split3(float x, short& h, short& m, short& l) {
+  h = bf16_bits(x);
+  const float r1 = x - bf16_value(h);
+  m = bf16_bits(r1);
+  const float r2 = r1 - bf16_value(m);
+  l = bf16_bits(r2);
+}
 
 // MODE 0: MFMA in the accumulation type; MODE 1 (Tacc = float): operands
-// rounded to BF16, BF16 MFMA with FP32 accumulation.
+// rounded to BF16, BF16 MFMA with FP32 accumulation; MODE 2 (Tacc = float):
+// each FP32 operand split exactly into three BF16 terms x = h + m + l (each
+// the BF16 rounding of what the previous ones leave), and the six products
+// of combined order up to l (hh, hm, mh, hl, mm, lh) accumulated on BF16
+// MFMA in FP32, which carries the product to about FP32 accuracy.
 // Split K: with split > 1 each of `split` workgroups of a tile multiplies
 // one contiguous share of K (a multiple of GK) and stores its partial tile
 // in ws; k_gemm_reduce then sums the shares in a fixed order.
@@ -159,7 +177,44 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
     __syncthreads();
     if (k0 + GK < ke) fetch(k0 + GK);
     const int kvalid = ke - k0;  // K columns of this slice that are not padding
-    if constexpr (MODE == 1) {
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int ks = 0; ks < GK / 16; ++ks) {
+        if (ks * 16 < kvalid) {
+          bf4 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int kr = ks * 16 + 4 * (lane >> 4) + j;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              short x0, x1, x2;
+              bf16_split3((float)As[kr][wm * 32 + 16 * h + (lane & 15)], x0, x1, x2);
+              ah[h][j] = x0;
+              am[h][j] = x1;
+              al[h][j] = x2;
+              bf16_split3((float)Bs[kr][wn * 32 + 16 * h + (lane & 15)], x0, x1, x2);
+              bh[h][j] = x0;
+              bm[h][j] = x1;
+              bl[h][j] = x2;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int jj = 0; jj < 2; ++jj) {
+              // smallest terms first
+              V c = acc[i][jj];
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bm[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bh[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bm[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[jj], c, 0, 0, 0);
+              acc[i][jj] = c;
+            }
+        }
+      }
+    } else if constexpr (MODE == 1) {
 #pragma unroll
       for (int ks = 0; ks < GK / 16; ++ks) {
         if (ks * 16 < kvalid) {

@@ -96,7 +96,7 @@ struct SimT : Sim {
       for (int i = 0; i < 6; ++i) dom[d].fplane[i] = -1;
     }
     E.sweeps = c.sweeps;
-    E.bf16_products = (c.precision == MPS_LBM_BF16);
+    E.bf16_products = c.precision == MPS_LBM_BF16 ? 1 : c.precision == MPS_LBM_BF16X3 ? 2 : 0;
     E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
     if (c.rank_predictor) E.enable_rsvd(c.rank_oversample, c.seed);
     rho0 = (double*)E.dalloc(8 * (D + 8));
@@ -738,7 +738,7 @@ static int validate(const mps_lbm_config* c) {
   if (c->inv_rho_mode == MPS_LBM_INV_NEWTON && c->inv_rho_iters < 1)
     return fail(MPS_LBM_EINVAL, "inv_rho_iters < 1");
   if (c->precision != MPS_LBM_FP64 && c->precision != MPS_LBM_FP32 &&
-      c->precision != MPS_LBM_BF16)
+      c->precision != MPS_LBM_BF16 && c->precision != MPS_LBM_BF16X3)
     return fail(MPS_LBM_EINVAL, "unknown precision");
   if (c->sweeps < 1) return fail(MPS_LBM_EINVAL, "sweeps < 1");
   if (c->rank_predictor != 0 && c->rank_predictor != 1)

@@ -20,7 +20,7 @@ MAX_SITES = 10
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 D3Q19 = 19
-FP64, FP32, BF16 = 0, 1, 2
+FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
 INV_TAYLOR2, INV_NEWTON = 0, 1
 BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
 POPS, RHO, J, VEL = 0, 1, 2, 3
@@ -273,7 +273,7 @@ def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_
         for a in range(3):
             c.face_val[face][a] = float(case.face_val[face][a])
     prec = precision or case.precision
-    c.precision = {"fp64": FP64, "fp32": FP32, "bf16": BF16}[prec]
+    c.precision = {"fp64": FP64, "fp32": FP32, "bf16": BF16, "bf16x3": BF16X3}[prec]
     c.sweeps = sweeps
     c.inv_rho_mode = inv_mode
     c.inv_rho_iters = inv_iters

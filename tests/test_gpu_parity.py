@@ -251,6 +251,29 @@ def test_bf16_contraction_policy(which):
     assert rel(gf, d.f) < 5e-5
 
 
+@pytest.mark.parametrize("which", ["porous16", "vascular16"])
+def test_bf16x3_contraction_policy(which):
+    """BF16X3 policy (product contractions on BF16 MFMA with each FP32
+    operand split into three BF16 terms): the dropped terms are of relative
+    order 2^-24, so the untruncated open-face geometries stay at the FP32
+    policy's bound against the dense oracle."""
+    L = lib()
+    if which == "porous16":
+        case = WL.case_porous(n=4, chi=64, tol=1e-7)
+    else:
+        case = WL.case_vascular(n=4, chi=64, tol=1e-7)
+    case = _case_with_flow(case)
+    s3 = L.Simulation(case, precision="bf16x3")
+    d = DenseLBM(case)
+    for _ in range(2):
+        s3.step(1)
+        d.step()
+    g3 = s3.dense(L.POPS)
+    s3.close()
+    print(which, "bf16x3 vs dense", rel(g3, d.f), flush=True)
+    assert rel(g3, d.f) < 5e-5
+
+
 def test_rank_predictor_randomized_truncation():
     """Rank-predicted randomized truncation (FP32 policy) on a
     tolerance-limited 32^3 flow: sketches are attempted from the second step
