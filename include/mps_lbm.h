@@ -96,7 +96,9 @@ typedef struct {
   int rank_predictor;  /* 1: truncations are first tried on a randomized
                           sketch sized by the rank the same truncation chose
                           in the previous step, with exact-error acceptance
-                          and full fallback (FP32/BF16 only); 0: off        */
+                          and full fallback (FP32/BF16 only); 2: as 1, with
+                          the learned predictor below sizing the sketch once
+                          trained; 0: off                                   */
   int rank_oversample; /* sketch width = predicted rank + this (>= 1)       */
 } mps_lbm_config;
 
@@ -249,6 +251,48 @@ int mps_lbm_kernel_timing(mps_lbm_t* h, int kind);
 /* Statistics of the timed class since it was enabled (synchronises the
    stream).  Errors: EINVAL (NULL handle or out), EHIP. */
 int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out);
+
+/* ---- learned rank predictor (rank_predictor = 2) --------------------------
+   The rounding's truncations (FP32/BF16 policies) record, per truncation,
+   the spectrum around the cut: sigma_{r-16} .. sigma_{r+15} as
+   log10(sigma / sigma_1) / 8 (absent: -2) and the step index / 1000; each
+   later step adds a training sample (that record, the rank change / 16).
+   A multilayer perceptron 33 -> 128 -> 128 -> 128 -> 1 (ReLU, FP32) trained
+   on these samples then predicts the rank that sizes the randomised sketch
+   of the truncation (rank_predictor = 1 uses the previous rank); the
+   acceptance test and the full-path fallback are the same. */
+typedef struct {
+  long long samples;      /* training samples recorded (total)             */
+  int trained;            /* 1 once mps_lbm_train_rank_predictor ran        */
+  double first_loss;      /* mean squared error of the first epoch          */
+  double last_loss;       /* of the last epoch                              */
+  long long predictions;  /* predictions scored since the last training     */
+  double mlp_abs_err;     /* mean |predicted rank - chosen rank|, network   */
+  double prev_abs_err;    /* the same for the previous rank as prediction   */
+} mps_lbm_predictor_info;
+
+/* Train the network on the samples recorded so far: `epochs` passes of
+   Adam (beta 0.9, 0.999) with learning rate lr over batches of up to 1024,
+   on the handle's stream with the library's kernels; *loss_out (may be
+   NULL) receives the last epoch's mean squared error.  Synchronises the
+   stream.  Errors: EINVAL (NULL handle, epochs < 1, lr outside (0, 1), fewer
+   than 16 samples), EUNSUPPORTED (predictor not in mode 2, or after graph
+   capture). */
+int mps_lbm_train_rank_predictor(mps_lbm_t* h, int epochs, double lr, double* loss_out);
+
+/* Predictor statistics (all zero when the predictor is not in mode 2).
+   Errors: EINVAL (NULL handle or out), EHIP. */
+int mps_lbm_rank_predictor_info(mps_lbm_t* h, mps_lbm_predictor_info* out);
+
+/* One forward and backward pass of the predictor network on the current
+   device, for checking its gradients: params (host, 37505 floats in the
+   layout W1 (33 x 128, row i = input i), b1, W2 (128 x 128), b2, W3, b3,
+   W4 (128 x 1), b4), x (host, batch x 33), t (host, batch targets);
+   *loss receives mean (f(x) - t)^2 and grad (host, 37505 floats) its
+   gradient.  Allocates and frees its own device buffers.  Errors: EINVAL
+   (NULL pointer, batch outside [1, 1024]), ENOMEM, EHIP. */
+int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, int batch,
+                         float* loss, float* grad);
 
 /* Release every device buffer of the handle; NULL is ignored. */
 void mps_lbm_destroy(mps_lbm_t* h);

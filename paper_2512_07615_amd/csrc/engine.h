@@ -639,8 +639,12 @@ struct FnEigTrunc {
   const double* delta2; double* disc; int chi; int* fail;
   const int* s0 = nullptr;    // bond sizes before truncation (randomized path on)
   const int* skip = nullptr;  // problems already truncated by the randomized path
+  float* feat = nullptr;      // rank-predictor features of this bond (MLP_IN per problem)
+  float stepf = 0.0f;
   __device__ EigProb get(int i) const {
     EigProb p;
+    p.feat = feat ? feat + i * MLP_IN : nullptr;
+    p.stepf = stepf;
     p.A = Rp + i * sq;  // R P^T (c x s, row-major) read as its transpose
     p.s = s0 ? s0[i] : L.p[i]->r[k];
     p.c = crank[i];
@@ -884,11 +888,88 @@ class Engine {
     return std::min(scap, full_bound(n, k)) <= 64 ? 512 : 1024;
   }
 
+  // learned rank predictor: features of the last step per (call, bond,
+  // problem), a ring of training samples (features of step t, rank change
+  // from t to t + 1, divided by 16) and the network
+  static constexpr int SMP_CAP = 1 << 16;
+  bool mlp_on = false, mlp_trained = false;
+  Mlp mlp;
+  float* rs_feat = nullptr;  // [RS_CALLS][MAXN + 1][MAXB][MLP_IN]
+  float* smp_x = nullptr;    // [SMP_CAP][MLP_IN]
+  float* smp_t = nullptr;    // [SMP_CAP]
+  int* smp_n = nullptr;      // samples written (total)
+  int* smp_slot = nullptr;   // [MAXB] pending sample of each problem of a bond, -1: none
+  float* mlp_x = nullptr;    // [MAXB][MLP_IN] inputs of one bond
+  int* rs_pred2 = nullptr;   // [MAXB] ranks used to size the sketches of one bond
+  double* mlp_err = nullptr; // [3]: sum |rhat - r|, sum |r_prev - r|, count
+  long long step_count = 0;
+  float first_loss = -1.0f, last_loss = -1.0f;
+  void enable_mlp(unsigned long long seed) {
+    if (mlp_on) return;
+    mlp_on = true;
+    rs_feat = (float*)dalloc(4L * RS_CALLS * (MAXN + 1) * MAXB * MLP_IN);
+    smp_x = (float*)dalloc(4L * SMP_CAP * MLP_IN);
+    smp_t = (float*)dalloc(4L * SMP_CAP);
+    smp_n = (int*)dalloc(64);
+    smp_slot = (int*)dalloc(4L * MAXB);
+    mlp_x = (float*)dalloc(4L * MAXB * MLP_IN);
+    rs_pred2 = (int*)dalloc(4L * MAXB);
+    mlp_err = (double*)dalloc(64);
+    HIP_OK(hipMemset(smp_n, 0, 64));
+    HIP_OK(hipMemset(mlp_err, 0, 64));
+    mlp.setup(1024, [this](size_t b) { return dalloc(b); }, seed ^ 0x5EEDull, st);
+  }
+  // Adam epochs over the collected samples in batches of up to 1024;
+  // returns the mean squared error of the last epoch
+  float train_mlp(int epochs, float lr) {
+    int n = 0;
+    HIP_OK(hipMemcpyAsync(&n, smp_n, 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    n = std::min(n, SMP_CAP);
+    if (n < 16) throw Error(-1, "fewer than 16 predictor samples collected");
+    float loss_sum = 0.0f;
+    for (int ep = 0; ep < epochs; ++ep) {
+      loss_sum = 0.0f;
+      int nb = 0;
+      for (int off = 0; off < n; off += mlp.bmax) {
+        const int B = std::min(mlp.bmax, n - off);
+        mlp.forward(smp_x + (long)off * MLP_IN, B, st);
+        mlp.backward(smp_x + (long)off * MLP_IN, smp_t + off, B, st);
+        mlp.adam(lr, st);
+        float l = 0.0f;
+        HIP_OK(hipMemcpyAsync(&l, mlp.loss, 4, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        loss_sum += l;
+        ++nb;
+      }
+      loss_sum /= nb;
+      if (first_loss < 0.0f) first_loss = loss_sum;
+    }
+    last_loss = loss_sum;
+    mlp_trained = true;
+    HIP_OK(hipMemset(mlp_err, 0, 64));
+    return loss_sum;
+  }
+
   // randomized attempt at bond k of one rounding call (see rsvd.h)
-  void rs_attempt(MpsList<T> L, int k, int cnt, int* predk, int scap, int chi_cap) {
+  void rs_attempt(MpsList<T> L, int k, int cnt, int* predk, int scap, int chi_cap,
+                  float* featk) {
     const long sq = rw.sq;
     const int lds = lds_elems * 8;
-    hipLaunchKernelGGL(k_rs_plan<T>, dim3(cnt), dim3(256), 0, st, L, k, (const int*)predk, rs_over,
+    const int* plan = predk;
+    if (mlp_on) {
+      // inputs of this bond (last step's spectra), pending samples, and the
+      // network's ranks once it is trained
+      hipLaunchKernelGGL(k_mlp_gather, dim3(1), dim3(64), 0, st, (const float*)featk,
+                         (const int*)predk, mlp_x, smp_x, smp_t, smp_n, smp_slot, SMP_CAP, cnt);
+      if (mlp_trained) {
+        mlp.forward(mlp_x, cnt, st);
+        hipLaunchKernelGGL(k_mlp_rank<T>, dim3(1), dim3(64), 0, st, L, k, (const int*)predk,
+                           (const float*)mlp.y, rs_pred2, cnt);
+        plan = rs_pred2;
+      }
+    }
+    hipLaunchKernelGGL(k_rs_plan<T>, dim3(cnt), dim3(256), 0, st, L, k, plan, rs_over,
                        (const double*)cw.G, rw, cnt);
     typedef double D;
     launch_gemm<T, D, D, D>(FRsMOm<T>{L, k, rw}, cnt, scap, scap, 1, st);
@@ -909,8 +990,9 @@ class Engine {
     hipLaunchKernelGGL(k_rs_dims_T, dim3(1), dim3(64), 0, st, rw, rs_dims, cnt);
     hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rs_dims, 1, rw.T, sq,
                        rw.B, rw.R, rw.rankT, eps_rank, lds_elems, cnt, 0, (double*)nullptr, 0.0);
-    hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st, FnRsEig{rw, chi_cap, istats},
-                       rs_ep, cnt);
+    hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st,
+                       FnRsEig{rw, chi_cap, istats, featk, 0.001f * (float)step_count}, rs_ep,
+                       cnt);
     hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)), lds, st,
                        (const EigProb*)rs_ep, lds_elems, 40, (double*)nullptr, eig_orth_tol);
     hipLaunchKernelGGL(k_rs_accept<T>, dim3(1), dim3(64), 0, st, L, k, (const double*)rdelta,
@@ -1257,10 +1339,12 @@ class Engine {
     for (int k = n - 1; k >= 1 && fast; --k) {
       int scap = capb[k], ccap = PHYS * capb[k + 1];
       int* predk = rs_now ? rs_pred + ((long)call * (MAXN + 1) + k) * MAXB : nullptr;
+      float* featk =
+          (rs_now && mlp_on) ? rs_feat + (((long)call * (MAXN + 1) + k) * MAXB) * MLP_IN : nullptr;
       launch_gemm<T, T, double, double>(FGramM<T>{L, k, cw.G, cw.sq}, cnt, scap, scap, 1, st,
                                         nullptr, ksplit(cnt, scap, scap, 1, ccap));
       if (rs_now)
-        rs_attempt(L, k, cnt, predk, scap, chi_cap);
+        rs_attempt(L, k, cnt, predk, scap, chi_cap, featk);
       else
         hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
       tbegin(4);
@@ -1272,7 +1356,8 @@ class Engine {
                          FnEigTrunc<T>{L, k, cw.R1, cw.sq, (const int*)cw.rank, svdUS, svdWk,
                                        sus, rdelta, rdisc, chi_cap, istats,
                                        rs_now ? (const int*)rw.s0 : nullptr,
-                                       rs_now ? (const int*)rw.acc : nullptr},
+                                       rs_now ? (const int*)rw.acc : nullptr, featk,
+                                       0.001f * (float)step_count},
                          ep, cnt);
       tbegin(1);
       hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)),
@@ -1286,6 +1371,10 @@ class Engine {
                          qslot, k);
       hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp,
                          maxcore, k - 1);
+      if (rs_now && mlp_on)
+        hipLaunchKernelGGL(k_mlp_target<T>, dim3(1), dim3(64), 0, st, L, k, (const int*)predk,
+                           (const int*)rs_pred2, mlp_trained ? 1 : 0, smp_t, smp_slot, mlp_err,
+                           cnt);
       if (rs_now) hipLaunchKernelGGL(k_rs_store<T>, dim3(1), dim3(64), 0, st, L, k, predk, cnt);
     }
     for (int k = n - 1; k >= 1 && !fast; --k) {

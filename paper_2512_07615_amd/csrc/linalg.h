@@ -1272,6 +1272,8 @@ struct EigProb {
   double* Ut;
   double* disc;
   int* fail;
+  float* feat;   // when set: spectrum around the cut for the rank predictor
+  float stepf;   // step index / 1000, the predictor's last input
 };
 
 template <typename F>
@@ -1324,6 +1326,18 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   }
   __syncthreads();
   const int r = *rsel;
+  if (p.feat && tid <= 32) {
+    // log10(sigma_q / sigma_1) / 8 for q = r-16 .. r+15 (absent: -2), then
+    // the step feature
+    float f = p.stepf;
+    if (tid < 32) {
+      const int q = r - 16 + tid;
+      const double s1 = nrm[perm[0]];
+      const double v = (q >= 0 && q < c && s1 > 0.0) ? nrm[perm[q]] : 0.0;
+      f = v > 0.0 ? (float)fmax(log10(v / s1) / 8.0, -2.0) : -2.0f;
+    }
+    p.feat[tid] = f;
+  }
   for (long e = tid; e < (long)s * r; e += blockDim.x) {
     int row = (int)(e / r), j = (int)(e % r);
     double sg = nrm[perm[j]];

@@ -47,6 +47,8 @@ struct Sim {
   virtual int get_mps(int d, int which, double* out, size_t out_len, int* bonds) = 0;
   virtual long cells() const = 0;
   virtual void capture() = 0;
+  virtual float train_predictor(int epochs, float lr) = 0;
+  virtual void predictor_info(mps_lbm_predictor_info* o) = 0;
 };
 
 __global__ void k_div_vec(const double* num, const double* den, double* out, int cnt) {
@@ -99,6 +101,7 @@ struct SimT : Sim {
     E.bf16_products = c.precision == MPS_LBM_BF16 ? 1 : c.precision == MPS_LBM_BF16X3 ? 2 : 0;
     E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
     if (c.rank_predictor) E.enable_rsvd(c.rank_oversample, c.seed);
+    if (c.rank_predictor == 2) E.enable_mlp(c.seed);
     rho0 = (double*)E.dalloc(8 * (D + 8));
     nfl = (double*)E.dalloc(8 * (D + 8));
     scratch = (double*)E.dalloc(8 * (19 * D + 64));
@@ -514,6 +517,7 @@ struct SimT : Sim {
         step_once();
       }
       ++steps;
+      E.step_count = steps;
     }
     HIP_OK(hipGetLastError());
   }
@@ -630,6 +634,29 @@ struct SimT : Sim {
 
   void set_timing(int kind) override { E.timing(kind); }
 
+  float train_predictor(int epochs, float lr) override {
+    if (!E.mlp_on) throw Error(MPS_LBM_EUNSUPPORTED, "the learned rank predictor is off");
+    if (gexec) throw Error(MPS_LBM_EUNSUPPORTED, "training after graph capture");
+    return E.train_mlp(epochs, lr);
+  }
+
+  void predictor_info(mps_lbm_predictor_info* o) override {
+    memset(o, 0, sizeof(*o));
+    if (!E.mlp_on) return;
+    int nsmp = 0;
+    double err[3] = {0, 0, 0};
+    HIP_OK(hipMemcpyAsync(&nsmp, E.smp_n, 4, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(err, E.mlp_err, 24, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    o->samples = nsmp;
+    o->trained = E.mlp_trained ? 1 : 0;
+    o->first_loss = E.first_loss;
+    o->last_loss = E.last_loss;
+    o->predictions = (long long)err[2];
+    o->mlp_abs_err = err[2] > 0 ? err[0] / err[2] : 0.0;
+    o->prev_abs_err = err[2] > 0 ? err[1] / err[2] : 0.0;
+  }
+
   void kstats(mps_lbm_kstats* o) override {
     E.flush_events();
     double fl = 0.0;
@@ -741,8 +768,8 @@ static int validate(const mps_lbm_config* c) {
       c->precision != MPS_LBM_BF16 && c->precision != MPS_LBM_BF16X3)
     return fail(MPS_LBM_EINVAL, "unknown precision");
   if (c->sweeps < 1) return fail(MPS_LBM_EINVAL, "sweeps < 1");
-  if (c->rank_predictor != 0 && c->rank_predictor != 1)
-    return fail(MPS_LBM_EINVAL, "rank_predictor must be 0 or 1");
+  if (c->rank_predictor < 0 || c->rank_predictor > 2)
+    return fail(MPS_LBM_EINVAL, "rank_predictor must be 0, 1 or 2");
   if (c->rank_predictor && c->rank_oversample < 1)
     return fail(MPS_LBM_EINVAL, "rank_oversample < 1");
   if (c->rank_predictor && c->precision == MPS_LBM_FP64)
@@ -932,6 +959,64 @@ int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out) {
   } catch (const Error& e) {
     return fail(e.code, e.what());
   }
+}
+
+int mps_lbm_train_rank_predictor(mps_lbm_t* h, int epochs, double lr, double* loss_out) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (epochs < 1) return fail(MPS_LBM_EINVAL, "epochs < 1");
+  if (!(lr > 0.0) || !(lr < 1.0)) return fail(MPS_LBM_EINVAL, "lr outside (0, 1)");
+  try {
+    const float l = h->sim->train_predictor(epochs, (float)lr);
+    if (loss_out) *loss_out = l;
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int mps_lbm_rank_predictor_info(mps_lbm_t* h, mps_lbm_predictor_info* out) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  try {
+    h->sim->predictor_info(out);
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, int batch,
+                         float* loss, float* grad) {
+  if (!params || !x || !t || !loss || !grad) return fail(MPS_LBM_EINVAL, "NULL argument");
+  if (batch < 1 || batch > 1024) return fail(MPS_LBM_EINVAL, "batch outside [1, 1024]");
+  std::vector<void*> mem;
+  auto alloc = [&mem](size_t b) -> void* {
+    void* p = nullptr;
+    if (hipMalloc(&p, b) != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(MPS_LBM_ENOMEM, "device allocation failed");
+    }
+    mem.push_back(p);
+    return p;
+  };
+  int rc = MPS_LBM_OK;
+  try {
+    Mlp m;
+    m.setup(batch, alloc, 0, nullptr);
+    float* dx = (float*)alloc(4L * batch * MLP_IN);
+    float* dt = (float*)alloc(4L * batch);
+    HIP_OK(hipMemcpy(m.p, params, 4L * MLP_NPARAM, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(dx, x, 4L * batch * MLP_IN, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(dt, t, 4L * batch, hipMemcpyHostToDevice));
+    m.forward(dx, batch, nullptr);
+    m.backward(dx, dt, batch, nullptr);
+    HIP_OK(hipMemcpy(grad, m.g, 4L * MLP_NPARAM, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(loss, m.loss, 4, hipMemcpyDeviceToHost));
+  } catch (const Error& e) {
+    rc = fail(e.code, e.what());
+  }
+  for (void* p : mem) (void)hipFree(p);
+  return rc;
 }
 
 void mps_lbm_destroy(mps_lbm_t* h) { delete h; }

@@ -23,6 +23,7 @@
 // weight), so the rest of the rounding is unchanged.
 #pragma once
 #include "linalg.h"
+#include "mlp.h"
 
 namespace mpslbm {
 
@@ -191,8 +192,12 @@ __global__ void k_rs_dims_T(RsWork w, int* out, int cnt) {
 // eigen problem of T; rank and tail go to the sketch's own arrays
 struct FnRsEig {
   RsWork w; int chi; int* fail;
+  float* feat = nullptr;  // rank-predictor features (Ritz values of the sketch)
+  float stepf = 0.0f;
   __device__ EigProb get(int i) const {
     EigProb p;
+    p.feat = feat ? feat + i * MLP_IN : nullptr;
+    p.stepf = stepf;
     p.A = w.R + i * w.sq;  // R P^T of the Cholesky of T, read as its transpose
     p.s = w.rank2[i];
     p.c = w.rankT[i];
@@ -277,6 +282,65 @@ struct FRsUt {
     return d;
   }
 };
+
+// ---- learned rank predictor (see mlp.h) ------------------------------------
+// Inputs of one bond from the previous step's features, and a pending
+// training sample for every problem that has them (predk[i] > 0).
+__global__ void k_mlp_gather(const float* featk, const int* predk, float* x, float* smp_x,
+                             float* smp_t, int* smp_n, int* smp_slot, int cap, int cnt) {
+  const int i = threadIdx.x;
+  if (i >= cnt) return;
+  if (predk[i] <= 0) {
+    smp_slot[i] = -1;
+    for (int q = 0; q < MLP_IN; ++q) x[i * MLP_IN + q] = 0.0f;
+    return;
+  }
+  const int slot = atomicAdd(smp_n, 1) % cap;
+  for (int q = 0; q < MLP_IN; ++q) {
+    const float f = featk[i * MLP_IN + q];
+    x[i * MLP_IN + q] = f;
+    smp_x[(long)slot * MLP_IN + q] = f;
+  }
+  smp_t[slot] = 0.0f;
+  smp_slot[i] = slot;
+}
+
+// predicted rank: the previous rank plus 16 times the network's output,
+// within [1, current bond]; -1 where there is no previous rank
+template <typename T>
+__global__ void k_mlp_rank(MpsList<T> L, int k, const int* predk, const float* y, int* out,
+                           int cnt) {
+  const int i = threadIdx.x;
+  if (i >= cnt) return;
+  const int rp = predk[i];
+  if (rp <= 0) {
+    out[i] = -1;
+    return;
+  }
+  const int s = L.p[i]->r[k];
+  int r = rp + (int)lrintf(16.0f * y[i]);
+  out[i] = r < 1 ? 1 : (r > s ? s : r);
+}
+
+// after the truncation: targets of the pending samples (rank change / 16)
+// and, once trained, the absolute rank errors of the network and of the
+// previous-rank predictor
+template <typename T>
+__global__ void k_mlp_target(MpsList<T> L, int k, const int* predk, const int* pred2,
+                             int trained, float* smp_t, const int* smp_slot, double* err,
+                             int cnt) {
+  const int i = threadIdx.x;
+  if (i >= cnt) return;
+  const int slot = smp_slot[i];
+  if (slot < 0) return;
+  const int r = L.p[i]->r[k], rp = predk[i];
+  smp_t[slot] = (float)(r - rp) / 16.0f;
+  if (trained) {
+    atomicAdd(err, (double)abs(pred2[i] - r));
+    atomicAdd(err + 1, (double)abs(rp - r));
+    atomicAdd(err + 2, 1.0);
+  }
+}
 
 // the chosen ranks become the next step's predictions
 template <typename T>

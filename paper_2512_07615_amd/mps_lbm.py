@@ -33,7 +33,9 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_last_error", "mps_lbm_version", "mps_lbm_kernel_timing",
                    "mps_lbm_kernel_stats", "mps_lbm_get_mps", "mps_lbm_init_batch",
                    "mps_lbm_domains", "mps_lbm_to_dense_domain",
-                   "mps_lbm_observables_domain", "mps_lbm_capture_step"])
+                   "mps_lbm_observables_domain", "mps_lbm_capture_step",
+                   "mps_lbm_train_rank_predictor", "mps_lbm_rank_predictor_info",
+                   "mps_lbm_mlp_gradient"])
 
 
 class Config(C.Structure):
@@ -58,6 +60,16 @@ class Obs(C.Structure):
         ("jacobi_sweeps", C.c_double), ("lds_bytes", C.c_int),
         ("rs_attempted", C.c_longlong), ("rs_accepted", C.c_longlong),
     ]
+
+
+class PredictorInfo(C.Structure):
+    _fields_ = [("samples", C.c_longlong), ("trained", C.c_int), ("first_loss", C.c_double),
+                ("last_loss", C.c_double), ("predictions", C.c_longlong),
+                ("mlp_abs_err", C.c_double), ("prev_abs_err", C.c_double)]
+
+
+MLP_IN, MLP_H = 33, 128
+MLP_NPARAM = MLP_IN * MLP_H + MLP_H + 2 * (MLP_H * MLP_H + MLP_H) + MLP_H + 1
 
 
 class KStats(C.Structure):
@@ -111,6 +123,13 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_to_dense_domain.restype = C.c_int
     lib.mps_lbm_observables_domain.argtypes = [P, C.c_int, C.POINTER(Obs)]
     lib.mps_lbm_observables_domain.restype = C.c_int
+    FP = C.POINTER(C.c_float)
+    lib.mps_lbm_train_rank_predictor.argtypes = [P, C.c_int, C.c_double, DP]
+    lib.mps_lbm_train_rank_predictor.restype = C.c_int
+    lib.mps_lbm_rank_predictor_info.argtypes = [P, C.POINTER(PredictorInfo)]
+    lib.mps_lbm_rank_predictor_info.restype = C.c_int
+    lib.mps_lbm_mlp_gradient.argtypes = [FP, FP, FP, C.c_int, FP, FP]
+    lib.mps_lbm_mlp_gradient.restype = C.c_int
     _lib = lib
     return lib
 
@@ -151,6 +170,33 @@ def mps_lbm_init_from_field(cfg: Config, rho=None, u=None, f=None, solid=None,
     _check(lib.mps_lbm_init_from_field(C.byref(cfg), _dp(rho), _dp(u), _dp(f), s,
                                        C.c_void_p(hip_stream or 0), C.byref(h)))
     return h
+
+
+def mps_lbm_train_rank_predictor(h, epochs: int, lr: float) -> float:
+    loss = C.c_double()
+    _check(load().mps_lbm_train_rank_predictor(h, int(epochs), float(lr), C.byref(loss)))
+    return loss.value
+
+
+def mps_lbm_rank_predictor_info(h) -> PredictorInfo:
+    o = PredictorInfo()
+    _check(load().mps_lbm_rank_predictor_info(h, C.byref(o)))
+    return o
+
+
+def mps_lbm_mlp_gradient(params, x, t):
+    """Loss and gradient of the predictor network (FP32 arrays: params of
+    MLP_NPARAM, x of batch x 33, t of batch)."""
+    fp = C.POINTER(C.c_float)
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    t = np.ascontiguousarray(t, dtype=np.float32)
+    grad = np.zeros(MLP_NPARAM, dtype=np.float32)
+    loss = C.c_float()
+    _check(load().mps_lbm_mlp_gradient(params.ctypes.data_as(fp), x.ctypes.data_as(fp),
+                                       t.ctypes.data_as(fp), int(len(t)), C.byref(loss),
+                                       grad.ctypes.data_as(fp)))
+    return float(loss.value), grad
 
 
 def mps_lbm_step(h, nsteps: int = 1):
@@ -309,6 +355,12 @@ class BatchSimulation:
     def capture(self):
         mps_lbm_capture_step(self.h)
 
+    def train_predictor(self, epochs: int, lr: float) -> float:
+        return mps_lbm_train_rank_predictor(self.h, epochs, lr)
+
+    def predictor_info(self) -> PredictorInfo:
+        return mps_lbm_rank_predictor_info(self.h)
+
     def kernel_timing(self, kind):
         mps_lbm_kernel_timing(self.h, kind)
 
@@ -356,6 +408,12 @@ class Simulation:
 
     def capture(self):
         mps_lbm_capture_step(self.h)
+
+    def train_predictor(self, epochs: int, lr: float) -> float:
+        return mps_lbm_train_rank_predictor(self.h, epochs, lr)
+
+    def predictor_info(self) -> PredictorInfo:
+        return mps_lbm_rank_predictor_info(self.h)
 
     def close(self):
         if self.h:

@@ -59,7 +59,7 @@ def test_default_config_values():
 @pytest.mark.parametrize("field,value,code", [
     ("tau", 0.5, -1), ("tau", 0.3, -1), ("n", 1, -1), ("n", 11, -1), ("chi_max", 0, -1),
     ("lattice", 15, -1), ("precision", 7, -1), ("inv_rho_mode", 9, -1), ("sweeps", 0, -1),
-    ("chi_max", 4096, -5), ("rank_predictor", 2, -1), ("rank_predictor", 1, -5),
+    ("chi_max", 4096, -5), ("rank_predictor", 3, -1), ("rank_predictor", 1, -5),
 ])
 def test_invalid_config_rejected_before_device_use(field, value, code):
     L = lib()
@@ -136,3 +136,21 @@ def test_batch_init_validation_before_device_use():
     assert so.mps_lbm_domains(None) == L.EINVAL
     o = L.Obs()
     assert so.mps_lbm_observables_domain(None, 0, C.byref(o)) == L.EINVAL
+
+
+def test_predictor_entry_points_validate_without_gpu():
+    """The learned-predictor entry points reject bad arguments before any
+    device call."""
+    L = lib()
+    so = L.load()
+    fp = C.POINTER(C.c_float)
+    z = (C.c_float * 64)()
+    zp = C.cast(z, fp)
+    loss = C.c_float()
+    big = (C.c_float * L.MLP_NPARAM)()
+    assert so.mps_lbm_mlp_gradient(C.cast(big, fp), zp, zp, 0, C.byref(loss), C.cast(big, fp)) == -1
+    assert so.mps_lbm_mlp_gradient(C.cast(big, fp), zp, zp, 2000, C.byref(loss), C.cast(big, fp)) == -1
+    assert so.mps_lbm_mlp_gradient(None, zp, zp, 1, C.byref(loss), C.cast(big, fp)) == -1
+    assert so.mps_lbm_train_rank_predictor(None, 1, 1e-3, None) == -1
+    info = L.PredictorInfo()
+    assert so.mps_lbm_rank_predictor_info(None, C.byref(info)) == -1

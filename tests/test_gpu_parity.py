@@ -357,3 +357,62 @@ def test_porous64_full_size_step_vs_mps_oracle():
     assert du < 1e-4
     assert df < 1e-5
     assert dm < 1e-5
+
+
+def test_predictor_network_gradient_vs_oracle():
+    """Forward and backward kernels of the rank-predictor network (FP32)
+    against the FP64 numpy backpropagation of the oracle on the same
+    parameters and batch."""
+    from oracle import mlp as M
+    L = lib()
+    rng = np.random.default_rng(11)
+    p = np.zeros(M.NPARAM)
+    off = 0
+    for name, shape in M.SHAPES:
+        n = int(np.prod(shape))
+        p[off:off + n] = (rng.uniform(-1, 1, n) * np.sqrt(6.0 / shape[0]) if name.startswith("W")
+                          else rng.uniform(-0.1, 0.1, n))
+        off += n
+    p = p.astype(np.float32)
+    x = rng.uniform(-2, 0, (96, M.IN)).astype(np.float32)
+    t = rng.normal(0, 0.5, 96).astype(np.float32)
+    loss_g, grad_g = L.mps_lbm_mlp_gradient(p, x, t)
+    loss_o, grad_o = M.gradient(p.astype(np.float64), x.astype(np.float64), t.astype(np.float64))
+    rg = float(np.linalg.norm(grad_g - grad_o) / np.linalg.norm(grad_o))
+    print("network loss", loss_g, loss_o, "gradient rel L2", rg, flush=True)
+    assert abs(loss_g - loss_o) <= 1e-5 * max(1.0, loss_o)
+    assert rg < 1e-5
+
+
+def test_learned_rank_predictor_end_to_end():
+    """Learned predictor on a tolerance-limited 32^3 flow: spectra recorded
+    during steps train the network with the library's kernels (the loss
+    falls), its ranks then size the sketches, and the state stays within a
+    few tolerances of the run without the predictor; the mean rank errors of
+    the network and of the previous-rank prediction are reported."""
+    L = lib()
+    case = _case_with_flow(WL.case_channel(n=5, chi=64, tol=1e-5), seed=3)
+    on = L.Simulation(case, precision="fp32", rank_predictor=2)
+    off = L.Simulation(case, precision="fp32")
+    for _ in range(4):
+        on.step(1)
+        off.step(1)
+    i0 = on.predictor_info()
+    loss = on.train_predictor(150, 1e-3)
+    for _ in range(2):
+        on.step(1)
+        off.step(1)
+    i1 = on.predictor_info()
+    a, b = on.dense(L.POPS), off.dense(L.POPS)
+    o = on.observables()
+    on.close()
+    off.close()
+    d = float(np.sqrt(((a - b) ** 2).sum() / (b ** 2).sum()))
+    print("samples", i0.samples, "loss first/last", i1.first_loss, i1.last_loss, loss,
+          "predictions", i1.predictions, "mean |rank error| network", i1.mlp_abs_err,
+          "previous rank", i1.prev_abs_err, "sketches", o.rs_attempted, o.rs_accepted,
+          "rel L2 on/off", d, flush=True)
+    assert i0.samples > 100 and i1.trained == 1
+    assert i1.last_loss < 0.5 * i1.first_loss
+    assert i1.predictions > 0 and o.rs_accepted > 0
+    assert d < 50 * case.tol
