@@ -144,6 +144,9 @@ def main():
                     help="steps timed for the MFMA utilisation of the product GEMMs")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue the step kernel by kernel instead of replaying a HIP graph")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default split-K shares instead of tuning them after the "
+                         "warm-up steps")
     ap.add_argument("--predictor-steps", type=int, default=3,
                     help="steps timed with the rank-predicted randomized truncation "
                          "(0 = skip; FP32/BF16 workloads)")
@@ -170,6 +173,10 @@ def main():
         torch.cuda.synchronize()
         progress("warm-up step done")
     torch.cuda.synchronize()
+    tuned = 0
+    if not args.no_autotune and args.warmup > 0:
+        tuned = sim.autotune()
+        progress(f"autotuned {tuned} contraction classes")
     kind = {"jacobi": L.K_JACOBI, "householder": L.K_HOUSEHOLDER,
             "prodgemm": L.K_PRODGEMM, "cholesky": L.K_CHOLESKY}[args.roofline_kernel]
     sim.kernel_timing(kind)
@@ -199,7 +206,7 @@ def main():
                    "mask_bond": obs.mask_bond, "mask_trunc_err": obs.mask_trunc_err,
                    "roundings_per_step": obs.roundings, "products_per_step": obs.products,
                    "jacobi_sweeps_mean": obs.jacobi_sweeps, "jacobi_sweep_limit_hits": obs.svd_failures,
-                   "lds_bytes": obs.lds_bytes,
+                   "lds_bytes": obs.lds_bytes, "autotuned_classes": tuned,
                    "compression": obs.compression},
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)

@@ -252,6 +252,17 @@ int mps_lbm_kernel_timing(mps_lbm_t* h, int kind);
    stream).  Errors: EINVAL (NULL handle or out), EHIP. */
 int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out);
 
+/* Autotune the split of K of the long contractions (K capacity above
+   512): every contraction class met in the steps taken so far (arithmetic,
+   capacities M, N, K, problem and batch counts) is timed on scratch
+   operands of its capacity shape for 1, 2, 4 and 8 shares of K, and later
+   steps use the fastest (untuned classes use one share per 256 columns of
+   K).  Allocates and frees scratch memory; synchronises the stream.
+   *classes_tuned (may be NULL) receives the number of classes tuned.
+   Errors: EINVAL (NULL handle, no step taken), EUNSUPPORTED (after graph
+   capture), ENOMEM, EHIP. */
+int mps_lbm_autotune(mps_lbm_t* h, int* classes_tuned);
+
 /* ---- learned rank predictor (rank_predictor = 2) --------------------------
    The rounding's truncations (FP32/BF16 policies) record, per truncation,
    the spectrum around the cut: sigma_{r-16} .. sigma_{r+15} as

@@ -8,6 +8,9 @@
 #pragma once
 #include <type_traits>
 #include <algorithm>
+#include <map>
+#include <set>
+#include <tuple>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -1226,7 +1229,8 @@ class Engine {
   template <typename F>
   void pgemm(const F& f, int nprob, int mcap, int ncap, int bcap, hipStream_t s,
              double* flops = nullptr, int kcap = 0) {
-    const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap);
+    const int acc = bf16_products == 2 ? 3 : bf16_products == 1 ? 2 : sizeof(Tacc) == 8 ? 0 : 1;
+    const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap, acc);
     if constexpr (std::is_same<T, float>::value) {
       if (bf16_products == 1) {
         launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops, ks);
@@ -1240,22 +1244,122 @@ class Engine {
     launch_gemm<T, T, T, Tacc>(f, nprob, mcap, ncap, bcap, s, flops, ks);
   }
 
-  // Split of K for contractions whose K capacity is long: one share per 256
-  // columns of K, at most 8; the partial tiles go to a workspace that grows
-  // on demand (the first, eager step reaches its peak before any capture).
+  // Split of K for contractions whose K capacity exceeds 512: the share
+  // count comes from the autotuner's table for the contraction's class
+  // (arithmetic, capacities, problem and batch counts) once it has been
+  // tuned, else one share per 256 columns of K, at most 8.  The partial
+  // tiles go to a workspace that grows on demand (the first, eager step
+  // reaches its peak before any capture).
   double* kws = nullptr;
   size_t kws_bytes = 0;
-  KSplit ksplit(int nprob, int mcap, int ncap, int bcap, int kcap) {
-    int sp = kcap / 256;
-    if (sp > 8) sp = 8;
-    if (sp < 2 || nprob <= 0 || mcap <= 0 || ncap <= 0 || bcap <= 0) return KSplit{nullptr, 1};
+  typedef std::tuple<int, int, int, int, int, int> KClass;  // acc, m, n, k, nprob, batch
+  std::map<KClass, int> ktab;  // tuned share counts
+  std::set<KClass> kseen;      // classes met and not tuned yet
+  KSplit ksplit(int nprob, int mcap, int ncap, int bcap, int kcap, int acc = 0) {
+    if (kcap < 512 || nprob <= 0 || mcap <= 0 || ncap <= 0 || bcap <= 0) return KSplit{nullptr, 1};
+    const KClass key(acc, mcap, ncap, kcap, nprob, bcap);
+    int sp;
+    auto it = ktab.find(key);
+    if (it != ktab.end()) {
+      sp = it->second;
+    } else {
+      kseen.insert(key);
+      sp = std::min(8, kcap / 256);
+    }
+    if (sp < 2) return KSplit{nullptr, 1};
+    return KSplit{kworkspace(nprob, mcap, ncap, bcap, sp), sp};
+  }
+  double* kworkspace(int nprob, int mcap, int ncap, int bcap, int sp) {
     const size_t need = (size_t)nprob * bcap * ceil_div(mcap, GT) * ceil_div(ncap, GT) * sp *
                         GT * GT * sizeof(double);
     if (need > kws_bytes) {
       kws = (double*)dalloc(need);
       kws_bytes = need;
     }
-    return KSplit{kws, sp};
+    return kws;
+  }
+
+  // ---- split-K autotuner ----------------------------------------------------
+  // Every class met since the last tuning is timed at its capacity shape on
+  // scratch operands (one shared A and B, a C per problem and batch entry)
+  // for 1, 2, 4 and 8 shares of K (each share at least one slice of GK):
+  // one warm-up launch and three timed ones with HIP events per candidate;
+  // the fastest is kept.  Returns the number of classes tuned.
+  template <typename TA, int MODE>
+  struct FTune {
+    const TA* A; const TA* B; void* C; int M, N, K, nb;
+    __device__ GemmDesc<TA, TA, TA> get(int i) const {
+      GemmDesc<TA, TA, TA> d = gemm_empty<TA, TA, TA>();
+      d.A = A; d.B = B; d.C = (TA*)C + (long)i * nb * M * N;
+      d.M = M; d.N = N; d.K = K; d.nb1 = nb;
+      d.sAm = K; d.sAk = 1; d.sBk = N; d.sBn = 1; d.sCm = N; d.sCn = 1;
+      d.bC1 = (long)M * N;
+      d.valid = 1;
+      return d;
+    }
+  };
+  template <typename TA, typename Tacc, int MODE>
+  int tune_class(const KClass& c, void* A, void* B, void* C) {
+    int acc, m, nn, kk, np, nb;
+    std::tie(acc, m, nn, kk, np, nb) = c;
+    const FTune<TA, MODE> f{(const TA*)A, (const TA*)B, C, m, nn, kk, nb};
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best = 1;
+    float tbest = 1e30f;
+    for (int sp = 1; sp <= 8; sp *= 2) {
+      if (sp > 1 && (long)sp * GK > kk) break;
+      const KSplit ks = sp > 1 ? KSplit{kworkspace(np, m, nn, nb, sp), sp} : KSplit{nullptr, 1};
+      launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE>(f, np, m, nn, nb, st, nullptr, ks);
+      HIP_OK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r)
+        launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE>(f, np, m, nn, nb, st, nullptr, ks);
+      HIP_OK(hipEventRecord(e1, st));
+      HIP_OK(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < tbest) {
+        tbest = ms;
+        best = sp;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return best;
+  }
+  int autotune() {
+    int tuned = 0;
+    for (const KClass& c : kseen) {
+      if (ktab.count(c)) continue;
+      int acc, m, nn, kk, np, nb;
+      std::tie(acc, m, nn, kk, np, nb) = c;
+      const size_t ea = (size_t)m * kk, eb = (size_t)kk * nn, ec = (size_t)np * nb * m * nn;
+      const size_t w = acc == 0 ? 8 : 4;
+      void *A = nullptr, *B = nullptr, *C = nullptr;
+      if (hipMalloc(&A, w * ea) != hipSuccess || hipMalloc(&B, w * eb) != hipSuccess ||
+          hipMalloc(&C, w * ec) != hipSuccess) {
+        (void)hipGetLastError();
+        if (A) (void)hipFree(A);
+        if (B) (void)hipFree(B);
+        throw Error(-2, "autotuner scratch allocation failed");
+      }
+      HIP_OK(hipMemsetAsync(A, 0, w * ea, st));
+      HIP_OK(hipMemsetAsync(B, 0, w * eb, st));
+      int sp = 1;
+      if (acc == 0) sp = tune_class<double, double, 0>(c, A, B, C);
+      else if (acc == 1) sp = tune_class<float, float, 0>(c, A, B, C);
+      else if (acc == 2) sp = tune_class<float, float, 1>(c, A, B, C);
+      else sp = tune_class<float, float, 2>(c, A, B, C);
+      HIP_OK(hipStreamSynchronize(st));
+      (void)hipFree(A);
+      (void)hipFree(B);
+      (void)hipFree(C);
+      ktab[c] = sp;
+      ++tuned;
+    }
+    kseen.clear();
+    return tuned;
   }
 
   // ------------------------------------------------------------ QR op
@@ -1580,7 +1684,7 @@ class Engine {
                            p);
         tbegin(3);
         pgemm(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
-                                   cpb[p + 1] * cpb[p + 1], 1, st, kf(3));
+                                   cpb[p + 1] * cpb[p + 1], 1, st, kf(3), PHYS * cpb[p]);
         tend(3);
       } else {
         qr(FnQrRightT<T>{Dl, p, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[p + 1], cpb[p]);
@@ -1619,7 +1723,7 @@ class Engine {
                                kf(3));
     tend(3);
     tbegin(3);
-    pgemm(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3));
+    pgemm(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3), PHYS * cpb[p + 1]);
     tend(3);
   }
 

@@ -48,6 +48,7 @@ struct Sim {
   virtual long cells() const = 0;
   virtual void capture() = 0;
   virtual float train_predictor(int epochs, float lr) = 0;
+  virtual int autotune() = 0;
   virtual void predictor_info(mps_lbm_predictor_info* o) = 0;
 };
 
@@ -634,6 +635,12 @@ struct SimT : Sim {
 
   void set_timing(int kind) override { E.timing(kind); }
 
+  int autotune() override {
+    if (gexec) throw Error(MPS_LBM_EUNSUPPORTED, "autotuning after graph capture");
+    if (steps == 0) throw Error(MPS_LBM_EINVAL, "no step taken yet");
+    return E.autotune();
+  }
+
   float train_predictor(int epochs, float lr) override {
     if (!E.mlp_on) throw Error(MPS_LBM_EUNSUPPORTED, "the learned rank predictor is off");
     if (gexec) throw Error(MPS_LBM_EUNSUPPORTED, "training after graph capture");
@@ -968,6 +975,17 @@ int mps_lbm_train_rank_predictor(mps_lbm_t* h, int epochs, double lr, double* lo
   try {
     const float l = h->sim->train_predictor(epochs, (float)lr);
     if (loss_out) *loss_out = l;
+    return MPS_LBM_OK;
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  }
+}
+
+int mps_lbm_autotune(mps_lbm_t* h, int* classes_tuned) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  try {
+    const int n = h->sim->autotune();
+    if (classes_tuned) *classes_tuned = n;
     return MPS_LBM_OK;
   } catch (const Error& e) {
     return fail(e.code, e.what());

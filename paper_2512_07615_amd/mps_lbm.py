@@ -35,7 +35,7 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_domains", "mps_lbm_to_dense_domain",
                    "mps_lbm_observables_domain", "mps_lbm_capture_step",
                    "mps_lbm_train_rank_predictor", "mps_lbm_rank_predictor_info",
-                   "mps_lbm_mlp_gradient"])
+                   "mps_lbm_mlp_gradient", "mps_lbm_autotune"])
 
 
 class Config(C.Structure):
@@ -130,6 +130,8 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_rank_predictor_info.restype = C.c_int
     lib.mps_lbm_mlp_gradient.argtypes = [FP, FP, FP, C.c_int, FP, FP]
     lib.mps_lbm_mlp_gradient.restype = C.c_int
+    lib.mps_lbm_autotune.argtypes = [P, C.POINTER(C.c_int)]
+    lib.mps_lbm_autotune.restype = C.c_int
     _lib = lib
     return lib
 
@@ -176,6 +178,12 @@ def mps_lbm_train_rank_predictor(h, epochs: int, lr: float) -> float:
     loss = C.c_double()
     _check(load().mps_lbm_train_rank_predictor(h, int(epochs), float(lr), C.byref(loss)))
     return loss.value
+
+
+def mps_lbm_autotune(h) -> int:
+    n = C.c_int()
+    _check(load().mps_lbm_autotune(h, C.byref(n)))
+    return n.value
 
 
 def mps_lbm_rank_predictor_info(h) -> PredictorInfo:
@@ -358,6 +366,9 @@ class BatchSimulation:
     def train_predictor(self, epochs: int, lr: float) -> float:
         return mps_lbm_train_rank_predictor(self.h, epochs, lr)
 
+    def autotune(self) -> int:
+        return mps_lbm_autotune(self.h)
+
     def predictor_info(self) -> PredictorInfo:
         return mps_lbm_rank_predictor_info(self.h)
 
@@ -411,6 +422,9 @@ class Simulation:
 
     def train_predictor(self, epochs: int, lr: float) -> float:
         return mps_lbm_train_rank_predictor(self.h, epochs, lr)
+
+    def autotune(self) -> int:
+        return mps_lbm_autotune(self.h)
 
     def predictor_info(self) -> PredictorInfo:
         return mps_lbm_rank_predictor_info(self.h)

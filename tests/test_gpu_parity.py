@@ -416,3 +416,26 @@ def test_learned_rank_predictor_end_to_end():
     assert i1.last_loss < 0.5 * i1.first_loss
     assert i1.predictions > 0 and o.rs_accepted > 0
     assert d < 50 * case.tol
+
+
+def test_split_autotuner_keeps_the_step():
+    """The split-K autotuner retimes the long contractions met in a step and
+    picks their share counts; the step it then runs differs from the
+    untuned one only by the summation order of those contractions."""
+    L = lib()
+    case = _case_with_flow(WL.case_porous(n=5, chi=64, tol=1e-8), seed=4)
+    a = L.Simulation(case, precision="fp32")
+    b = L.Simulation(case, precision="fp32")
+    a.step(1)
+    b.step(1)
+    tuned = a.autotune()
+    for _ in range(2):
+        a.step(1)
+        b.step(1)
+    fa, fb = a.dense(L.POPS), b.dense(L.POPS)
+    a.close()
+    b.close()
+    d = float(np.sqrt(((fa - fb) ** 2).sum() / (fb ** 2).sum()))
+    print("classes tuned", tuned, "rel L2 tuned/untuned", d, flush=True)
+    assert tuned > 0
+    assert d < 1e-4
