@@ -7,6 +7,7 @@ products, BGK sums, streaming, open faces, bounce-back, all roundings) on
 the synthetic workload, inputs resident in HBM.  Prints one JSON line.
 """
 import argparse
+import re
 import json
 import os
 import sys
@@ -109,6 +110,28 @@ def batched_rate(case, count, stream, steps):
             "equiv_mlups": count * case.N ** 3 * 1000.0 / ms / 1e6}
 
 
+def stored_traffic(kind, workload):
+    """HBM bytes per launch of the roofline kernel from the committed
+    rocprofv3 counter summary, when it covers this kernel and workload and
+    the kernel's sources still hash to what was measured; else None."""
+    import hashlib
+    if kind != "jacobi" or workload != "porous64":
+        return None
+    root = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(root, "profiles", "porous64_fp32_jacobi_hbm_traffic.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    fields = dict(re.findall(r"^(source_sha256|traffic_bytes_per_launch): (\S+)$", text, re.M))
+    h = hashlib.sha256()
+    for f in ("paper_2512_07615_amd/csrc/linalg.h", "paper_2512_07615_amd/csrc/common.h"):
+        h.update(open(os.path.join(root, f), "rb").read())
+    if fields.get("source_sha256") != h.hexdigest() or "traffic_bytes_per_launch" not in fields:
+        return None
+    return float(fields["traffic_bytes_per_launch"])
+
+
 def roofline(kind, ks, prec):
     """Roofline entry of the timed kernel class from its event-timed launches
     and device-counted algorithmic flops."""
@@ -144,6 +167,9 @@ def main():
                     help="steps timed for the MFMA utilisation of the product GEMMs")
     ap.add_argument("--no-graph", action="store_true",
                     help="issue the step kernel by kernel instead of replaying a HIP graph")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain elementwise copy of 256 MiB three times (the "
+                         "reference for scaling rocprofv3's FETCH_SIZE / WRITE_SIZE)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default split-K shares instead of tuning them after the "
                          "warm-up steps")
@@ -165,6 +191,15 @@ def main():
 
     case = make_case(args.workload)
     stream = torch.cuda.Stream()
+    if args.copy_calibration:
+        # y = x * 1 over 256 MiB of FP32: reads and writes 256 MiB per launch
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(3):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        del x, y
+        progress("copy calibration: 3 launches of 256 MiB read + 256 MiB written")
     t_init = time.perf_counter()
     sim = L.Simulation(case, hip_stream=stream.cuda_stream)
     progress(f"{case.name}: initialised in {time.perf_counter() - t_init:.1f} s")
@@ -210,6 +245,7 @@ def main():
                    "compression": obs.compression},
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)
+    out["roofline"]["traffic"] = stored_traffic(args.roofline_kernel, args.workload)
     out["roofline"]["share_of_step"] = ks.total_ms / (ms * args.steps)
     if args.mfma_steps > 0:
         # MFMA utilisation of the product contractions, timed the same way
