@@ -1432,9 +1432,8 @@ class Engine {
                                         PHYS * capb[k + 2], 1, st);
       hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, L,
                          (const QrProb<T>*)qp, k + 1, cnt);
-      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)qtmp, qslot, k);
-      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp, maxcore,
-                         k + 1);
+      hipLaunchKernelGGL(k_store_core2<T>, dim3(chunks(), cnt, 2), blk, 0, st, L, (const T*)qtmp,
+                         qslot, k, (const T*)ctmp, maxcore, k + 1);
     }
     hipLaunchKernelGGL(k_round_threshold<T>, dim3(cnt), blk, 0, st, L, tol_r, rdelta, rnorm, cnt);
     hipLaunchKernelGGL(k_fill_f64, dim3(3), dim3(256), 0, st, rdisc, 0.0, (long)MAXB * (MAXN + 1));
@@ -1471,10 +1470,8 @@ class Engine {
       launch_gemm<double, T, T, double>(FUtM<T>{L, ep, qtmp, qslot, k}, cnt, scap, ccap, 1, st);
       launch_gemm<T, double, T, double>(FCoreUS2<T>{L, ep, ctmp, maxcore, k}, cnt,
                                         PHYS * capb[k - 1], scap, 1, st);
-      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)qtmp,
-                         qslot, k);
-      hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, L, (const T*)ctmp,
-                         maxcore, k - 1);
+      hipLaunchKernelGGL(k_store_core2<T>, dim3(chunks(), cnt, 2), blk, 0, st, L, (const T*)qtmp,
+                         qslot, k, (const T*)ctmp, maxcore, k - 1);
       if (rs_now && mlp_on)
         hipLaunchKernelGGL(k_mlp_target<T>, dim3(1), dim3(64), 0, st, L, k, (const int*)predk,
                            (const int*)rs_pred2, mlp_trained ? 1 : 0, smp_t, smp_slot, mlp_err,

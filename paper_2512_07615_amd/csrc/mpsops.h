@@ -249,6 +249,21 @@ __global__ __launch_bounds__(256) void k_round_threshold(MpsList<T> src, double 
 
 // Copy a packed matrix (rows x cols at ld cols) from a workspace into core k
 // of each MPS (the shape is taken from the MPS ranks after the update).
+// Two such copies in one launch (blockIdx.z picks the pair member); the
+// cores have fixed slots, so the two never overlap.
+template <typename T>
+__global__ void k_store_core2(MpsList<T> dst, const T* tmp0, long slot0, int k0, const T* tmp1,
+                              long slot1, int k1) {
+  const int pr = blockIdx.y, k = blockIdx.z ? k1 : k0;
+  MpsDev<T>* d = dst.p[pr];
+  const long tot = (long)d->r[k] * PHYS * d->r[k + 1];
+  const T* s = (blockIdx.z ? tmp1 + pr * slot1 : tmp0 + pr * slot0);
+  T* o = core_ptr(d, k);
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x)
+    o[e] = s[e];
+}
+
 template <typename T>
 __global__ void k_store_core(MpsList<T> dst, const T* tmp, long slot, int k) {
   int pr = blockIdx.y;
