@@ -439,3 +439,70 @@ def test_split_autotuner_keeps_the_step():
     print("classes tuned", tuned, "rel L2 tuned/untuned", d, flush=True)
     assert tuned > 0
     assert d < 1e-4
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-10), ("fp32", 5e-5)])
+def test_minimum_size_4cubed(prec, bound):
+    """The smallest grid (4^3, two sites per MPS: one bond, of rank at most
+    8) with walls and a body force, untruncated, against the dense oracle."""
+    L = lib()
+    case = _case_with_flow(WL.case_channel(n=2, chi=64, tol=1e-13), seed=5)
+    s = L.Simulation(case, precision=prec)
+    d = DenseLBM(case)
+    for _ in range(2):
+        s.step(1)
+        d.step()
+    g = s.dense(L.POPS)
+    s.close()
+    print("4^3", prec, "rel vs dense", rel(g, d.f), flush=True)
+    assert rel(g, d.f) < bound
+
+
+def test_rest_state_rank_one_fixed_point():
+    """Degenerate inputs at the benchmark's grid size: an all-fluid periodic
+    64^3 box at rest (uniform density, no force, no solid cell, so the mask
+    MPS is zero) held at chi = 1.  The equilibrium at rest is a fixed point
+    of the step, and every MPS is rank one, so three steps must return the
+    initial populations w_i with every bond at 1."""
+    L = lib()
+    n = 6
+    N = 1 << n
+    case = WL.Case(name="rest64", n=n, tau=0.8, chi=1, tol=1e-8,
+                   solid=np.zeros((N, N, N), dtype=np.uint8), precision="fp32")
+    s = L.Simulation(case)
+    f0 = s.dense(L.POPS)
+    s.step(3)
+    f3 = s.dense(L.POPS)
+    o = s.observables()
+    s.close()
+    w = np.array([1 / 3] + [1 / 18] * 6 + [1 / 36] * 12)
+    print("rest state: max |f3 - f0|", float(np.abs(f3 - f0).max()), "max bond", o.max_bond,
+          flush=True)
+    assert np.abs(np.sort(f0.reshape(19, -1).mean(axis=1)) - np.sort(w)).max() < 1e-6
+    assert np.abs(f3 - f0).max() < 1e-6
+    assert o.max_bond == 1
+
+
+def test_vascular128_full_size_velocity_vs_fp64():
+    """The 128^3, chi = 128 branching-tube configuration (velocity inlet,
+    pressure outlet) at full size: FP32 and BF16X3 against the library's
+    FP64 policy (itself pinned to the oracle at smaller sizes), two steps
+    from a seeded flow; velocity within the 1e-4 relative L2 asked of the
+    reduced-precision step, on fluid cells."""
+    from oracle.dense_lbm import moments
+    L = lib()
+    case = _case_with_flow(WL.case_vascular(n=7, chi=128, tau=0.55, tol=1e-8))
+    fluid = ~np.asarray(case.solid, dtype=bool)
+    u = {}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        s = L.Simulation(case, precision=prec)
+        s.step(2)
+        f = s.dense(L.POPS).astype(np.float64)
+        s.close()
+        r, j = moments(f)
+        u[prec] = j[:, fluid] / r[fluid]
+        del f
+    for prec in ("fp32", "bf16x3"):
+        du = _vel_rel_l2(u[prec], u["fp64"])
+        print("vascular128", prec, "velocity rel L2 vs fp64", du, flush=True)
+        assert du < 1e-4
