@@ -884,11 +884,12 @@ class Engine {
 
   // Threads of the truncation's Jacobi at bond k: the columns it rotates
   // number at most the rank of the unfolding, which the full bound of the
-  // bond caps below the storage capacity (twice the bond for sums); up to 64
-  // columns, 512 threads give 16 lanes per pair, which keep every row of a
-  // column up to 128 in registers.
+  // bond caps below the storage capacity (twice the bond for sums); 16 lanes
+  // per pair (every row of a column up to 128 in registers) for up to 8, 32,
+  // 64 or 128 columns take one, four, eight or sixteen waves.
   int eig_threads(int scap, int k) const {
-    return std::min(scap, full_bound(n, k)) <= 64 ? 512 : 1024;
+    const int c = std::min(scap, full_bound(n, k));
+    return c <= 8 ? 64 : c <= 32 ? 256 : c <= 64 ? 512 : 1024;
   }
 
   // learned rank predictor: features of the last step per (call, bond,
