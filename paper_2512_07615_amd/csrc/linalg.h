@@ -1095,7 +1095,7 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
   for (; sweep < max_sweeps; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
-    int rot = 0;
+    float mx = 0.0f;  // largest relative coupling this thread rotated away
     for (int S = P; S >= 2; S >>= 1) {
       const int h = S / 2, j = g / h, u = g % h;
       const int ri = j * S + u;  // resident column of this phase
@@ -1132,6 +1132,7 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
         // same test and rotation as the round-robin sweeps, with the column
         // of smaller index as the first of the pair
         if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
+          mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
           const bool rfirst = ri < ti;
           const double aa = rfirst ? al : be, bb = rfirst ? be : al;
           // one Newton-Raphson step on each hardware estimate (relative
@@ -1171,7 +1172,6 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
           // the resident's new norm (all lanes of the group take this branch)
           al = group_sum(nal, G);
           if (gl == 0) work += 6.0 * m;
-          rot = 1;
         }
         __syncthreads();
       }
@@ -1182,11 +1182,19 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
       }
       __syncthreads();
     }
-    if (rot) *flag = 1;  // every writer stores the same value
+    // the sweep's largest coupling (positive floats order as their bits)
+    if (mx > 0.0f) atomicMax(flag, __float_as_int(mx));
     __syncthreads();
     const int any = *flag;
     __syncthreads();
     if (!any) break;
+    // Jacobi sweeps converge quadratically: once every rotated pair of a
+    // sweep was coupled by less than sqrt(tol) / 10, the next sweep would
+    // meet couplings of order tol / 100 and rotate nothing
+    if (__int_as_float(any) < (float)(0.1 * sqrt(tol))) {
+      ++sweep;
+      break;
+    }
   }
   return sweep;
 }
