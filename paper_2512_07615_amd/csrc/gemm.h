@@ -302,21 +302,32 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
   int b1 = b % d.nb1, b2 = b / d.nb1;
   TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
   const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (GT * GT);
-  for (int e = threadIdx.x; e < GT * GT; e += blockDim.x) {
-    const int row = ti * GT + e / GT, col = tj * GT + e % GT;
-    if (row >= d.M || col >= d.N) continue;
-    // the shares' loads are issued together, then summed in share order
-    double v[8];
+  // four outputs per pass, the loads of all their shares issued together,
+  // then each output summed in share order
+  constexpr int OUT = 4;
+  for (int e0 = threadIdx.x; e0 < GT * GT; e0 += OUT * blockDim.x) {
+    double v[OUT][8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = q < ks.split ? W[(long)q * (GT * GT) + e] : 0.0;
-    double sum = 0.0;
+    for (int o = 0; o < OUT; ++o) {
+      const int e = e0 + o * blockDim.x;
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-      if (q < ks.split) sum += v[q];
-    TC* p = C + row * d.sCm + col * d.sCn;
-    double val = d.alpha * sum;
-    if (d.beta != 0.0) val += d.beta * (double)(*p);
-    *p = (TC)val;
+      for (int q = 0; q < 8; ++q)
+        v[o][q] = (e < GT * GT && q < ks.split) ? W[(long)q * (GT * GT) + e] : 0.0;
+    }
+#pragma unroll
+    for (int o = 0; o < OUT; ++o) {
+      const int e = e0 + o * blockDim.x;
+      const int row = ti * GT + e / GT, col = tj * GT + e % GT;
+      if (e >= GT * GT || row >= d.M || col >= d.N) continue;
+      double sum = 0.0;
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < ks.split) sum += v[o][q];
+      TC* p = C + row * d.sCm + col * d.sCn;
+      double val = d.alpha * sum;
+      if (d.beta != 0.0) val += d.beta * (double)(*p);
+      *p = (TC)val;
+    }
   }
 }
 
