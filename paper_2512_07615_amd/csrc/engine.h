@@ -1742,16 +1742,35 @@ class Engine {
     HIP_OK(hipGetLastError());
   }
 
-  // Streaming f_new(x) = f(x - c) one axis at a time (x, y, z order), each
-  // shift followed by rounding.  Returns fresh objects.
+  // A two-term sum ca a + cb b, rounded.
+  struct PairSum {
+    Coef ca;
+    int a;
+    Coef cb;
+    int b;
+  };
+
+  // Streaming f_new(x) = f(x - c): every item is shifted along its nonzero
+  // axes in x, y, z order, each shift followed by rounding.  Level L of the
+  // batch holds the L-th shift of every item, so each item sees the same
+  // sequence of operations as in an axis-by-axis schedule, in as many levels
+  // as an item has nonzero components (two for D3Q19).  The pair sums, if
+  // any, are assembled and rounded together with the first level; their
+  // results go to *pair_out.  Returns fresh objects.
   std::vector<int> stream(const std::vector<int>& src, const std::vector<const int*>& cvec,
-                          const std::vector<const int*>& axis_open) {
+                          const std::vector<const int*>& axis_open, const double* rho0 = nullptr,
+                          const std::vector<PairSum>& pairs = {},
+                          std::vector<int>* pair_out = nullptr) {
     std::vector<int> cur = src;
     std::vector<bool> owned(src.size(), false);
-    for (int ax = 0; ax < 3; ++ax) {
+    std::vector<int> next_ax(src.size(), 0);
+    for (int level = 0; level < 3; ++level) {
       std::vector<int> dst, s, a, d, cy, who;
       for (size_t i = 0; i < src.size(); ++i) {
-        if (cvec[i][ax] == 0) continue;
+        int ax = next_ax[i];
+        while (ax < 3 && cvec[i][ax] == 0) ++ax;
+        next_ax[i] = ax < 3 ? ax + 1 : 3;
+        if (ax == 3) continue;
         dst.push_back(acquire());
         s.push_back(cur[i]);
         a.push_back(ax);
@@ -1759,9 +1778,25 @@ class Engine {
         cy.push_back(axis_open[i][ax] ? 0 : 1);
         who.push_back((int)i);
       }
-      if (dst.empty()) continue;
-      shift(dst, s, a, d, cy);
-      round(dst);
+      std::vector<int> pd;
+      if (level == 0 && !pairs.empty()) {
+        std::vector<int> pa, pb;
+        std::vector<Coef> pc;
+        for (const PairSum& q : pairs) {
+          pd.push_back(acquire());
+          pa.push_back(q.a);
+          pb.push_back(q.b);
+          pc.push_back(q.ca);
+          pc.push_back(q.cb);
+        }
+        add(pd, pa, pb, pc, rho0);
+        if (pair_out) *pair_out = pd;
+      }
+      if (dst.empty() && pd.empty()) break;
+      if (!dst.empty()) shift(dst, s, a, d, cy);
+      std::vector<int> all = dst;
+      all.insert(all.end(), pd.begin(), pd.end());
+      round(all);
       for (size_t j = 0; j < who.size(); ++j) {
         int i = who[j];
         if (owned[i]) release(cur[i]);

@@ -14,6 +14,12 @@
 //  8. obstacles: f_i <- f_i - m_O (.) f_i + S(c_i)(m_O (.) f_ihat).
 // Every sum is a pairwise tree (adjacent pairs, odd last term carried up)
 // rounded after each addition; the CPU oracle follows the same schedule.
+// Roundings that do not depend on each other share one batch: the j_eq sums
+// run with the first sums of step 3, each population's streaming shifts are
+// batched by their order (two levels for D3Q19), and the first pair of the
+// obstacle sum runs with the first shift level of the reflected part.  This
+// changes which launch carries an operation, never the operations applied to
+// one MPS or their order.
 #include "../../include/mps_lbm.h"
 
 #include <array>
@@ -73,6 +79,7 @@ struct Domain {
 template <typename T>
 struct SimT : Sim {
   typedef typename Engine<T>::Term Term;
+  typedef typename Engine<T>::PairSum PairSum;
   Engine<T> E;
   hipStream_t st;
   int n, N, D;
@@ -242,13 +249,40 @@ struct SimT : Sim {
     E.inner_ones(rho, scratch);
     hipLaunchKernelGGL(k_div_vec, dim3(1), dim3(std::max(64, ((D + 63) / 64) * 64)), 0, st,
                        (const double*)scratch, (const double*)nfl, rho0, D);
+    // 4a. j_eq = j + tau g rho on the forced axes; these sums need only the
+    // moments, so they are rounded together with the first sums of step 3
+    std::vector<int> jeq(3 * D);
+    std::vector<std::vector<Term>> SJ;
+    std::vector<int> which;
+    for (int d = 0; d < D; ++d)
+      for (int a = 0; a < 3; ++a) {
+        const double ga = dom[d].cfg.g[a];
+        if (ga != 0.0) {
+          SJ.push_back({{Coef{1.0, 0, d}, j[3 * d + a]}, {Coef{dom[d].cfg.tau * ga, 0, d}, rho[d]}});
+          which.push_back(3 * d + a);
+        } else {
+          jeq[3 * d + a] = j[3 * d + a];
+        }
+      }
+    // the sums SF followed by SJ in one batch; the j_eq results are placed
+    // into jeq and the first D results returned
+    auto with_jeq = [&](std::vector<std::vector<Term>> SF) {
+      SF.insert(SF.end(), SJ.begin(), SJ.end());
+      std::vector<int> o = E.sums(SF, rho0);
+      for (size_t q = 0; q < which.size(); ++q) {
+        E.release(j[which[q]]);
+        jeq[which[q]] = o[D + q];
+      }
+      o.resize(D);
+      return o;
+    };
     // 3. inverse density (every domain of a handle uses the same mode)
     const mps_lbm_config& c0 = dom[0].cfg;
     std::vector<int> r(D);
     if (c0.inv_rho_mode == MPS_LBM_INV_TAYLOR2) {
       std::vector<std::vector<Term>> SE(D);
       for (int d = 0; d < D; ++d) SE[d] = {{Coef{1.0, -1, d}, rho[d]}, {Coef{-1.0, 0, d}, one}};
-      std::vector<int> e = E.sums(SE, rho0);
+      std::vector<int> e = with_jeq(SE);
       std::vector<std::pair<int, int>> pe;
       for (int d = 0; d < D; ++d) pe.push_back({e[d], e[d]});
       std::vector<int> ee = E.prods(pe);
@@ -263,7 +297,7 @@ struct SimT : Sim {
     } else {
       std::vector<std::vector<Term>> SY(D);
       for (int d = 0; d < D; ++d) SY[d] = {{Coef{2.0, -1, d}, one}, {Coef{-1.0, -2, d}, rho[d]}};
-      std::vector<int> y = E.sums(SY, rho0);
+      std::vector<int> y = with_jeq(SY);
       for (int it = 1; it < c0.inv_rho_iters; ++it) {
         std::vector<std::pair<int, int>> p1;
         for (int d = 0; d < D; ++d) p1.push_back({rho[d], y[d]});
@@ -283,30 +317,7 @@ struct SimT : Sim {
       }
       r = y;
     }
-    // 4. j_eq = j + tau g rho, u = j_eq (.) r, Pi_ab = j_eq,a (.) u_b
-    std::vector<int> jeq(3 * D);
-    {
-      std::vector<std::vector<Term>> SJ;
-      std::vector<int> which;
-      for (int d = 0; d < D; ++d)
-        for (int a = 0; a < 3; ++a) {
-          const double ga = dom[d].cfg.g[a];
-          if (ga != 0.0) {
-            SJ.push_back({{Coef{1.0, 0, d}, j[3 * d + a]},
-                          {Coef{dom[d].cfg.tau * ga, 0, d}, rho[d]}});
-            which.push_back(3 * d + a);
-          } else {
-            jeq[3 * d + a] = j[3 * d + a];
-          }
-        }
-      if (!SJ.empty()) {
-        std::vector<int> o = E.sums(SJ, rho0);
-        for (size_t q = 0; q < which.size(); ++q) {
-          E.release(j[which[q]]);
-          jeq[which[q]] = o[q];
-        }
-      }
-    }
+    // 4b. u = j_eq (.) r, Pi_ab = j_eq,a (.) u_b
     std::vector<std::pair<int, int>> pu;
     for (int d = 0; d < D; ++d)
       for (int a = 0; a < 3; ++a) pu.push_back({jeq[3 * d + a], r[d]});
@@ -483,13 +494,21 @@ struct SimT : Sim {
             hc.push_back(kC[i]);
             ha.push_back(dom[dd[k]].cfg.axis_open);
           }
-        std::vector<int> h = E.stream(hs, hc, ha);
+        // the sum f_i - g1_i + h_i is a pairwise tree: its first pair
+        // (f_i - g1_i) is rounded together with the first shift level of h
+        std::vector<PairSum> pre;
+        for (size_t k = 0; k < dd.size(); ++k) {
+          const int d = dd[k];
+          for (int i = 1; i < 19; ++i)
+            pre.push_back({Coef{1.0, 0, d}, fs[19 * d + i], Coef{-1.0, 0, d}, g1[18 * k + i - 1]});
+        }
+        std::vector<int> fg;
+        std::vector<int> h = E.stream(hs, hc, ha, rho0, pre, &fg);
         std::vector<std::vector<Term>> SO;
         for (size_t k = 0; k < dd.size(); ++k) {
           const int d = dd[k];
           for (int i = 1; i < 19; ++i)
-            SO.push_back({{Coef{1.0, 0, d}, fs[19 * d + i]},
-                          {Coef{-1.0, 0, d}, g1[18 * k + i - 1]},
+            SO.push_back({{Coef{1.0, 0, d}, fg[18 * k + i - 1]},
                           {Coef{1.0, 0, d}, h[18 * k + i - 1]}});
         }
         std::vector<int> o = E.sums(SO, rho0);
@@ -499,6 +518,7 @@ struct SimT : Sim {
             E.release(fs[19 * d + i]);
             E.release(g1[18 * k + i - 1]);
             E.release(h[18 * k + i - 1]);
+            E.release(fg[18 * k + i - 1]);
             fs[19 * d + i] = o[18 * k + i - 1];
           }
         }
