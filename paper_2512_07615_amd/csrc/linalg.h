@@ -1082,7 +1082,7 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
 // two can use it too.
 __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int max_sweeps,
                                                   double tol, double small2, double& work,
-                                                  int* flag) {
+                                                  int* flag, double* tn) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nwaves = blockDim.x >> 6;
   int P = 1;
@@ -1123,12 +1123,23 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
         for (int q = 0; q < 8; ++q) {
           const int r = gl + q * G;
           yr[q] = (act && r < m) ? cb[r] : 0.0;
-          be += yr[q] * yr[q];
           ga += xr[q] * yr[q];
         }
-        be = group_sum(be, G);
+        // the travelling column's norm: computed when the phase starts
+        // (t = 0), then carried in tn by the group that last rotated it
+        if (t == 0) {
+#pragma unroll
+          for (int q = 0; q < 8; ++q) be += yr[q] * yr[q];
+          be = group_sum(be, G);
+          if (act && gl == 0) {
+            tn[ti] = be;
+            work += 2.0 * m;
+          }
+        } else {
+          be = act ? tn[ti] : 0.0;
+        }
         ga = group_sum(ga, G);
-        if (act && gl == 0) work += 6.0 * m;
+        if (act && gl == 0) work += 2.0 * m;
         // same test and rotation as the round-robin sweeps, with the column
         // of smaller index as the first of the pair
         if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
@@ -1156,22 +1167,44 @@ __device__ __forceinline__ int jacobi_sweeps_ring(double* A, int m, int n, int m
           // first' = cs first - sn second, second' = sn first + cs second
           const double sx = rfirst ? -sn : sn;  // resident' = cs x + sx y
           const double sy = rfirst ? sn : -sn;  // travelling' = sy x + cs y
-          double nal = 0.0;
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const double x = xr[q], y = yr[q];
             xr[q] = cs * x + sx * y;
             yr[q] = sy * x + cs * y;
-            nal += xr[q] * xr[q];
           }
 #pragma unroll
           for (int q = 0; q < 8; ++q) {
             const int r = gl + q * G;
             if (r < m) cb[r] = yr[q];
           }
-          // the resident's new norm (all lanes of the group take this branch)
-          al = group_sum(nal, G);
-          if (gl == 0) work += 6.0 * m;
+          // new squared norms from the 2 x 2 rotation: first' = aa - tt ga,
+          // second' = bb + tt ga.  Where one drops below 1e-3 of its old
+          // value the update has cancelled digits, and the norm is summed
+          // again from the rotated column (group-uniform branches)
+          const double na = rfirst ? aa - tt * ga : bb + tt * ga;
+          const double nb = rfirst ? bb + tt * ga : aa - tt * ga;
+          if (!(na >= 1e-3 * al)) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += xr[q] * xr[q];
+            al = group_sum(v, G);
+            if (gl == 0) work += 2.0 * m;
+          } else {
+            al = na;
+          }
+          double nbe = nb;
+          if (!(nb >= 1e-3 * be)) {
+            double v = 0.0;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) v += yr[q] * yr[q];
+            nbe = group_sum(v, G);
+            if (gl == 0) work += 2.0 * m;
+          }
+          if (gl == 0) {
+            tn[ti] = nbe;
+            work += 6.0 * m;
+          }
         }
         __syncthreads();
       }
@@ -1310,7 +1343,8 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   const int Gr = jacobi_group_lanes(P2, blockDim.x >> 6);
   const bool ring = c > 1 && 5 * c > 4 * P2 && s <= 8 * Gr &&
                     P2 / 2 <= (int)(blockDim.x >> 6) * (64 / Gr);  // one pair per group
-  const int sw = ring ? jacobi_sweeps_ring(A, s, c, max_sweeps, tol, eps * eps * fro2, work, flag)
+  const int sw = ring ? jacobi_sweeps_ring(A, s, c, max_sweeps, tol, eps * eps * fro2, work, flag,
+                                           nrm)
                       : jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2, work,
                                       flag);
   if (tid == 0 && p.fail) {
