@@ -572,22 +572,42 @@ struct FCqR {  // R = R2 R1 (rho2 x s) -> output
     return d;
   }
 };
-// pass-2 rank into p; an all-zero Q (A = 0) becomes e_0 so Q stays orthonormal
+// pass-2 rank into p; an all-zero Q (A = 0) becomes e_0 so Q stays orthonormal.
+// Problems with m <= s, which the Cholesky passes skip, get Q = I_m and R = A
+// (in FP64) here.  With set_rank, the final p of problem i also becomes rank
+// `bond` of the i-th MPS of L (every problem, as after any QR of a core).
 template <typename T>
-__global__ void k_cq_finish(QrProb<T>* qp, const int* rank, int nprob) {
+__global__ void k_cq_finish(QrProb<T>* qp, const int* rank, int nprob, MpsList<T> L, int bond,
+                            int set_rank) {
   int i = blockIdx.x;
   if (i >= nprob) return;
   QrProb<T> q = qp[i];
-  if (!q.valid || q.m <= q.s) return;
-  __shared__ double red[8];
-  int r2 = rank[2 * i + 1];
-  double acc = 0.0;
-  for (int e = threadIdx.x; e < q.m; e += blockDim.x) acc += fabs((double)q.Q[(long)e * r2]);
-  acc = block_sum(acc, red);
-  if (threadIdx.x == 0) {
-    qp[i].p = r2;
-    if (acc == 0.0) q.Q[0] = (T)1;
+  int pfin = q.p;
+  if (q.valid && q.m > q.s) {
+    __shared__ double red[8];
+    int r2 = rank[2 * i + 1];
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < q.m; e += blockDim.x) acc += fabs((double)q.Q[(long)e * r2]);
+    acc = block_sum(acc, red);
+    if (threadIdx.x == 0) {
+      qp[i].p = r2;
+      if (acc == 0.0) q.Q[0] = (T)1;
+    }
+    pfin = r2;
+  } else if (q.valid) {
+    const long tot = (long)q.m * q.m + (long)q.m * q.s;
+    for (long e = threadIdx.x; e < tot; e += blockDim.x) {
+      if (e < (long)q.m * q.m) {
+        const int a = (int)(e / q.m), b = (int)(e % q.m);
+        q.Q[e] = (T)(a == b ? 1.0 : 0.0);
+      } else {
+        const long f = e - (long)q.m * q.m;
+        const int a = (int)(f / q.s), b = (int)(f % q.s);
+        q.R[f] = (double)q.A[a * q.sAm + b * q.sAk];
+      }
+    }
   }
+  if (set_rank && threadIdx.x == 0) L.p[i]->r[bond] = pfin;
 }
 
 // Widen a rank-deficient Q (m x p, ld p) to m x s (ld s) with zero columns,
@@ -1365,16 +1385,20 @@ class Engine {
 
   // ------------------------------------------------------------ QR op
   template <typename F>
-  void qr(const F& f, int nprob, int mcap, int scap) {
+  // With rank_list, the Cholesky path also stores each problem's final rank
+  // as rank `bond` of the MPS of *rank_list (the Householder path leaves that
+  // to the caller).
+  void qr(const F& f, int nprob, int mcap, int scap, const MpsList<T>* rank_list = nullptr,
+          int bond = 0) {
     if (nprob <= 0) return;
     hipLaunchKernelGGL((k_qr_prep<T, F>), dim3(1), dim3(64), 0, st, f, qp, nprob,
                        fast ? cq_n : (int*)nullptr);
-    hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
-                       (const QrProb<T>*)qp);
     if (fast) {
-      qr_cholesky(nprob, mcap, scap);
+      qr_cholesky(nprob, mcap, scap, rank_list, bond);
       return;
     }
+    hipLaunchKernelGGL(k_qr_identity<T>, dim3(chunks_q(), nprob), dim3(256), 0, st,
+                       (const QrProb<T>*)qp);
     tbegin(2);
     hipLaunchKernelGGL(k_householder<T>, dim3(nprob), dim3(256), (size_t)lds_elems * 8, st,
                        (const QrProb<T>*)qp, qw, lds_elems, kf(2));
@@ -1383,7 +1407,7 @@ class Engine {
   }
 
   // rank-revealing Cholesky-QR2 of the materialised problems (m > s)
-  void qr_cholesky(int nprob, int mcap, int scap) {
+  void qr_cholesky(int nprob, int mcap, int scap, const MpsList<T>* rank_list, int bond) {
     size_t lds = (size_t)lds_elems * 8;
     CholWork w = cw;
     launch_gemm<T, T, double, double>(FCqGram1<T>{qp, w}, nprob, scap, scap, 1, st, nullptr,
@@ -1405,7 +1429,7 @@ class Engine {
     launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqR<T>{qp, w}, nprob, scap, scap, 1, st);
     hipLaunchKernelGGL(k_cq_finish<T>, dim3(nprob), dim3(256), 0, st, qp, (const int*)w.rank,
-                       nprob);
+                       nprob, rank_list ? *rank_list : MpsList<T>{}, bond, rank_list ? 1 : 0);
     HIP_OK(hipGetLastError());
   }
 
@@ -1428,11 +1452,14 @@ class Engine {
     dim3 blk(256);
     for (int k = 0; k < n - 1; ++k) {
       int mcap = capb[k] * PHYS, scap = capb[k + 1];
-      qr(FnQrLeft<T>{L, k, qtmp, qslot, rbuf, rslot}, cnt, mcap, scap);
+      // the rank update r_{k+1} = p reads nothing that the product R core
+      // needs (it takes p and s from the QR problem)
+      qr(FnQrLeft<T>{L, k, qtmp, qslot, rbuf, rslot}, cnt, mcap, scap, &L, k + 1);
       launch_gemm<double, T, T, double>(FnRTimesCore<T>{L, qp, ctmp, maxcore, k}, cnt, scap,
                                         PHYS * capb[k + 2], 1, st);
-      hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, L,
-                         (const QrProb<T>*)qp, k + 1, cnt);
+      if (!fast)
+        hipLaunchKernelGGL(k_set_rank_from_qr<T>, dim3(1), dim3(64), 0, st, L,
+                           (const QrProb<T>*)qp, k + 1, cnt);
       hipLaunchKernelGGL(k_store_core2<T>, dim3(chunks(), cnt, 2), blk, 0, st, L, (const T*)qtmp,
                          qslot, k, (const T*)ctmp, maxcore, k + 1);
     }
