@@ -752,7 +752,81 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
     }
   }
   __syncthreads();
-  for (int b = IB; b < rho; b *= 2) {
+  if (regs) {
+    // Orders up to 128 with 16 waves: each level's two products on FP64 MFMA
+    // (16 x 16 x 4), one wave per 16 x 16 output tile (at most 16 tiles a
+    // level).  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
+    // holds the results of column l % 16, rows l / 16 + 4 v.  Out-of-range
+    // operands enter as zeros; the triangular factors contribute only their
+    // nonzero K range.
+    typedef double dv4 __attribute__((ext_vector_type(4)));
+    const int l16 = lane & 15, lq = lane >> 4;
+    for (int b = IB; b < rho; b *= 2) {
+      int tile = wv, tp = -1, tI = 0, tJ = 0, tbc = 0;
+      for (int p = 0; p + b < rho; p += 2 * b) {
+        const int bc = rho - p - b < b ? rho - p - b : b;
+        const int ncol = (bc + 15) / 16, nt = (b / 16) * ncol;
+        if (tile < nt) {
+          tp = p;
+          tI = (tile / ncol) * 16;
+          tJ = (tile % ncol) * 16;
+          tbc = bc;
+          break;
+        }
+        tile -= nt;
+      }
+      // U = X11 R12: X11[i][t] is xd[i] on the diagonal and sits in the
+      // lower slot (t, i) above it; R12[t][c] in the upper slot (t, c)
+      dv4 acc = {0.0, 0.0, 0.0, 0.0};
+      if (tp >= 0) {
+        const int ia = tp + tI + l16, cb = tp + b + tJ + l16;
+        const bool cok = tJ + l16 < tbc;
+        for (int k0 = tI; k0 < b; k0 += 4) {
+          const int t = tp + k0 + lq;
+          const double a = t < ia ? 0.0 : (t == ia ? xd[ia] : G[(long)t * rho + sk(ia + t)]);
+          const double bv = cok ? G[(long)t * rho + sk(cb + t)] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        }
+      }
+      __syncthreads();
+      if (tp >= 0 && tJ + l16 < tbc) {
+        const int c = tp + b + tJ + l16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ig = tp + tI + lq + 4 * v;
+          G[(long)ig * rho + sk(c + ig)] = acc[v];
+        }
+      }
+      __syncthreads();
+      // X12 = -U X22: U[i][t] in the upper slot (i, t); X22[t][c] is xd[c]
+      // on the diagonal and sits in the lower slot (c, t) above it.  The
+      // results go to the lower slots (c, i), which no product of this level
+      // reads
+      acc = dv4{0.0, 0.0, 0.0, 0.0};
+      if (tp >= 0) {
+        const int ia = tp + tI + l16, cb = tp + b + tJ + l16;
+        const bool cok = tJ + l16 < tbc;
+        const int kend = tJ + 16 < tbc ? tJ + 16 : tbc;
+        for (int k0 = 0; k0 < kend; k0 += 4) {
+          const int kt = k0 + lq, t = tp + b + kt;
+          const double a = kt < tbc ? G[(long)ia * rho + sk(t + ia)] : 0.0;
+          double bv = 0.0;
+          if (kt < tbc && cok)
+            bv = t > cb ? 0.0 : (t == cb ? xd[cb] : G[(long)cb * rho + sk(t + cb)]);
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+        }
+        if (cok) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ig = tp + tI + lq + 4 * v;
+            G[(long)cb * rho + sk(ig + cb)] = -acc[v];
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int b = IB; b < rho && !regs; b *= 2) {
     // U = X11 R12 (rows [p, p+b), columns [p+b, p+b+bc)); at most rho b / 2
     // entries, so at most 4 per thread when staged through registers
     double u[4];
