@@ -450,14 +450,6 @@ __device__ inline double wave_max_f64(double v) {
   return fmax(fmax(readlane_f64(v, 0), readlane_f64(v, 16)),
               fmax(readlane_f64(v, 32), readlane_f64(v, 48)));
 }
-__device__ inline int wave_min_i32(int v) {
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false));
-  v = min(v, __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false));
-  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
-             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
-}
 
 // Blocked pivoted Cholesky for n <= CPB_MAXN with G in LDS.  Wave 0 factors
 // a panel of CPB columns (left-looking inside the panel, pivots chosen on
@@ -496,11 +488,13 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
 #pragma unroll
       for (int k = 0; k < CPB; ++k) {
         if (k < bw && !stop) {
-          double cand = d0;
-          int ci = i0;
-          if (d1 > cand) { cand = d1; ci = i1; }
+          const double cand = d1 > d0 ? d1 : d0;
           const double best = wave_max_f64(cand);
-          const int bi = wave_min_i32(cand == best ? ci : 0x7FFFFFFF);
+          // lowest physical row holding the maximum: rows 0..63 (d0) come
+          // before rows 64..127 (d1), so the lowest lane with d0 == best, else
+          // 64 + the lowest lane with d1 == best (no lane: the panel stops)
+          const unsigned long long m0 = __ballot(d0 == best), m1 = __ballot(d1 == best);
+          const int bi = m0 ? __builtin_ctzll(m0) : (m1 ? 64 + __builtin_ctzll(m1) : 0);
           if (!(best > thr) || !(best > 0.0)) {
             stop = true;  // the same decision in every lane
           } else {
