@@ -563,49 +563,32 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
       __syncthreads();
       break;
     }
-    // trailing update of the rows and columns not pivoted yet (entries of L
-    // beyond the panel's pivots are zero)
-    if ((blockDim.x & 63) == 0) {
-      // G -= L L^T on FP64 MFMA (16 x 16 x 4): the waves take the 16 x 16
-      // tiles of the whole order in turn; lane l supplies L[a][q] for row
-      // a = a0 + l % 16 and L[b][q] for column b = b0 + l % 16 (q = q0 + l / 16)
-      // and holds rows a0 + l / 16 + 4 v of column b0 + l % 16.  Only entries
-      // whose row and column are both unpivoted are stored: the rows of R
-      // written above are pivoted ones
-      typedef double dv4 __attribute__((ext_vector_type(4)));
-      const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4;
-      for (int t = wv; t < nb * nb; t += nw) {
-        const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
-        const int ar = a0 + l16, bc = b0 + l16;
-        dv4 acc = {0.0, 0.0, 0.0, 0.0};
+    // trailing update of the rows and columns not pivoted yet, G -= L L^T
+    // (entries of L beyond the panel's pivots are zero), on FP64 MFMA
+    // (16 x 16 x 4; the workgroup is whole waves): the waves take the
+    // 16 x 16 tiles of the whole order in turn; lane l supplies L[a][q] for
+    // row a = a0 + l % 16 and L[b][q] for column b = b0 + l % 16
+    // (q = q0 + l / 16) and holds rows a0 + l / 16 + 4 v of column
+    // b0 + l % 16.  Only entries whose row and column are both unpivoted are
+    // stored: the rows of R written above are pivoted ones
+    typedef double dv4 __attribute__((ext_vector_type(4)));
+    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4;
+    for (int t = wv; t < nb * nb; t += nw) {
+      const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
+      const int ar = a0 + l16, bc = b0 + l16;
+      dv4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q0 = 0; q0 < CPB; q0 += 4) {
-          const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
-          const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
-        }
-        if (bc < n && posn[bc] == n) {
-#pragma unroll
-          for (int v = 0; v < 4; ++v) {
-            const int a = a0 + lq + 4 * v;
-            if (a < n && posn[a] == n) G[(long)a * n + bc] -= acc[v];
-          }
-        }
+      for (int q0 = 0; q0 < CPB; q0 += 4) {
+        const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
+        const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
       }
-      __syncthreads();
-      continue;
-    }
-    for (int b = lane; b < n; b += 64) {
-      const bool ub = posn[b] == n;
-      double lb[CPB];
+      if (bc < n && posn[bc] == n) {
 #pragma unroll
-      for (int q = 0; q < CPB; ++q) lb[q] = ub ? Lp[b * LPS + q] : 0.0;
-      for (int a = wv; a < n; a += nw) {
-        if (posn[a] < n) continue;
-        double acc = 0.0;
-#pragma unroll
-        for (int q = 0; q < CPB; ++q) acc += Lp[a * LPS + q] * lb[q];
-        if (ub) G[(long)a * n + b] -= acc;
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + lq + 4 * v;
+          if (a < n && posn[a] == n) G[(long)a * n + bc] -= acc[v];
+        }
       }
     }
     __syncthreads();
