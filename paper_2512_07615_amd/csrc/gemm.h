@@ -285,9 +285,15 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
 }
 
 // Sum of the split-K partial tiles in share order, then C = alpha sum + beta C.
+// Each output tile is shared by RQ workgroups (a quarter of its entries
+// each), so that one pass of loads covers a workgroup's part and the launch
+// spreads over RQ times as many CUs.
+constexpr int RQ = 4;
 template <typename TA, typename TB, typename TC, typename F>
 __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int batch_cap, KSplit ks) {
   long wg = blockIdx.x;
+  const int part = (int)(wg % RQ);
+  wg /= RQ;
   int tile = (int)(wg % tiles_cap);
   long rest = wg / tiles_cap;
   int b = (int)(rest % batch_cap);
@@ -304,21 +310,22 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
   const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (GT * GT);
   // four outputs per pass, the loads of all their shares issued together,
   // then each output summed in share order
-  constexpr int OUT = 4;
-  for (int e0 = threadIdx.x; e0 < GT * GT; e0 += OUT * blockDim.x) {
+  constexpr int OUT = 4, PART = GT * GT / RQ;
+  const int e_end = (part + 1) * PART;
+  for (int e0 = part * PART + threadIdx.x; e0 < e_end; e0 += OUT * blockDim.x) {
     double v[OUT][8];
 #pragma unroll
     for (int o = 0; o < OUT; ++o) {
       const int e = e0 + o * blockDim.x;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        v[o][q] = (e < GT * GT && q < ks.split) ? W[(long)q * (GT * GT) + e] : 0.0;
+        v[o][q] = (e < e_end && q < ks.split) ? W[(long)q * (GT * GT) + e] : 0.0;
     }
 #pragma unroll
     for (int o = 0; o < OUT; ++o) {
       const int e = e0 + o * blockDim.x;
       const int row = ti * GT + e / GT, col = tj * GT + e % GT;
-      if (e >= GT * GT || row >= d.M || col >= d.N) continue;
+      if (e >= e_end || row >= d.M || col >= d.N) continue;
       double sum = 0.0;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
@@ -345,8 +352,8 @@ inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap
   hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE>), dim3((unsigned)(grid * ks.split)),
                      dim3(256), 0, s, f, tiles, batch_cap, flops, ks);
   if (ks.split > 1)
-    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, F>), dim3((unsigned)grid), dim3(256), 0, s, f,
-                       tiles, batch_cap, ks);
+    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, F>), dim3((unsigned)(grid * RQ)), dim3(256), 0,
+                       s, f, tiles, batch_cap, ks);
   HIP_OK(hipGetLastError());
 }
 
