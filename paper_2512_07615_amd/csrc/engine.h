@@ -864,9 +864,10 @@ class Engine {
   bool rsvd = false;
   int rs_over = 16;
   // Jacobi of the FP32 truncation: column pairs count as orthogonal at a
-  // relative 1e-12, four orders below FP32 rounding (the eigenvalues are then
-  // exact to about 1e-24 relative, the vectors orthonormal to 1e-12)
-  double eig_orth_tol = 1e-12;
+  // relative 1e-9, which leaves the eigenvectors orthonormal to 1e-9: the
+  // level at which the FP32 Cholesky-QR already accepts a Q, and far below
+  // the rounding of the FP32 cores they become (about 1e-7)
+  double eig_orth_tol = 1e-9;
   int rs_call = 0;
   int* rs_pred = nullptr;   // [RS_CALLS][MAXN + 1][MAXB]
   int* rs_dims = nullptr;
