@@ -248,8 +248,10 @@ __global__ void k_store_core_T(MpsList<T> L, const QrProb<T>* qp, int k) {
 // Left environment after the centre moves right (reuses T2 of site p):
 //  G3L: Lenv[p+1][a'][b'c'] = sum_{a s} A[a][s][a'] T2[a][s][b'c']
 // Right environment after the centre moves left:
-//  H1: U1[a'][c'][b s] = sum_{b'} R[a'][b'][c'] B[b][s][b']  (batched over a')
-//  H2: U2[s][a'][b][c] = sum_{c'} U1[a'][c'][b s] C[c][s][c'] (batched over s, a')
+//  H1: U1[a'][c'][s][b] = sum_{b'} R[a'][b'][c'] B[b][s][b']  (batched over a', s)
+//  H2: U2[s][a'][b][c] = sum_{c'} U1[a'][c'][s][b] C[c][s][c'] (batched over s, a')
+//  (s before b in U1, so that the operand of H2 at fixed s is read in
+//  contiguous rows)
 //  H3: Renv[p][a][b c] = sum_{s a'} A[a][s][a'] U2[s][a'][b c]
 template <typename T>
 struct ProdCtx {
@@ -339,10 +341,10 @@ struct FnH1 {
     c.get(i, &D, &B, &C);
     int a2 = D->r[p + 1], b = B->r[p], b2 = B->r[p + 1], c2 = C->r[p + 1];
     g.A = c.R(i, p + 1); g.B = core_ptr(B, p); g.C = c.T1 + i * c.tcap;
-    g.M = c2; g.N = PHYS * b; g.K = b2; g.nb1 = a2; g.nb2 = 1;
+    g.M = c2; g.N = b; g.K = b2; g.nb1 = a2; g.nb2 = PHYS;
     g.sAm = 1; g.sAk = c2; g.bA1 = (long)b2 * c2;
-    g.sBk = 1; g.sBn = b2;
-    g.sCm = PHYS * b; g.sCn = 1; g.bC1 = (long)c2 * PHYS * b;
+    g.sBk = 1; g.sBn = PHYS * b2; g.bB2 = b2;
+    g.sCm = PHYS * b; g.sCn = 1; g.bC1 = (long)c2 * PHYS * b; g.bC2 = b;
     g.valid = 1;
     return g;
   }
@@ -357,7 +359,7 @@ struct FnH2 {
     int a2 = D->r[p + 1], b = B->r[p], cc = C->r[p], c2 = C->r[p + 1];
     g.A = c.T1 + i * c.tcap; g.B = core_ptr(C, p); g.C = c.T2 + i * c.tcap;
     g.M = b; g.N = cc; g.K = c2; g.nb1 = PHYS; g.nb2 = a2;
-    g.sAm = PHYS; g.sAk = PHYS * b; g.bA1 = 1; g.bA2 = (long)c2 * PHYS * b;
+    g.sAm = 1; g.sAk = PHYS * b; g.bA1 = b; g.bA2 = (long)c2 * PHYS * b;
     g.sBk = 1; g.sBn = PHYS * c2; g.bB1 = c2; g.bB2 = 0;
     g.sCm = cc; g.sCn = 1; g.bC1 = (long)a2 * b * cc; g.bC2 = (long)b * cc;
     g.valid = 1;
@@ -1741,8 +1743,7 @@ class Engine {
 
   void right_env(const ProdCtx<T>& c, int p, int cnt) {
     tbegin(3);
-    pgemm(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], PHYS * cpb[p], cpb[p + 1],
-                               st, kf(3));
+    pgemm(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p], PHYS * cpb[p + 1], st, kf(3));
     tend(3);
     tbegin(3);
     pgemm(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st,
