@@ -285,10 +285,10 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
 }
 
 // Sum of the split-K partial tiles in share order, then C = alpha sum + beta C.
-// Each output tile is shared by RQ workgroups (a quarter of its entries
+// Each output tile is shared by RQ workgroups (an eighth of its entries
 // each), so that one pass of loads covers a workgroup's part and the launch
 // spreads over RQ times as many CUs.
-constexpr int RQ = 4;
+constexpr int RQ = 8;
 template <typename TA, typename TB, typename TC, typename F>
 __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int batch_cap, KSplit ks) {
   long wg = blockIdx.x;
@@ -308,9 +308,9 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
   int b1 = b % d.nb1, b2 = b / d.nb1;
   TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
   const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (GT * GT);
-  // four outputs per pass, the loads of all their shares issued together,
+  // two outputs per thread, the loads of all their shares issued together,
   // then each output summed in share order
-  constexpr int OUT = 4, PART = GT * GT / RQ;
+  constexpr int OUT = 2, PART = GT * GT / RQ;
   const int e_end = (part + 1) * PART;
   for (int e0 = part * PART + threadIdx.x; e0 < e_end; e0 += OUT * blockDim.x) {
     double v[OUT][8];
