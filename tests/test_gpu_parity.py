@@ -506,3 +506,52 @@ def test_vascular128_full_size_velocity_vs_fp64():
         du = _vel_rel_l2(u[prec], u["fp64"])
         print("vascular128", prec, "velocity rel L2 vs fp64", du, flush=True)
         assert du < 1e-4
+
+
+@pytest.mark.parametrize("prec,bound", [("fp64", 1e-10), ("fp32", 5e-5)])
+def test_newton_inverse_density_untruncated(prec, bound):
+    """Newton-Schulz inverse density (three iterations, Appendix B) on the
+    body-forced 8^3 channel, untruncated, two steps, against the CPU MPS
+    oracle run in the same mode.  The reference is the MPS oracle, not the
+    dense one: the Newton products act on operands of order one (rho (.) y is
+    about 1), so the fitting error of the two-sweep variational product
+    (about 1e-9 here) stays in the result, and only the MPS oracle runs the
+    same product.  The body force makes j_eq a sum that the library rounds
+    together with the first Newton sum."""
+    L = lib()
+    case = _case_with_flow(WL.case_channel(n=3, chi=64, tol=1e-13))
+    print("case", case.name, prec, "newton x3", flush=True)
+    sim = L.Simulation(case, precision=prec, inv_mode=L.INV_NEWTON, inv_iters=3)
+    sim.step(2)
+    got = sim.dense(L.POPS)
+    sim.close()
+    m = MPSLBM(case, inv_mode="newton", inv_iters=3)
+    m.step()
+    m.step()
+    r = rel(got, m.dense_populations())
+    print("rel vs MPS oracle", r, flush=True)
+    assert r < bound
+
+
+def test_newton_inverse_density_truncated_vs_mps_oracle():
+    """Newton-Schulz inverse density (two iterations) with truncation
+    (chi = 8 on the body-forced 16^3 channel), FP64 and FP32 policies
+    against the CPU MPS oracle on the same schedule, two steps."""
+    L = lib()
+    case = _case_with_flow(WL.case_channel(n=4, chi=8, tol=1e-6))
+    print("case", case.name, "chi 8 newton x2", flush=True)
+    m = MPSLBM(case, inv_mode="newton", inv_iters=2)
+    sims = {p: L.Simulation(case, precision=p, inv_mode=L.INV_NEWTON, inv_iters=2)
+            for p in ("fp64", "fp32")}
+    for _ in range(2):
+        m.step()
+        for s in sims.values():
+            s.step(1)
+    ref = m.dense_populations()
+    out = {}
+    for p, s in sims.items():
+        out[p] = rel(s.dense(L.POPS), ref)
+        s.close()
+    print("channel16 chi8 newton rel vs MPS oracle", out, flush=True)
+    assert out["fp64"] < 1e-7
+    assert out["fp32"] < 1e-3
