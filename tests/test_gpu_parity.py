@@ -555,3 +555,39 @@ def test_newton_inverse_density_truncated_vs_mps_oracle():
     print("channel16 chi8 newton rel vs MPS oracle", out, flush=True)
     assert out["fp64"] < 1e-7
     assert out["fp32"] < 1e-3
+
+
+def test_batched_domains_beyond_one_launch():
+    """Five domains in one handle: the levels of a step then hold 90 to 245
+    problems, more than one launch carries (64), so roundings, sums and
+    shifts are issued in several chunks.  Each domain must still match its
+    own single-domain handle and the CPU MPS oracle."""
+    L = lib()
+    cases = [
+        _case_with_flow(WL.case_channel(n=3, chi=64, tol=1e-13), seed=11),
+        _case_with_flow(WL.case_porous(n=3, chi=64, tol=1e-13, tau=0.7), seed=12),
+        _case_with_flow(WL.case_channel(n=3, chi=64, tol=1e-13, tau=0.65, g=3e-6), seed=13),
+        _case_with_flow(WL.case_porous(n=3, chi=64, tol=1e-13, tau=0.9, seed=2520), seed=14),
+        _case_with_flow(WL.case_channel(n=3, chi=64, tol=1e-13, tau=0.75, g=-2e-6), seed=15),
+    ]
+    print("five domains", [c.name for c in cases], flush=True)
+    b = L.BatchSimulation(cases, precision="fp64")
+    assert b.domains() == 5
+    singles = [L.Simulation(c, precision="fp64") for c in cases]
+    refs = [MPSLBM(c) for c in cases]
+    for _ in range(2):
+        b.step(1)
+        for s in singles:
+            s.step(1)
+        for m in refs:
+            m.step()
+    for k, c in enumerate(cases):
+        got = b.dense(k)
+        one = singles[k].dense()
+        ref = refs[k].dense_populations()
+        print(k, c.name, "batch vs single", rel(got, one), "vs MPS oracle", rel(got, ref), flush=True)
+        assert rel(got, one) < 1e-12
+        assert rel(got, ref) < 1e-10
+    for s in singles:
+        s.close()
+    b.close()
