@@ -130,17 +130,6 @@ def inner_ones(cores) -> float:
     return float(v[0])
 
 
-def inner(a, b) -> float:
-    E = np.ones((1, 1))
-    for x, y in zip(a, b):
-        E = np.einsum("ab,asc,bsd->cd", E, x, y)
-    return float(E[0, 0])
-
-
-def norm(a) -> float:
-    return float(np.sqrt(max(inner(a, a), 0.0)))
-
-
 # --------------------------------------------------------------------------
 # addition, rounding
 # --------------------------------------------------------------------------

@@ -64,21 +64,23 @@ class MPSLBM:
         self.cnt = Counters()
         n = self.n
         self.one = M.ones(n)
-        # the mask rank is capped at the flow bond dimension chi (products with
-        # the mask run at the candidate's bonds, and chi_mask <= chi keeps every
-        # operand within the same capacity)
-        chi_mask = min(case.chi_mask if case.chi_mask else 1 << 30, self.chi)
+        # obstacle mask (objects equation): TT-SVD of the binary solid field
+        # at tol_mask.  By default no rank cap applies, so the mask is
+        # represented to machine precision, which is how Section 5.2 fixes
+        # the mask bond dimension; case.chi_mask caps it explicitly.
+        chi_mask = int(case.chi_mask) if case.chi_mask else 1 << 30
+        fluid = None
         if case.solid is not None:
             self.mask = M.from_dense(case.solid.astype(np.float64), n, chi_mask,
                                      case.tol_mask)
             self.n_fluid = float(self.N ** 3) - M.inner_ones(self.mask)
-            fluid_mps = M.round_mps(M.add(self.one, M.scale(self.mask, -1.0)),
-                                    self.chi, case.tol_mask)
+            fluid = 1.0 - case.solid.astype(np.float64)
         else:
             self.mask = None
             self.n_fluid = float(self.N ** 3)
-            fluid_mps = self.one
-        # fluid part of each open face (rank-1 plane mask applied exactly)
+        # face masks m_B (boundaries equations): the fluid cells of each open
+        # face plane, decomposed from that dense definition at tol_mask; they
+        # are added into population sums, so their rank is capped at chi
         self.fluid_plane = {}
         for ax in range(3):
             if not self.axis_open[ax]:
@@ -87,7 +89,14 @@ class MPSLBM:
                 face = 2 * ax + side
                 if case.face_bc[face]:
                     idx = 0 if side == 0 else self.N - 1
-                    self.fluid_plane[face] = M.plane_slice(fluid_mps, ax, idx)
+                    plane = np.zeros((self.N,) * 3)
+                    sl = [slice(None)] * 3
+                    sl[ax] = idx
+                    plane[tuple(sl)] = 1.0
+                    if fluid is not None:
+                        plane *= fluid
+                    self.fluid_plane[face] = M.from_dense(plane, n, self.chi,
+                                                          case.tol_mask)
         if f_init is None:
             f_init = self.initial_dense(case)
         self.f = [M.from_dense(f_init[i], n, self.chi, self.tol) for i in range(Q)]
@@ -132,6 +141,11 @@ class MPSLBM:
     def prod(self, x, y):
         self.cnt.products += 1
         return M.product(x, y, self.sweeps)
+
+    def prod_first(self, x, y):
+        """Variational product with the first factor as the candidate."""
+        self.cnt.products += 1
+        return M.hadamard_variational(x, y, self.sweeps)
 
     def stream(self, x, c):
         for ax in range(3):
@@ -236,7 +250,9 @@ class MPSLBM:
         for i, terms in sorted(bterms.items()):
             fs[i] = self.lin_sum([(1.0, fs[i])] + terms)
         if self.mask is not None:
-            g = [None] + [self.prod(fs[i], self.mask) for i in range(1, Q)]
+            # the candidate of each obstacle product is the population, the
+            # factor whose bond dimension the result keeps (Section 2.3)
+            g = [None] + [self.prod_first(fs[i], self.mask) for i in range(1, Q)]
             fn = [fs[0]]
             for i in range(1, Q):
                 h = self.stream(g[OPP[i]], C[i])

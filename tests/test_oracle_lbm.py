@@ -227,3 +227,100 @@ def test_pressure_faces_drive_flow_down_the_gradient():
     prof = rho.mean(axis=(1, 2))
     assert np.all(np.diff(prof) < 0)
     assert d.j()[0][:, 1:-1, :].min() > 0
+
+
+def _uniform_duct(face_bc, face_val, u):
+    """An 8^3 duct open in x, periodic in y and z, no solid, holding the
+    uniform state (rho_b, u) everywhere."""
+    n = 3
+    N = 1 << n
+    rho_b = 1.02
+    return WL.Case(name="uniform_duct", n=n, tau=0.7, chi=10 ** 6, tol=1e-14,
+                   axis_open=(1, 0, 0), face_bc=face_bc, face_val=face_val,
+                   rho_init=np.full((N,) * 3, rho_b),
+                   u_init=np.broadcast_to(np.asarray(u, float)[:, None, None, None],
+                                          (3, N, N, N)).copy()), rho_b
+
+
+def _feq_uniform(rho, u, shape):
+    out = np.empty((Q,) + shape)
+    uu = float(np.dot(u, u))
+    for i in range(Q):
+        cu = float(C[i] @ u)
+        out[i] = W[i] * rho * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
+    return out
+
+
+@pytest.mark.parametrize("oracle", ["dense", "mps"])
+def test_pressure_faces_keep_a_uniform_equilibrium(oracle):
+    """The pressure face term -f_ihat + 2 w_i rho_b (1 + 4.5 (c_i.u)^2 - 1.5
+    u.u) is exact at equilibrium: with f_ihat = f_eq,ihat(rho_b, u) it gives
+    f_eq,i(rho_b, u), since the odd terms of f_i + f_ihat cancel.  So a
+    uniform flow (rho_b, u) with pressure faces at rho_b on both ends is a
+    fixed point of the step.  u has three nonzero components, so every
+    coefficient (4.5, 1.5 and the cross terms 9 c_a c_b u_a u_b) is
+    exercised; a wrong one moves the face planes by O(u^2)."""
+    u = np.array([0.06, -0.04, 0.03])
+    case, rho_b = _uniform_duct((WL.BC_PRESSURE, WL.BC_PRESSURE, 0, 0, 0, 0),
+                                ((1.02, 0, 0), (1.02, 0, 0)) + ((0, 0, 0),) * 4, u)
+    sim = DenseLBM(case) if oracle == "dense" else MPSLBM(case)
+    ref = _feq_uniform(rho_b, u, (case.N,) * 3)
+    for _ in range(2):
+        sim.step()
+    f = sim.f if oracle == "dense" else sim.dense_populations()
+    assert np.abs(f - ref).max() < 1e-13
+    # a perturbed coefficient would not keep it: the face term's quadratic
+    # part is not negligible at this velocity
+    assert 4.5 * 0.1 ** 2 * W[7] * rho_b > 1e-5
+
+
+@pytest.mark.parametrize("oracle", ["dense", "mps"])
+def test_velocity_face_keeps_a_uniform_equilibrium(oracle):
+    """The velocity face term f_ihat + 6 w_i rho_0 c_i.u_b is exact at
+    equilibrium: with f_ihat = f_eq,ihat(rho_0, u_b) it gives
+    f_eq,i(rho_0, u_b).  A uniform flow at u_b with a velocity inlet and a
+    pressure outlet at rho_b = rho_0 is therefore a fixed point."""
+    u = np.array([0.05, 0.02, -0.03])
+    case, rho_b = _uniform_duct((WL.BC_VELOCITY, WL.BC_PRESSURE, 0, 0, 0, 0),
+                                (tuple(u), (1.02, 0, 0)) + ((0, 0, 0),) * 4, u)
+    sim = DenseLBM(case) if oracle == "dense" else MPSLBM(case)
+    ref = _feq_uniform(rho_b, u, (case.N,) * 3)
+    for _ in range(2):
+        sim.step()
+    f = sim.f if oracle == "dense" else sim.dense_populations()
+    assert np.abs(f - ref).max() < 1e-13
+
+
+def test_obstacle_mask_is_machine_precision_and_products_keep_population_bonds():
+    """The obstacle mask is decomposed to machine precision (Section 5.2:
+    the mask bond dimension is the one that represents it exactly), so its
+    rank may exceed chi; the obstacle products take the population as the
+    candidate, so every population keeps bonds <= chi.  An explicit cap
+    (case.chi_mask) still applies when given."""
+    case = WL.case_porous(n=4, chi=8, tol=1e-6)
+    rho, u = WL.random_flow_state(4, 3, amp=0.01)
+    case.rho_init, case.u_init = rho, u
+    m = MPSLBM(case)
+    dense = M.to_dense(m.mask)
+    assert np.abs(dense - case.solid).max() < 1e-12
+    assert max(M.bonds(m.mask)) > case.chi
+    assert m.n_fluid == pytest.approx(float((case.solid == 0).sum()), abs=1e-8)
+    m.step()
+    assert all(max(b) <= case.chi for b in m.bond_dims())
+    capped = WL.case_porous(n=4, chi=8, tol=1e-6, chi_mask=4)
+    assert max(M.bonds(MPSLBM(capped).mask)) <= 4
+
+
+def test_face_masks_are_the_fluid_cells_of_the_face_planes():
+    """m_B of an open face is the indicator of the fluid cells of the face
+    plane, decomposed from that definition (exact to tol_mask)."""
+    case = WL.case_vascular(n=4, chi=64, tol=1e-12)
+    m = MPSLBM(case)
+    N = case.N
+    for face, mps in m.fluid_plane.items():
+        ax, side = divmod(face, 2)
+        ref = np.zeros((N,) * 3)
+        sl = [slice(None)] * 3
+        sl[ax] = 0 if side == 0 else N - 1
+        ref[tuple(sl)] = 1.0 - case.solid[tuple(sl)]
+        assert np.abs(M.to_dense(mps) - ref).max() < 1e-12

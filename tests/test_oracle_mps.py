@@ -163,6 +163,49 @@ def test_rounding_chi_cap_is_optimal_at_one_bond():
     assert err == pytest.approx(np.sqrt(np.sum(sv[3:] ** 2)), rel=1e-10)
 
 
+def test_rank_rule_is_minimal_and_meets_the_tail_bound():
+    """The rank kept is the smallest one whose discarded tail is within
+    delta^2: a rule that keeps one rank too many (or too few) fails here.
+    The tails are summed independently of the rule, by a sorted cumulative
+    sum of exact squares."""
+    rng = np.random.default_rng(12)
+    for trial in range(400):
+        m = int(rng.integers(1, 40))
+        s = np.sort(np.abs(rng.standard_normal(m)) * 10.0 ** rng.uniform(-8, 0, m))[::-1]
+        tot = float(np.sum(s * s))
+        delta2 = tot * 10.0 ** rng.uniform(-12, 0)
+        chi = int(rng.integers(1, 45))
+        r = M.rank_rule(s, delta2, chi)
+        tail = lambda k: float(np.sum(s[k:] ** 2))  # weight discarded at rank k
+        assert 1 <= r <= min(chi, m)
+        if r < chi:
+            assert tail(r) <= delta2
+            # one rank fewer would discard too much
+            if r > 1:
+                assert tail(r - 1) > delta2
+        else:
+            # capped at chi: the uncapped rule needs at least chi
+            assert chi == 1 or tail(chi - 1) > delta2 or chi > m
+
+
+def test_rounding_keeps_the_exact_minimal_ranks_of_a_known_spectrum():
+    """An n = 2 MPS built as U diag(s) V^T with orthonormal U, V has the
+    bond spectrum s exactly; at a tolerance whose threshold falls between
+    two known tails the rounding must keep exactly the rank in between."""
+    rng = np.random.default_rng(13)
+    s = np.array([1.0, 0.5, 0.2, 1e-2, 1e-3, 1e-4, 1e-5, 1e-6])
+    U, _ = np.linalg.qr(rng.standard_normal((8, 8)))
+    V, _ = np.linalg.qr(rng.standard_normal((8, 8)))
+    a = [U.reshape(1, 8, 8), (np.diag(s) @ V.T).reshape(8, 8, 1)]
+    tot = float(np.sum(s * s))
+    for keep in range(1, 8):
+        lo, hi = float(np.sum(s[keep:] ** 2)), float(np.sum(s[keep - 1:] ** 2))
+        delta2 = np.sqrt(lo * hi)  # strictly between the two tails
+        tol = np.sqrt(delta2 / tot)  # n - 1 = 1 bond
+        r = M.round_mps(a, 10 ** 6, tol)
+        assert M.bonds(r) == [keep]
+
+
 # ------------------------------------------------------- variational product
 
 def test_variational_product_exact_at_full_bonds():
@@ -204,6 +247,21 @@ def test_variational_product_residual_non_increasing_and_near_optimal():
     A = M.hadamard_variational(B, Cm)
     err_var = np.linalg.norm(M.contract(A) - target)
     assert err_var <= 3.0 * err_svd + 1e-12 * np.linalg.norm(target)
+
+
+def test_variational_product_keeps_the_first_factors_bonds():
+    """hadamard_variational takes the first factor as the candidate
+    (Section 2.3): the result has its bonds whatever the second factor's
+    rank, and where the exact product fits those bonds it is reproduced."""
+    rng = np.random.default_rng(10)
+    hi = M.from_dense(rng.standard_normal((8, 8, 8)), 3, 10 ** 6, 0.0)
+    one_like = [np.ones((1, 8, 1)) * 1.5 for _ in range(3)]
+    A = M.hadamard_variational(one_like, hi)
+    assert M.bonds(A) == [1, 1]
+    # a rank-1 second factor times a full-rank first factor is exact
+    B = M.hadamard_variational(hi, one_like)
+    assert M.bonds(B) == M.bonds(hi)
+    assert np.allclose(M.contract(B), 1.5 ** 3 * M.contract(hi), atol=1e-11)
 
 
 def test_product_puts_higher_rank_first():
