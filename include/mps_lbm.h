@@ -80,7 +80,11 @@ typedef struct {
   int n;            /* N = 2^n cells per axis, 2 <= n <= MPS_LBM_MAX_SITES */
   int lattice;      /* MPS_LBM_D3Q19                                      */
   int chi_max;      /* bond dimension cap of every population MPS, >= 1    */
-  int chi_mask_max; /* cap of the obstacle-mask MPS; <= 0 means no cap     */
+  int chi_mask_max; /* rank cap of the obstacle-mask MPS; <= 0 means no cap:
+                       the mask is then decomposed to tol_mask, i.e. to
+                       machine precision (Section 5.2 sets the mask bond
+                       dimension that way), with its own storage, and may
+                       exceed chi_max                                     */
   double tol;       /* relative Frobenius truncation tolerance of a rounding */
   double tol_mask;  /* truncation tolerance of the mask decomposition      */
   double tau;       /* BGK relaxation time, > 1/2                          */
@@ -124,6 +128,9 @@ typedef struct {
   int lds_bytes;           /* LDS per workgroup the factorisation kernels use */
   long long rs_attempted;  /* truncations tried on a randomized sketch (total) */
   long long rs_accepted;   /* of those, accepted without fallback (total)    */
+  double face_trunc_err;   /* largest ||m_B - m_B~|| / ||m_B|| of the open-face
+                              masks (fluid cells of the face plane), which are
+                              decomposed at tol_mask with rank cap chi_max */
 } mps_lbm_obs;
 
 /* Fill *cfg with defaults: D3Q19, FP64, TAYLOR2, 2 sweeps, tol 1e-10,

@@ -253,17 +253,28 @@ __global__ void k_store_core_T(MpsList<T> L, const QrProb<T>* qp, int k) {
 //  (s before b in U1, so that the operand of H2 at fixed s is read in
 //  contiguous rows)
 //  H3: Renv[p][a][b c] = sum_{s a'} A[a][s][a'] U2[s][a'][b c]
+// Environments of problem i at bond k start at env + i * estride + eoff[k]
+// (each bond sized by its capacities r_A r_B r_C).  With `fixed` set, X is
+// the candidate (the obstacle products, whose result keeps the population's
+// bonds); otherwise the factor with the larger maximal bond is.
 template <typename T>
 struct ProdCtx {
   MpsList<T> D, X, Y;
-  T* envL; T* envR; long envcap;
-  T* T1; T* T2; long tcap; int nsl;
+  T* envL; T* envR; long estride;
+  T* T1; T* T2; long tcap;
+  long eoff[MAXN + 2];
+  int fixed;
   __device__ void get(int i, MpsDev<T>** d, MpsDev<T>** b, MpsDev<T>** c) const {
     *d = D.p[i];
-    prod_order(X.p[i], Y.p[i], b, c);
+    if (fixed) {
+      *b = X.p[i];
+      *c = Y.p[i];
+    } else {
+      prod_order(X.p[i], Y.p[i], b, c);
+    }
   }
-  __device__ T* L(int i, int k) const { return envL + ((long)i * nsl + k) * envcap; }
-  __device__ T* R(int i, int k) const { return envR + ((long)i * nsl + k) * envcap; }
+  __device__ T* L(int i, int k) const { return envL + i * estride + eoff[k]; }
+  __device__ T* R(int i, int k) const { return envR + i * estride + eoff[k]; }
 };
 
 template <typename T, typename Tacc>
@@ -740,7 +751,8 @@ struct FnTtQr {
 template <typename T>
 struct FnTtSvd {
   MpsList<T> L; const QrProb<T>* qp; int k; double* W; long wslot; double* US; double* Wk;
-  long uslot; double* sv; long svslot; const double* delta2; double* disc; int chi; int* fail;
+  long uslot; long wkslot; double* sv; long svslot; const double* delta2; double* disc; int chi;
+  int* fail;
   __device__ SvdProb get(int i) const {
     QrProb<T> q = qp[i];
     SvdProb p;
@@ -748,7 +760,7 @@ struct FnTtSvd {
     p.rows = q.s; p.cols = q.p; p.valid = 1;
     p.delta2 = delta2[i]; p.chi = chi;
     p.rank_out = &L.p[i]->r[k + 1];
-    p.US = US + i * uslot; p.Wk = Wk + i * uslot;
+    p.US = US + i * uslot; p.Wk = Wk + i * wkslot;
     p.sv = sv + i * svslot;
     p.disc = disc + i;
     p.fail = fail;
@@ -759,12 +771,12 @@ struct FnTtSvd {
 // core k = U_r (U S with column j divided by s_j); Wk column j scaled by s_j
 template <typename T>
 __global__ void k_tt_core(MpsList<T> L, int k, const QrProb<T>* qp, const double* US, double* Wk,
-                          long uslot, const double* sv, long svslot) {
+                          long uslot, long wkslot, const double* sv, long svslot) {
   const int i = blockIdx.y;
   MpsDev<T>* d = L.p[i];
   const int m = PHYS * d->r[k], r = d->r[k + 1], p = qp[i].p;
   const double* us = US + i * uslot;
-  double* wk = Wk + i * uslot;
+  double* wk = Wk + i * wkslot;
   const double* s = sv + i * svslot;
   T* core = core_ptr(d, k);
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < (long)m * r;
@@ -821,7 +833,8 @@ class Engine {
   int cpb[MAXN + 1];   // bond bound of rounded MPS: min(chi, full-rank bound)
   int maxbond = 1;
   long maxcore = 0;
-  long envcap = 0, tcap = 0;
+  long estride = 0, tcap = 0;  // product workspaces per problem (largest profile)
+  long ws_env = 0, ws_t = 0;     // elements allocated for envL/envR and T1/T2
   int lds_elems = 8000;
   std::vector<Mps<T>> pool;
   std::vector<int> freelist;
@@ -1158,17 +1171,6 @@ class Engine {
     istats = (int*)dalloc(4 * 16);
     HIP_OK(hipMemsetAsync(stats, 0, 8 * 16, st));
     HIP_OK(hipMemsetAsync(istats, 0, 4 * 16, st));
-    long ec = 1, tc = 1;
-    for (int k = 0; k <= n; ++k) {
-      long b = cpb[k];
-      ec = std::max(ec, b * b * b);
-    }
-    for (int k = 0; k < n; ++k) {
-      long a = cpb[k], a2 = cpb[k + 1];
-      tc = std::max(tc, std::max(a * a * PHYS * a2, PHYS * a * a2 * a2));
-    }
-    envcap = ec;
-    tcap = tc;
     fast = (sizeof(T) == 4);
     cw.sq = sq; cw.mq = mq;
     cw.G = (double*)dalloc(8 * sq * MAXB);
@@ -1180,10 +1182,60 @@ class Engine {
     cw.rank = (int*)dalloc(4 * 4 * MAXB);  // [0, 2 MAXB): per-problem pairs (pass 1, pass 2)
     cq_n = (int*)dalloc(4 * 2 * MAXB);
     ep = (EigProb*)dalloc(sizeof(EigProb) * MAXB);
-    envL = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
-    envR = (T*)dalloc(sizeof(T) * envcap * (n + 1) * pbatch);
-    T1 = (T*)dalloc(sizeof(T) * tcap * pbatch);
-    T2 = (T*)dalloc(sizeof(T) * tcap * pbatch);
+    reserve_products(cpb);
+  }
+
+  // Product workspaces for a second factor of capacity profile ccp (the
+  // candidate and the result are at most cpb): environment of bond k holds
+  // cpb[k]^2 ccp[k] elements; the intermediates of a site update hold the
+  // largest of T1 (a c 8 b'), T2 (a 8 b' c'), U1 (a' c' 8 b), U2 (8 a' b c).
+  // Grows the buffers when a profile needs more (at initialisation only).
+  void prod_sizes(const int* ccp, long* eoff, long* stride, long* tsz) const {
+    long off = 0;
+    for (int k = 0; k <= n; ++k) {
+      eoff[k] = off;
+      off += (long)cpb[k] * cpb[k] * ccp[k];
+    }
+    eoff[n + 1] = off;
+    *stride = off;
+    long tc = 1;
+    for (int k = 0; k < n; ++k) {
+      const long a = cpb[k], a2 = cpb[k + 1], c = ccp[k], c2 = ccp[k + 1];
+      tc = std::max({tc, a * c * PHYS * a2, a * PHYS * a2 * c2, a2 * c2 * PHYS * a,
+                     PHYS * a2 * a * c});
+    }
+    *tsz = tc;
+  }
+  void free_alloc(void* p) {
+    if (!p) return;
+    for (size_t i = 0; i < allocs.size(); ++i)
+      if (allocs[i] == p) {
+        (void)hipFree(p);
+        allocs.erase(allocs.begin() + i);
+        return;
+      }
+  }
+  void reserve_products(const int* ccp) {
+    long eoff[MAXN + 2], stride = 0, tsz = 0;
+    prod_sizes(ccp, eoff, &stride, &tsz);
+    estride = std::max(estride, stride);
+    tcap = std::max(tcap, tsz);
+    if (estride * pbatch > ws_env) {
+      HIP_OK(hipStreamSynchronize(st));
+      free_alloc(envL);
+      free_alloc(envR);
+      envL = (T*)dalloc(sizeof(T) * estride * pbatch);
+      envR = (T*)dalloc(sizeof(T) * estride * pbatch);
+      ws_env = estride * pbatch;
+    }
+    if (tcap * pbatch > ws_t) {
+      HIP_OK(hipStreamSynchronize(st));
+      free_alloc(T1);
+      free_alloc(T2);
+      T1 = (T*)dalloc(sizeof(T) * tcap * pbatch);
+      T2 = (T*)dalloc(sizeof(T) * tcap * pbatch);
+      ws_t = tcap * pbatch;
+    }
   }
 
   Mps<T> make_mps(const int* cap) {
@@ -1210,6 +1262,13 @@ class Engine {
     HIP_OK(hipMemcpy(m.dev, &h, sizeof(h), hipMemcpyHostToDevice));
     HIP_OK(hipMemset(m.data, 0, sizeof(T) * off));
     return m;
+  }
+
+  // An MPS of its own capacity profile outside the recycled pool (geometry
+  // masks, decomposed once and only read afterwards); never released.
+  int add_fixed(const int* cap) {
+    pool.push_back(make_mps(cap));
+    return (int)pool.size() - 1;
   }
 
   int acquire() {
@@ -1660,7 +1719,11 @@ class Engine {
   // higher-rank factor, right-canonicalised by QR; environments; sweeps
   // 1 -> n -> 1 (twice by default) with a QR centre shift after every
   // local update.
-  std::vector<int> prods(const std::vector<std::pair<int, int>>& P) {
+  // With ccp given, the second factor of every pair has that capacity
+  // profile and the first factor is the candidate (obstacle products);
+  // otherwise both factors are rounded pool MPS and the candidate is the
+  // one with the larger maximal bond.
+  std::vector<int> prods(const std::vector<std::pair<int, int>>& P, const int* ccp = nullptr) {
     std::vector<int> out(P.size());
     for (size_t i = 0; i < P.size(); ++i) out[i] = acquire();
     for (size_t off = 0; off < P.size(); off += pbatch) {
@@ -1671,14 +1734,24 @@ class Engine {
         x[i] = P[off + i].first;
         y[i] = P[off + i].second;
       }
-      prod_list(list_idx(d, 0, cnt), list_idx(x, 0, cnt), list_idx(y, 0, cnt), cnt);
+      prod_list(list_idx(d, 0, cnt), list_idx(x, 0, cnt), list_idx(y, 0, cnt), cnt,
+                ccp ? ccp : cpb, ccp ? 1 : 0);
     }
     return out;
   }
 
-  void prod_list(MpsList<T> Dl, MpsList<T> Xl, MpsList<T> Yl, int cnt) {
+  void prod_list(MpsList<T> Dl, MpsList<T> Xl, MpsList<T> Yl, int cnt, const int* ccp,
+                 int fixed) {
     products += cnt;
-    ProdCtx<T> c{Dl, Xl, Yl, envL, envR, envcap, T1, T2, tcap, n + 1};
+    ProdCtx<T> c;
+    c.D = Dl; c.X = Xl; c.Y = Yl;
+    c.envL = envL; c.envR = envR; c.T1 = T1; c.T2 = T2;
+    long stride = 0, tsz = 0;
+    prod_sizes(ccp, c.eoff, &stride, &tsz);
+    if (stride > estride || tsz > tcap) throw Error(-1, "product workspaces not reserved");
+    c.estride = estride;
+    c.tcap = tcap;
+    c.fixed = fixed;
     dim3 blk(256);
     hipLaunchKernelGGL(k_prod_init<T>, dim3(n + 1, cnt), blk, 0, st, c, n);
     // right-canonicalise the candidate
@@ -1693,7 +1766,7 @@ class Engine {
       hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)ctmp, maxcore,
                          k - 1);
     }
-    for (int k = n - 1; k >= 1; --k) right_env(c, k, cnt);
+    for (int k = n - 1; k >= 1; --k) right_env(c, k, cnt, ccp);
     std::vector<int> pos;
     for (int k = 0; k < n; ++k) pos.push_back(k);
     for (int k = n - 2; k >= 0; --k) pos.push_back(k);
@@ -1701,7 +1774,7 @@ class Engine {
     for (int s = 1; s < sweeps; ++s) pos.insert(pos.end(), one.begin() + 1, one.end());
     for (size_t idx = 0; idx < pos.size(); ++idx) {
       int p = pos[idx];
-      local_update(c, p, cnt);
+      local_update(c, p, cnt, ccp);
       if (idx + 1 == pos.size()) break;
       int nxt = pos[idx + 1];
       if (nxt > p) {
@@ -1711,8 +1784,8 @@ class Engine {
         hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), blk, 0, st, Dl, (const T*)qtmp, qslot,
                            p);
         tbegin(3);
-        pgemm(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1],
-                                   cpb[p + 1] * cpb[p + 1], 1, st, kf(3), PHYS * cpb[p]);
+        pgemm(FnG3L<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1] * ccp[p + 1], 1, st, kf(3),
+              PHYS * cpb[p]);
         tend(3);
       } else {
         qr(FnQrRightT<T>{Dl, p, qtmp, qslot, rbuf, rslot}, cnt, PHYS * cpb[p + 1], cpb[p]);
@@ -1720,37 +1793,36 @@ class Engine {
                            (const QrProb<T>*)qp, p, cnt);
         hipLaunchKernelGGL(k_store_core_T<T>, dim3(chunks(), cnt), blk, 0, st, Dl,
                            (const QrProb<T>*)qp, p);
-        right_env(c, p, cnt);
+        right_env(c, p, cnt, ccp);
       }
     }
     HIP_OK(hipGetLastError());
   }
 
-  void local_update(const ProdCtx<T>& c, int p, int cnt) {
+  // Launch capacities: bonds of the result and the candidate are at most
+  // cpb, those of the second factor at most ccp.
+  void local_update(const ProdCtx<T>& c, int p, int cnt, const int* ccp) {
     tbegin(3);
-    pgemm(FnG1<T, Tacc>{c, p}, cnt, cpb[p], PHYS * cpb[p + 1], cpb[p], st,
-                               kf(3));
+    pgemm(FnG1<T, Tacc>{c, p}, cnt, ccp[p], PHYS * cpb[p + 1], cpb[p], st, kf(3));
     tend(3);
     tbegin(3);
-    pgemm(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p + 1], PHYS * cpb[p],
-                               st, kf(3));
+    pgemm(FnG2<T, Tacc>{c, p}, cnt, cpb[p + 1], ccp[p + 1], PHYS * cpb[p], st, kf(3));
     tend(3);
     tbegin(3);
-    pgemm(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st,
-                               kf(3), cpb[p + 1] * cpb[p + 1]);
+    pgemm(FnG3<T, Tacc>{c, p}, cnt, PHYS * cpb[p], cpb[p + 1], 1, st, kf(3),
+          cpb[p + 1] * ccp[p + 1]);
     tend(3);
   }
 
-  void right_env(const ProdCtx<T>& c, int p, int cnt) {
+  void right_env(const ProdCtx<T>& c, int p, int cnt, const int* ccp) {
     tbegin(3);
-    pgemm(FnH1<T, Tacc>{c, p}, cnt, cpb[p + 1], cpb[p], PHYS * cpb[p + 1], st, kf(3));
+    pgemm(FnH1<T, Tacc>{c, p}, cnt, ccp[p + 1], cpb[p], PHYS * cpb[p + 1], st, kf(3));
     tend(3);
     tbegin(3);
-    pgemm(FnH2<T, Tacc>{c, p}, cnt, cpb[p], cpb[p], PHYS * cpb[p + 1], st,
-                               kf(3));
+    pgemm(FnH2<T, Tacc>{c, p}, cnt, cpb[p], ccp[p], PHYS * cpb[p + 1], st, kf(3));
     tend(3);
     tbegin(3);
-    pgemm(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * cpb[p], 1, st, kf(3), PHYS * cpb[p + 1]);
+    pgemm(FnH3<T, Tacc>{c, p}, cnt, cpb[p], cpb[p] * ccp[p], 1, st, kf(3), PHYS * cpb[p + 1]);
     tend(3);
   }
 
@@ -1894,9 +1966,12 @@ class Engine {
       for (int k = 0; k < n; ++k) {
         T* dst = (k % 2 == 0) ? b : a;
         T* srcb = (k % 2 == 0) ? a : b;
+        // launch capacity: the largest storage bound of the objects
+        int ncap = 1;
+        for (int i = 0; i < cnt; ++i) ncap = std::max(ncap, pool[src[off + i]].cap[k + 1]);
         // ensure the final result lands in `b`: n steps alternate a->b->a...
         launch_gemm<T, T, T, Tacc>(FnContract<T>{L, srcb, dst, N3, rows, k}, cnt, (int)rows,
-                                   PHYS * cpb[k + 1], 1, st);
+                                   PHYS * ncap, 1, st);
         rows *= PHYS;
       }
       if (n % 2 == 0) {
@@ -1918,27 +1993,36 @@ class Engine {
     RankArr ones;
     for (int k = 0; k <= MAXN; ++k) ones.r[k] = 1;
     hipLaunchKernelGGL(k_set_ranks<T>, dim3(1), dim3(64), 0, st, L, ones, cnt);
-    const long mmax = (long)PHYS * std::max(1, std::min(chi_r, maxbond));
+    // at site k the remainder has 8 r_k <= 8 min(chi_r, 8^k) rows and
+    // rest = 8^(n-1-k) columns; its QR has p = min(rows, rest) and the SVD
+    // acts on p columns, at most 1024 in one workgroup.  Slots hold the
+    // largest p x rows (R, U S) and p x p (W, W_k) of all sites.
+    long slot = 1, pmax = 1;
     {
-      // the SVD at site k has min(8^(n-1-k), 8 r_k) columns; one workgroup
-      // handles at most 1024
       long rest = N3;
       for (int k = 0; k < n - 1; ++k) {
         rest /= PHYS;
-        long m = (long)PHYS * std::min<long>(chi_r, full_bound(n, k));
-        if (std::min(rest, m) > 1024)
+        const long rows = (long)PHYS * std::min<long>(chi_r, full_bound(n, k));
+        const long p = std::min(rest, rows);
+        if (p > 1024)
           throw Error(-5, "initial decomposition needs an SVD wider than 1024 columns "
-                          "(reduce chi_max)");
+                          "(reduce chi_max or chi_mask_max)");
+        slot = std::max(slot, p * rows);
+        pmax = std::max(pmax, p);
       }
     }
+    for (int o : objs)
+      for (int k = 1; k < n; ++k)
+        if (pool[o].cap[k] < std::min(chi_r, full_bound(n, k)))
+          throw Error(-1, "decomposition target smaller than its rank bound");
     size_t mark = allocs.size();
     T* nxt = (T*)dalloc(sizeof(T) * N3 * cnt);
     T* Qb = (T*)dalloc(sizeof(T) * N3 * cnt);
-    double* Rb = (double*)dalloc(8 * mmax * mmax * cnt);
-    double* Wb = (double*)dalloc(8 * mmax * mmax * cnt);
-    double* USb = (double*)dalloc(8 * mmax * mmax * cnt);
-    double* Wkb = (double*)dalloc(8 * mmax * mmax * cnt);
-    double* svb = (double*)dalloc(8 * mmax * cnt);
+    double* Rb = (double*)dalloc(8 * slot * cnt);
+    double* Wb = (double*)dalloc(8 * pmax * pmax * cnt);
+    double* USb = (double*)dalloc(8 * slot * cnt);
+    double* Wkb = (double*)dalloc(8 * pmax * pmax * cnt);
+    double* svb = (double*)dalloc(8 * pmax * cnt);
     double* d2 = (double*)dalloc(8 * cnt);
     double* disc = (double*)dalloc(8 * cnt);
     QrWork tw = qw;
@@ -1951,24 +2035,24 @@ class Engine {
     long rest = N3;
     for (int k = 0; k < n - 1; ++k) {
       rest /= PHYS;
-      const int mcap = (int)mmax;
+      const long rows = (long)PHYS * std::min<long>(chi_r, full_bound(n, k));
       hipLaunchKernelGGL((k_qr_prep<T, FnTtQr<T>>), dim3(1), dim3(64), 0, st,
-                         FnTtQr<T>{L, cur, N3, k, rest, Qb, Rb, mmax * mmax}, qp, cnt);
-      int ch = (int)std::max<long>(1, std::min<long>(2048, (rest * mcap + 255) / 256));
+                         FnTtQr<T>{L, cur, N3, k, rest, Qb, Rb, slot}, qp, cnt);
+      int ch = (int)std::max<long>(1, std::min<long>(2048, (rest * rows + 255) / 256));
       hipLaunchKernelGGL(k_qr_identity<T>, dim3(ch, cnt), dim3(256), 0, st, (const QrProb<T>*)qp);
       hipLaunchKernelGGL(k_householder<T>, dim3(cnt), dim3(256), (size_t)lds_elems * 8, st,
                          (const QrProb<T>*)qp, tw, lds_elems, (double*)nullptr);
       hipLaunchKernelGGL(k_svd_prep<FnTtSvd<T>>, dim3(1), dim3(64), 0, st,
-                         FnTtSvd<T>{L, (const QrProb<T>*)qp, k, Wb, mmax * mmax, USb, Wkb,
-                                    mmax * mmax, svb, mmax, d2, disc, chi_r, istats},
+                         FnTtSvd<T>{L, (const QrProb<T>*)qp, k, Wb, pmax * pmax, USb, Wkb,
+                                    slot, pmax * pmax, svb, pmax, d2, disc, chi_r, istats},
                          sp, cnt);
       hipLaunchKernelGGL(k_jacobi_svd, dim3(cnt), dim3(1024), (size_t)lds_elems * 8, st,
                          (const SvdProb*)sp, lds_elems, 60, (double*)nullptr);
       hipLaunchKernelGGL(k_tt_core<T>, dim3(64, cnt), dim3(256), 0, st, L, k, (const QrProb<T>*)qp,
-                         (const double*)USb, Wkb, mmax * mmax, (const double*)svb, mmax);
+                         (const double*)USb, Wkb, slot, pmax * pmax, (const double*)svb, pmax);
       launch_gemm<double, T, T, double>(
-          FnTtNext<T>{L, (const QrProb<T>*)qp, Wkb, mmax * mmax, nxt, N3, k, rest}, cnt,
-          std::min(chi_r, maxbond), (int)rest, 1, st);
+          FnTtNext<T>{L, (const QrProb<T>*)qp, Wkb, pmax * pmax, nxt, N3, k, rest}, cnt,
+          (int)std::min<long>(chi_r, full_bound(n, k + 1)), (int)rest, 1, st);
       std::swap(cur, nxt);
     }
     hipLaunchKernelGGL(k_store_core<T>, dim3(chunks(), cnt), dim3(256), 0, st, L, (const T*)cur, N3,

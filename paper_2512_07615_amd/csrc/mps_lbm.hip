@@ -67,11 +67,23 @@ __global__ void k_div_vec(const double* num, const double* den, double* out, int
 struct Domain {
   mps_lbm_config cfg;
   int f[19];
-  int mask = -1, fluid = -1;
+  int mask = -1;
   int fplane[6];
   double n_fluid = 0.0;
   double mask_err = 0.0;
+  double face_err = 0.0;
 };
+
+// dense [x][y][z] field: 1 on the fluid cells of the plane x_ax = idx
+__global__ void k_face_plane(const uint8_t* solid, double* out, int n, int ax, int idx) {
+  const long N3 = 1L << (3 * n);
+  const int N = 1 << n;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
+       e += (long)gridDim.x * blockDim.x) {
+    const int c[3] = {(int)(e >> (2 * n)), (int)((e >> n) & (N - 1)), (int)(e & (N - 1))};
+    out[e] = (c[ax] == idx && !(solid && solid[e])) ? 1.0 : 0.0;
+  }
+}
 
 // One engine advancing D domains of equal n, chi and precision together:
 // every operation of the step is issued once for the MPS of all domains, so
@@ -140,70 +152,109 @@ struct SimT : Sim {
     E.tt_svd(W, cnt, objs, chi_r, tol_r);
   }
 
+  // Decomposition error ||m - m~|| / ||m|| of MPS obj against the dense
+  // scale-ordered field Wref (synchronises).
+  double decomposition_error(int obj, const T* Wref) {
+    T* back = (T*)E.dalloc(sizeof(T) * N3);
+    T* work = (T*)E.dalloc(sizeof(T) * N3);
+    E.to_dense({obj}, back, work);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, scratch, 0.0, 2L);
+    hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st,
+                       (const T*)back, Wref, N3, scratch);
+    double hnorm[2];
+    HIP_OK(hipMemcpyAsync(hnorm, scratch, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    E.free_alloc(work);
+    E.free_alloc(back);
+    return hnorm[1] > 0 ? std::sqrt(hnorm[0] / hnorm[1]) : 0.0;
+  }
+
+  // capacity profile of the obstacle masks: min(chi_mask_max, 8^k, 8^(n-k)),
+  // no cap when chi_mask_max <= 0 (the mask at machine precision)
+  int mask_cap(int k) const {
+    const int c = dom[0].cfg.chi_mask_max > 0 ? dom[0].cfg.chi_mask_max : (1 << 30);
+    return (k == 0 || k == n) ? 1 : std::min(c, Engine<T>::full_bound(n, k));
+  }
+  int mcp[MAXN + 1];    // product launch capacities of the masks' bonds
+  bool any_mask = false;
+
   // Initial state of domain d from dense fields (all synchronous).
   void init_domain(int d, const double* rho, const double* u, const double* fin,
                    const uint8_t* solid) {
     Domain& dm = dom[d];
     const mps_lbm_config& cfg = dm.cfg;
-    const int chi_mask =
-        cfg.chi_mask_max > 0 ? std::min(cfg.chi_mask_max, cfg.chi_max) : cfg.chi_max;
-    size_t mark = E.allocs.size();
-    double* dd = (double*)E.dalloc(8 * N3 * 19);  // dense staging (FP64)
-    T* W = (T*)E.dalloc(sizeof(T) * N3 * 19);
+    // dense staging, released at the end (the masks allocated on the way
+    // stay)
+    std::vector<void*> staged;
+    auto stage = [&](size_t bytes) {
+      void* p = E.dalloc(bytes);
+      staged.push_back(p);
+      return p;
+    };
+    double* dd = (double*)stage(8 * N3 * 19);
+    T* W = (T*)stage(sizeof(T) * N3 * 19);
     uint8_t* dsolid = nullptr;
     if (solid) {
-      dsolid = (uint8_t*)E.dalloc(N3);
+      dsolid = (uint8_t*)stage(N3);
       HIP_OK(hipMemcpy(dsolid, solid, N3, hipMemcpyHostToDevice));
       std::vector<double> hs(N3);
       for (long e = 0; e < N3; ++e) hs[e] = solid[e] ? 1.0 : 0.0;
       HIP_OK(hipMemcpy(dd, hs.data(), 8 * N3, hipMemcpyHostToDevice));
       hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(N3)), dim3(256), 0, st,
                          (const double*)dd, W, n, 1, 1);
-      dm.mask = E.acquire();
-      T* Wkeep = (T*)E.dalloc(sizeof(T) * N3);
+      // obstacle mask (objects equation): TT-SVD of the solid field at
+      // tol_mask in an MPS of its own capacity, by default uncapped, i.e.
+      // at machine precision (the mask bond dimension of Section 5.2)
+      int cap[MAXN + 1];
+      for (int k = 0; k <= n; ++k) cap[k] = mask_cap(k);
+      dm.mask = E.add_fixed(cap);
+      T* Wkeep = (T*)stage(sizeof(T) * N3);
       hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W,
                          Wkeep, N3);
+      const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
       dense_to_mps(W, 1, {dm.mask}, chi_mask, cfg.tol_mask);
-      // decomposition error of the mask
-      T* back = (T*)E.dalloc(sizeof(T) * N3);
-      T* work = (T*)E.dalloc(sizeof(T) * N3);
-      E.to_dense({dm.mask}, back, work);
-      HIP_OK(hipMemsetAsync(scratch, 0, 16, st));
-      hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st,
-                         (const T*)back, (const T*)Wkeep, N3, scratch);
-      double hnorm[2];
-      HIP_OK(hipMemcpyAsync(hnorm, scratch, 16, hipMemcpyDeviceToHost, st));
+      dm.mask_err = decomposition_error(dm.mask, Wkeep);
       E.inner_ones({dm.mask}, scratch + 2);
       double ones_m = 0.0;
+      MpsDev<T> md;
       HIP_OK(hipMemcpyAsync(&ones_m, scratch + 2, 8, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(&md, E.D(dm.mask), sizeof(md), hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
-      dm.mask_err = hnorm[1] > 0 ? std::sqrt(hnorm[0] / hnorm[1]) : 0.0;
       dm.n_fluid = (double)N3 - ones_m;
-      // fluid = round(1 - m)
-      dm.fluid = E.acquire();
-      E.add({dm.fluid}, {one}, {dm.mask}, {Coef{1.0, 0, d}, Coef{-1.0, 0, d}}, nullptr);
-      E.round({dm.fluid}, cfg.chi_max, cfg.tol_mask);
+      if (!any_mask)
+        for (int k = 0; k <= n; ++k) mcp[k] = 1;
+      any_mask = true;
+      for (int k = 0; k <= n; ++k) mcp[k] = std::max(mcp[k], md.r[k]);
     } else {
       dm.n_fluid = (double)N3;
-      dm.fluid = one;
     }
     HIP_OK(hipMemcpyAsync(nfl + d, &dm.n_fluid, 8, hipMemcpyHostToDevice, st));
-    // open-face planes of the fluid indicator
+    // face masks m_B (boundaries equations): the fluid cells of each open
+    // face plane, decomposed from that dense field at tol_mask; they enter
+    // population sums, so their rank is capped at chi_max
     for (int ax = 0; ax < 3; ++ax) {
       if (!cfg.axis_open[ax]) continue;
       for (int side = 0; side < 2; ++side) {
         int face = 2 * ax + side;
         if (cfg.face_bc[face] == MPS_LBM_BC_NONE) continue;
-        std::vector<int> o = E.slice({dm.fluid}, {ax}, {side == 0 ? 0 : N - 1});
-        dm.fplane[face] = o[0];
+        hipLaunchKernelGGL(k_face_plane, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                           (const uint8_t*)dsolid, dd, n, ax, side == 0 ? 0 : N - 1);
+        hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(N3)), dim3(256), 0,
+                           st, (const double*)dd, W, n, 1, 1);
+        T* Wkeep = (T*)stage(sizeof(T) * N3);
+        hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                           (const T*)W, Wkeep, N3);
+        dm.fplane[face] = E.acquire();
+        dense_to_mps(W, 1, {dm.fplane[face]}, cfg.chi_max, cfg.tol_mask);
+        dm.face_err = std::max(dm.face_err, decomposition_error(dm.fplane[face], Wkeep));
       }
     }
     // initial populations
     if (fin) {
       HIP_OK(hipMemcpy(dd, fin, 8 * N3 * 19, hipMemcpyHostToDevice));
     } else {
-      double* drho = (double*)E.dalloc(8 * N3);
-      double* du = (double*)E.dalloc(8 * N3 * 3);
+      double* drho = (double*)stage(8 * N3);
+      double* du = (double*)stage(8 * N3 * 3);
       HIP_OK(hipMemcpy(drho, rho, 8 * N3, hipMemcpyHostToDevice));
       HIP_OK(hipMemcpy(du, u, 8 * N3 * 3, hipMemcpyHostToDevice));
       hipLaunchKernelGGL(k_feq_dense, dim3(dense_chunks(N3)), dim3(256), 0, st,
@@ -216,11 +267,13 @@ struct SimT : Sim {
     for (int i = 0; i < 19; ++i) objs[i] = dm.f[i] = E.acquire();
     dense_to_mps(W, 19, objs, cfg.chi_max, cfg.tol);
     HIP_OK(hipStreamSynchronize(st));
-    // release the dense staging
-    while (E.allocs.size() > mark) {
-      (void)hipFree(E.allocs.back());
-      E.allocs.pop_back();
-    }
+    for (void* p : staged) E.free_alloc(p);
+  }
+
+  // After every domain is initialised: product workspaces for the masks'
+  // bond profile (the obstacle products' second factor).
+  void finish_init() {
+    if (any_mask) E.reserve_products(mcp);
   }
 
   // ---------------------------------------------------------------- step
@@ -485,7 +538,8 @@ struct SimT : Sim {
         std::vector<std::pair<int, int>> pm;
         for (int d : dd)
           for (int i = 1; i < 19; ++i) pm.push_back({fs[19 * d + i], dom[d].mask});
-        std::vector<int> g1 = E.prods(pm);  // g1[18 k + i - 1]
+        // candidate = the population (its bonds are those the result keeps)
+        std::vector<int> g1 = E.prods(pm, mcp);  // g1[18 k + i - 1]
         std::vector<int> hs;
         std::vector<const int*> hc, ha;
         for (size_t k = 0; k < dd.size(); ++k)
@@ -737,6 +791,7 @@ struct SimT : Sim {
       for (int k = 1; k < n; ++k) mk = std::max(mk, md.r[k]);
     o->mask_bond = dm.mask >= 0 ? mk : 0;
     o->mask_trunc_err = dm.mask_err;
+    o->face_trunc_err = dm.face_err;
     o->roundings = last_roundings;
     o->products = last_products;
     o->svd_failures = ist[0];
@@ -831,12 +886,14 @@ static int create(const mps_lbm_config* cfgs, int count, const double* const* rh
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
                        solid ? solid[d] : nullptr);
+      s->finish_init();
     } else {
       auto* s = new SimT<float>(cfgs, count, st);
       h->sim.reset(s);
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
                        solid ? solid[d] : nullptr);
+      s->finish_init();
     }
     *out = h.release();
     g_last_error.clear();

@@ -59,6 +59,7 @@ class Obs(C.Structure):
         ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
         ("jacobi_sweeps", C.c_double), ("lds_bytes", C.c_int),
         ("rs_attempted", C.c_longlong), ("rs_accepted", C.c_longlong),
+        ("face_trunc_err", C.c_double),
     ]
 
 
