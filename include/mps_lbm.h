@@ -43,7 +43,11 @@ extern "C" {
 #define MPS_LBM_D3Q19 19
 
 /* arithmetic of the step (storage and contractions); the R-factor SVDs,
-   rank selection and 1/rho coefficients are FP64 under every policy.
+   rank selection and 1/rho coefficients are FP64 under every policy, and
+   under FP32, BF16 and BF16X3 the inverse density (Section 3.2, Appendix B:
+   the sums and variational products of the Taylor or Newton-Schulz form)
+   runs in FP64 too, on a copy of rho converted to FP64, its result
+   converted back to FP32.
    BF16: FP32 storage and factorisations as MPS_LBM_FP32, with the
    contractions of the variational products (Section 2.3) run on BF16 MFMA
    (operands rounded to BF16, FP32 accumulation).  BF16X3: as BF16, but each
@@ -133,6 +137,23 @@ typedef struct {
                               decomposed at tol_mask with rank cap chi_max */
 } mps_lbm_obs;
 
+/*
+ * Register the source of every device buffer of handles created from now on
+ * (process-wide; each handle keeps the allocator it was created with).
+ * alloc(bytes, stream, ctx) returns device memory usable on `stream` (the
+ * handle's hip_stream, NULL for handle-less calls) or NULL when it has none
+ * left, which the calling entry point reports as MPS_LBM_ENOMEM; free_(ptr,
+ * stream, ctx) takes back what alloc returned.  Meant for a framework's
+ * caching allocator (the Python binding registers PyTorch's), so that the
+ * library's state, workspaces and read-back staging share its memory pool.
+ * Both NULL restore hipMalloc / hipFree.  The library calls free_ only after
+ * the stream has finished with the buffer.  (Section 3.2 describes the
+ * step; this call only concerns where its memory lives.)
+ * Errors: EINVAL (exactly one of alloc, free_ is NULL).
+ */
+int mps_lbm_set_allocator(void* (*alloc)(size_t bytes, void* stream, void* ctx),
+                          void (*free_)(void* ptr, void* stream, void* ctx), void* ctx);
+
 /* Fill *cfg with defaults: D3Q19, FP64, TAYLOR2, 2 sweeps, tol 1e-10,
    tol_mask 1e-12, tau 0.8, periodic, no force, chi_max 16, no rank
    predictor (oversampling 16). */
@@ -157,6 +178,18 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho,
                             mps_lbm_t** out);
 
 /*
+ * Numerical failures.  The factorisation kernels flag non-finite values and
+ * Jacobi sweeps that stop at their iteration limit (Section 2.1 truncations)
+ * in device memory.  Every call that synchronises with the device to read
+ * the state (mps_lbm_to_dense*, mps_lbm_get_mps) first checks these flags:
+ * a non-finite value makes it, and every later such call and mps_lbm_step,
+ * return MPS_LBM_ENUMERIC without writing outputs or stepping (the handle
+ * remains destroyable and mps_lbm_observables still reports the counts); new
+ * sweep-limit hits are returned once as MPS_LBM_ENUMERIC, after which the
+ * state can be read again.
+ */
+
+/*
  * Advance nsteps lattice Boltzmann steps (Section 3.2): moments,
  * 1/rho approximation, equilibrium by variational Hadamard products
  * (Section 2.3), BGK relaxation, streaming by shift MPOs (Section 2.5),
@@ -165,6 +198,13 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho,
  * no host synchronisation.  Errors: EINVAL (NULL handle, nsteps < 0), EHIP.
  */
 int mps_lbm_step(mps_lbm_t* h, int nsteps);
+
+/* Testing hook for the numerical-failure path: adds nonfinite to the
+   device's non-finite count and sweep_limit to its sweep-limit count, as a
+   kernel that met them would (enqueued on the handle's stream; no kernel
+   computes on invalid data).  Errors: EINVAL (NULL handle, negative
+   counts), EHIP. */
+int mps_lbm_debug_raise_flags(mps_lbm_t* h, int nonfinite, int sweep_limit);
 
 /*
  * Contract the state to a dense host array (synchronises the stream).
@@ -297,6 +337,16 @@ typedef struct {
    than 16 samples), EUNSUPPORTED (predictor not in mode 2, or after graph
    capture). */
 int mps_lbm_train_rank_predictor(mps_lbm_t* h, int epochs, double lr, double* loss_out);
+
+/* Trained weights of the predictor network (37505 FP32 values in the
+   layout of mps_lbm_mlp_gradient's params): load copies them into the
+   handle and marks the network trained, so that a model trained once can
+   size the sketches of later runs; get copies the handle's weights out.
+   Both synchronise the stream.  Errors: EINVAL (NULL handle or weights,
+   n != 37505 for load, n < 37505 for get), EUNSUPPORTED (predictor not in
+   mode 2; load after graph capture), EHIP. */
+int mps_lbm_load_rank_model(mps_lbm_t* h, const float* weights, size_t n);
+int mps_lbm_get_rank_model(mps_lbm_t* h, float* weights, size_t n);
 
 /* Predictor statistics (all zero when the predictor is not in mode 2).
    Errors: EINVAL (NULL handle or out), EHIP. */

@@ -14,6 +14,15 @@ constexpr int PHYS = 8;      // physical dimension of a site (x, y, z bits)
 constexpr int WG = 256;      // threads per workgroup for the batched kernels
 constexpr int MAXB = 64;     // maximum batch of a single launch
 
+// Device memory source of a handle: the caller's callbacks (for example a
+// framework's caching allocator), each called with the handle's stream, or
+// hipMalloc / hipFree when none are registered.
+struct Allocator {
+  void* (*alloc)(size_t bytes, void* stream, void* ctx) = nullptr;
+  void (*free_)(void* ptr, void* stream, void* ctx) = nullptr;
+  void* ctx = nullptr;
+};
+
 // Error carried through the host code as an exception (never crosses the ABI).
 struct Error : std::runtime_error {
   int code;

@@ -1085,18 +1085,37 @@ class Engine {
     ev_next = 0;
   }
 
+  // every device buffer of the engine comes from here (and goes back
+  // through dfree), through the handle's allocator on the engine's stream
+  Allocator al;
   void* dalloc(size_t bytes) {
     void* p = nullptr;
     if (bytes == 0) bytes = 256;
-    if (hipMalloc(&p, bytes) != hipSuccess) {
+    if (al.alloc) {
+      p = al.alloc(bytes, (void*)st, al.ctx);
+      if (!p) throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
+    } else if (hipMalloc(&p, bytes) != hipSuccess) {
       (void)hipGetLastError();
       throw Error(-2, "device allocation of " + std::to_string(bytes) + " bytes failed");
     }
-    allocs.push_back(p);
+    try {
+      allocs.push_back(p);
+    } catch (...) {
+      dfree(p);
+      throw;
+    }
     return p;
   }
+  void dfree(void* p) {
+    if (!p) return;
+    if (al.free_)
+      al.free_(p, (void*)st, al.ctx);
+    else
+      (void)hipFree(p);
+  }
   ~Engine() {
-    for (void* p : allocs) (void)hipFree(p);
+    (void)hipStreamSynchronize(st);
+    for (void* p : allocs) dfree(p);
     for (auto& e : evs) (void)hipEventDestroy(e);
   }
 
@@ -1210,7 +1229,7 @@ class Engine {
     if (!p) return;
     for (size_t i = 0; i < allocs.size(); ++i)
       if (allocs[i] == p) {
-        (void)hipFree(p);
+        dfree(p);
         allocs.erase(allocs.begin() + i);
         return;
       }
@@ -1269,6 +1288,14 @@ class Engine {
   int add_fixed(const int* cap) {
     pool.push_back(make_mps(cap));
     return (int)pool.size() - 1;
+  }
+
+  // frees the storage of an add_fixed object (its index is not reused)
+  void drop_fixed(int i) {
+    free_alloc(pool[i].data);
+    free_alloc(pool[i].dev);
+    pool[i].data = nullptr;
+    pool[i].dev = nullptr;
   }
 
   int acquire() {
@@ -1419,14 +1446,11 @@ class Engine {
       std::tie(acc, m, nn, kk, np, nb) = c;
       const size_t ea = (size_t)m * kk, eb = (size_t)kk * nn, ec = (size_t)np * nb * m * nn;
       const size_t w = acc == 0 ? 8 : 4;
-      void *A = nullptr, *B = nullptr, *C = nullptr;
-      if (hipMalloc(&A, w * ea) != hipSuccess || hipMalloc(&B, w * eb) != hipSuccess ||
-          hipMalloc(&C, w * ec) != hipSuccess) {
-        (void)hipGetLastError();
-        if (A) (void)hipFree(A);
-        if (B) (void)hipFree(B);
-        throw Error(-2, "autotuner scratch allocation failed");
-      }
+      // scratch operands, freed one by one afterwards: the split-K
+      // workspace may grow while a class is timed and must stay
+      void* A = dalloc(w * ea);
+      void* B = dalloc(w * eb);
+      void* C = dalloc(w * ec);
       HIP_OK(hipMemsetAsync(A, 0, w * ea, st));
       HIP_OK(hipMemsetAsync(B, 0, w * eb, st));
       int sp = 1;
@@ -1435,9 +1459,9 @@ class Engine {
       else if (acc == 2) sp = tune_class<float, float, 1>(c, A, B, C);
       else sp = tune_class<float, float, 2>(c, A, B, C);
       HIP_OK(hipStreamSynchronize(st));
-      (void)hipFree(A);
-      (void)hipFree(B);
-      (void)hipFree(C);
+      free_alloc(C);
+      free_alloc(B);
+      free_alloc(A);
       ktab[c] = sp;
       ++tuned;
     }
@@ -2015,19 +2039,24 @@ class Engine {
       for (int k = 1; k < n; ++k)
         if (pool[o].cap[k] < std::min(chi_r, full_bound(n, k)))
           throw Error(-1, "decomposition target smaller than its rank bound");
-    size_t mark = allocs.size();
-    T* nxt = (T*)dalloc(sizeof(T) * N3 * cnt);
-    T* Qb = (T*)dalloc(sizeof(T) * N3 * cnt);
-    double* Rb = (double*)dalloc(8 * slot * cnt);
-    double* Wb = (double*)dalloc(8 * pmax * pmax * cnt);
-    double* USb = (double*)dalloc(8 * slot * cnt);
-    double* Wkb = (double*)dalloc(8 * pmax * pmax * cnt);
-    double* svb = (double*)dalloc(8 * pmax * cnt);
-    double* d2 = (double*)dalloc(8 * cnt);
-    double* disc = (double*)dalloc(8 * cnt);
+    std::vector<void*> tmp;
+    auto tdalloc = [&](size_t b) {
+      void* q = dalloc(b);
+      tmp.push_back(q);
+      return q;
+    };
+    T* nxt = (T*)tdalloc(sizeof(T) * N3 * cnt);
+    T* Qb = (T*)tdalloc(sizeof(T) * N3 * cnt);
+    double* Rb = (double*)tdalloc(8 * slot * cnt);
+    double* Wb = (double*)tdalloc(8 * pmax * pmax * cnt);
+    double* USb = (double*)tdalloc(8 * slot * cnt);
+    double* Wkb = (double*)tdalloc(8 * pmax * pmax * cnt);
+    double* svb = (double*)tdalloc(8 * pmax * cnt);
+    double* d2 = (double*)tdalloc(8 * cnt);
+    double* disc = (double*)tdalloc(8 * cnt);
     QrWork tw = qw;
-    tw.Q1 = (double*)dalloc(8 * N3 * cnt);
-    tw.Q2 = (double*)dalloc(8 * N3 * cnt);
+    tw.Q1 = (double*)tdalloc(8 * N3 * cnt);
+    tw.Q2 = (double*)tdalloc(8 * N3 * cnt);
     tw.mq = N3;
     hipLaunchKernelGGL(k_dense_delta2<T>, dim3(cnt), dim3(256), 0, st, (const T*)W, N3, cnt,
                        tol_r * tol_r / (double)(n > 1 ? n - 1 : 1), d2);
@@ -2059,10 +2088,7 @@ class Engine {
                        n - 1);
     HIP_OK(hipGetLastError());
     HIP_OK(hipStreamSynchronize(st));
-    while (allocs.size() > mark) {
-      (void)hipFree(allocs.back());
-      allocs.pop_back();
-    }
+    for (void* q : tmp) free_alloc(q);
   }
 };
 

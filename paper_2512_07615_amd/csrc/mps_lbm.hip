@@ -56,7 +56,35 @@ struct Sim {
   virtual float train_predictor(int epochs, float lr) = 0;
   virtual int autotune() = 0;
   virtual void predictor_info(mps_lbm_predictor_info* o) = 0;
+  virtual int numeric_status() = 0;
+  virtual bool fatal_seen() const = 0;
+  virtual void raise_flags(int nonfinite, int sweep_limit) = 0;
+  virtual void rank_model(float* w, int load) = 0;
 };
+
+// Copy MPS i of S into MPS i of D (same capacity profile), converting the
+// element type: ranks and the cores in use.
+template <typename Ts, typename Td>
+__global__ void k_convert_mps(MpsList<Ts> S, MpsList<Td> Dl, int n) {
+  const int i = blockIdx.z, k = blockIdx.y;
+  const MpsDev<Ts>* a = S.p[i];
+  MpsDev<Td>* b = Dl.p[i];
+  if (blockIdx.x == 0 && k == 0 && (int)threadIdx.x <= n) b->r[threadIdx.x] = a->r[threadIdx.x];
+  if (k >= n) return;
+  const long tot = (long)a->r[k] * PHYS * a->r[k + 1];
+  const Ts* x = a->data + a->off[k];
+  Td* y = b->data + b->off[k];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x)
+    y[e] = (Td)x[e];
+}
+
+__global__ void k_add_flags(int* istats, int sweep_limit, int nonfinite) {
+  if (threadIdx.x == 0) {
+    istats[0] += sweep_limit;
+    istats[1] += nonfinite;
+  }
+}
 
 __global__ void k_div_vec(const double* num, const double* den, double* out, int cnt) {
   int i = threadIdx.x;
@@ -93,6 +121,8 @@ struct SimT : Sim {
   typedef typename Engine<T>::Term Term;
   typedef typename Engine<T>::PairSum PairSum;
   Engine<T> E;
+  std::unique_ptr<Engine<double>> X;  // FP64 island (reduced-precision policies)
+  int one64 = -1;
   hipStream_t st;
   int n, N, D;
   long N3;
@@ -106,8 +136,10 @@ struct SimT : Sim {
   long long steps = 0;
   long long last_roundings = 0, last_products = 0;
 
-  SimT(const mps_lbm_config* cfgs, int count, hipStream_t s) : st(s) {
+  SimT(const mps_lbm_config* cfgs, int count, hipStream_t s, const Allocator& al) : st(s) {
     const mps_lbm_config& c = cfgs[0];
+    E.al = al;
+    E.st = s;
     D = count;
     n = c.n;
     N = 1 << n;
@@ -120,6 +152,16 @@ struct SimT : Sim {
     E.sweeps = c.sweeps;
     E.bf16_products = c.precision == MPS_LBM_BF16 ? 1 : c.precision == MPS_LBM_BF16X3 ? 2 : 0;
     E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
+    if (sizeof(T) == 4) {
+      // FP64 island of the reduced-precision policies: the inverse density
+      // (its sums and products) runs in an FP64 engine on the same stream
+      X.reset(new Engine<double>());
+      X->al = al;
+      X->sweeps = c.sweeps;
+      X->setup(n, c.chi_max, c.tol, s, 8 + 8 * D, std::min(MAXB, D));
+      one64 = X->acquire();
+      X->set_ones(one64);
+    }
     if (c.rank_predictor) E.enable_rsvd(c.rank_oversample, c.seed);
     if (c.rank_predictor == 2) E.enable_mlp(c.seed);
     rho0 = (double*)E.dalloc(8 * (D + 8));
@@ -148,8 +190,38 @@ struct SimT : Sim {
 
   // dense -> MPS: TT-SVD (Section 2.1, svd-comp equation) of cnt
   // scale-ordered fields W, truncated at (chi_r, tol_r).  W is overwritten.
-  void dense_to_mps(T* W, int cnt, const std::vector<int>& objs, int chi_r, double tol_r) {
-    E.tt_svd(W, cnt, objs, chi_r, tol_r);
+  // W holds the same fields scale-ordered in the working type.  Under the
+  // reduced-precision policies the decomposition runs in the FP64 engine on
+  // the FP64 fields (so that ranks are decided as in FP64 arithmetic) and the
+  // cores are then converted; objects of the recycled pool go through pool
+  // objects of the FP64 engine, others (the obstacle masks, capacity cap)
+  // through a fixed FP64 object of that profile.
+  void dense_to_mps(const double* dense, T* W, int cnt, const std::vector<int>& objs, int chi_r,
+                    double tol_r, const int* cap = nullptr) {
+    if (!X) {
+      E.tt_svd(W, cnt, objs, chi_r, tol_r);
+      return;
+    }
+    double* W64 = (double*)X->dalloc(8 * N3 * cnt);
+    hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(cnt * N3)), dim3(256),
+                       0, st, dense, W64, n, cnt, 1);
+    std::vector<int> xo(cnt);
+    for (int i = 0; i < cnt; ++i) xo[i] = cap ? X->add_fixed(cap) : X->acquire();
+    X->tt_svd(W64, cnt, xo, chi_r, tol_r);
+    for (size_t off = 0; off < xo.size(); off += MAXB) {
+      const int c = (int)std::min<size_t>(MAXB, xo.size() - off);
+      hipLaunchKernelGGL((k_convert_mps<double, T>), dim3(E.chunks(), n, c), dim3(256), 0, st,
+                         X->list_idx(xo, off, c), E.list_idx(objs, off, c), n);
+    }
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    X->free_alloc(W64);
+    for (int o : xo) {
+      if (cap)
+        X->drop_fixed(o);
+      else
+        X->release(o);
+    }
   }
 
   // Decomposition error ||m - m~|| / ||m|| of MPS obj against the dense
@@ -212,7 +284,7 @@ struct SimT : Sim {
       hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W,
                          Wkeep, N3);
       const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
-      dense_to_mps(W, 1, {dm.mask}, chi_mask, cfg.tol_mask);
+      dense_to_mps(dd, W, 1, {dm.mask}, chi_mask, cfg.tol_mask, cap);
       dm.mask_err = decomposition_error(dm.mask, Wkeep);
       E.inner_ones({dm.mask}, scratch + 2);
       double ones_m = 0.0;
@@ -245,7 +317,7 @@ struct SimT : Sim {
         hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st,
                            (const T*)W, Wkeep, N3);
         dm.fplane[face] = E.acquire();
-        dense_to_mps(W, 1, {dm.fplane[face]}, cfg.chi_max, cfg.tol_mask);
+        dense_to_mps(dd, W, 1, {dm.fplane[face]}, cfg.chi_max, cfg.tol_mask);
         dm.face_err = std::max(dm.face_err, decomposition_error(dm.fplane[face], Wkeep));
       }
     }
@@ -265,7 +337,7 @@ struct SimT : Sim {
                        st, (const double*)dd, W, n, 19, 1);
     std::vector<int> objs(19);
     for (int i = 0; i < 19; ++i) objs[i] = dm.f[i] = E.acquire();
-    dense_to_mps(W, 19, objs, cfg.chi_max, cfg.tol);
+    dense_to_mps(dd, W, 19, objs, cfg.chi_max, cfg.tol);
     HIP_OK(hipStreamSynchronize(st));
     for (void* p : staged) E.free_alloc(p);
   }
@@ -274,6 +346,91 @@ struct SimT : Sim {
   // bond profile (the obstacle products' second factor).
   void finish_init() {
     if (any_mask) E.reserve_products(mcp);
+  }
+
+  // Objects of E copied into fresh objects of X (to FP64) and back.
+  std::vector<int> to_island(const std::vector<int>& src) {
+    std::vector<int> dst(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = X->acquire();
+    for (size_t off = 0; off < src.size(); off += MAXB) {
+      const int cnt = (int)std::min<size_t>(MAXB, src.size() - off);
+      hipLaunchKernelGGL((k_convert_mps<T, double>), dim3(E.chunks(), n, cnt), dim3(256), 0, st,
+                         E.list_idx(src, off, cnt), X->list_idx(dst, off, cnt), n);
+    }
+    HIP_OK(hipGetLastError());
+    return dst;
+  }
+  std::vector<int> from_island(const std::vector<int>& src) {
+    std::vector<int> dst(src.size());
+    for (size_t i = 0; i < src.size(); ++i) dst[i] = E.acquire();
+    for (size_t off = 0; off < src.size(); off += MAXB) {
+      const int cnt = (int)std::min<size_t>(MAXB, src.size() - off);
+      hipLaunchKernelGGL((k_convert_mps<double, T>), dim3(E.chunks(), n, cnt), dim3(256), 0, st,
+                         X->list_idx(src, off, cnt), E.list_idx(dst, off, cnt), n);
+    }
+    HIP_OK(hipGetLastError());
+    return dst;
+  }
+
+  // Inverse density of every domain (Section 3.2; Appendix B) on engine Q
+  // with its unit MPS one_q: Taylor-2 about rho_0, r = (1/rho_0)(1 - e +
+  // e (.) e) with e = rho/rho_0 - 1, or Newton-Schulz from 1/rho_0.  The
+  // first sums of the chosen form are rounded together with the sums
+  // `extra` (appended; their results are returned in *extra_out).
+  template <typename U>
+  std::vector<int> inverse_density(Engine<U>& Q, int one_q, const std::vector<int>& rho,
+                                   const std::vector<std::vector<typename Engine<U>::Term>>& extra,
+                                   std::vector<int>* extra_out) {
+    typedef typename Engine<U>::Term TermU;
+    const mps_lbm_config& c0 = dom[0].cfg;
+    auto first = [&](std::vector<std::vector<TermU>> SF) {
+      SF.insert(SF.end(), extra.begin(), extra.end());
+      std::vector<int> o = Q.sums(SF, rho0);
+      if (extra_out) extra_out->assign(o.begin() + D, o.end());
+      o.resize(D);
+      return o;
+    };
+    std::vector<int> r(D);
+    if (c0.inv_rho_mode == MPS_LBM_INV_TAYLOR2) {
+      std::vector<std::vector<TermU>> SE(D);
+      for (int d = 0; d < D; ++d) SE[d] = {{Coef{1.0, -1, d}, rho[d]}, {Coef{-1.0, 0, d}, one_q}};
+      std::vector<int> e = first(SE);
+      std::vector<std::pair<int, int>> pe;
+      for (int d = 0; d < D; ++d) pe.push_back({e[d], e[d]});
+      std::vector<int> ee = Q.prods(pe);
+      std::vector<std::vector<TermU>> SR(D);
+      for (int d = 0; d < D; ++d)
+        SR[d] = {{Coef{1.0, -1, d}, one_q}, {Coef{-1.0, -1, d}, e[d]}, {Coef{1.0, -1, d}, ee[d]}};
+      r = Q.sums(SR, rho0);
+      for (int d = 0; d < D; ++d) {
+        Q.release(e[d]);
+        Q.release(ee[d]);
+      }
+    } else {
+      std::vector<std::vector<TermU>> SY(D);
+      for (int d = 0; d < D; ++d)
+        SY[d] = {{Coef{2.0, -1, d}, one_q}, {Coef{-1.0, -2, d}, rho[d]}};
+      std::vector<int> y = first(SY);
+      for (int it = 1; it < c0.inv_rho_iters; ++it) {
+        std::vector<std::pair<int, int>> p1;
+        for (int d = 0; d < D; ++d) p1.push_back({rho[d], y[d]});
+        std::vector<int> ry = Q.prods(p1);
+        std::vector<std::vector<TermU>> ST(D);
+        for (int d = 0; d < D; ++d) ST[d] = {{Coef{2.0, 0, d}, one_q}, {Coef{-1.0, 0, d}, ry[d]}};
+        std::vector<int> t = Q.sums(ST, rho0);
+        std::vector<std::pair<int, int>> p2;
+        for (int d = 0; d < D; ++d) p2.push_back({y[d], t[d]});
+        std::vector<int> y2 = Q.prods(p2);
+        for (int d = 0; d < D; ++d) {
+          Q.release(ry[d]);
+          Q.release(t[d]);
+          Q.release(y[d]);
+        }
+        y = y2;
+      }
+      r = y;
+    }
+    return r;
   }
 
   // ---------------------------------------------------------------- step
@@ -317,58 +474,27 @@ struct SimT : Sim {
           jeq[3 * d + a] = j[3 * d + a];
         }
       }
-    // the sums SF followed by SJ in one batch; the j_eq results are placed
-    // into jeq and the first D results returned
-    auto with_jeq = [&](std::vector<std::vector<Term>> SF) {
-      SF.insert(SF.end(), SJ.begin(), SJ.end());
-      std::vector<int> o = E.sums(SF, rho0);
-      for (size_t q = 0; q < which.size(); ++q) {
-        E.release(j[which[q]]);
-        jeq[which[q]] = o[D + q];
-      }
-      o.resize(D);
-      return o;
-    };
-    // 3. inverse density (every domain of a handle uses the same mode)
-    const mps_lbm_config& c0 = dom[0].cfg;
-    std::vector<int> r(D);
-    if (c0.inv_rho_mode == MPS_LBM_INV_TAYLOR2) {
-      std::vector<std::vector<Term>> SE(D);
-      for (int d = 0; d < D; ++d) SE[d] = {{Coef{1.0, -1, d}, rho[d]}, {Coef{-1.0, 0, d}, one}};
-      std::vector<int> e = with_jeq(SE);
-      std::vector<std::pair<int, int>> pe;
-      for (int d = 0; d < D; ++d) pe.push_back({e[d], e[d]});
-      std::vector<int> ee = E.prods(pe);
-      std::vector<std::vector<Term>> SR(D);
-      for (int d = 0; d < D; ++d)
-        SR[d] = {{Coef{1.0, -1, d}, one}, {Coef{-1.0, -1, d}, e[d]}, {Coef{1.0, -1, d}, ee[d]}};
-      r = E.sums(SR, rho0);
+    // 3. inverse density (every domain of a handle uses the same mode); the
+    // j_eq sums need only the moments and are rounded with its first sums,
+    // or, with the FP64 island, on their own
+    std::vector<int> r(D), jq;
+    if (X) {
+      X->roundings = 0;
+      X->products = 0;
+      std::vector<int> rho64 = to_island(rho);
+      std::vector<int> r64 = inverse_density(*X, one64, rho64, {}, nullptr);
+      r = from_island(r64);
       for (int d = 0; d < D; ++d) {
-        E.release(e[d]);
-        E.release(ee[d]);
+        X->release(rho64[d]);
+        X->release(r64[d]);
       }
+      if (!SJ.empty()) jq = E.sums(SJ, rho0);
     } else {
-      std::vector<std::vector<Term>> SY(D);
-      for (int d = 0; d < D; ++d) SY[d] = {{Coef{2.0, -1, d}, one}, {Coef{-1.0, -2, d}, rho[d]}};
-      std::vector<int> y = with_jeq(SY);
-      for (int it = 1; it < c0.inv_rho_iters; ++it) {
-        std::vector<std::pair<int, int>> p1;
-        for (int d = 0; d < D; ++d) p1.push_back({rho[d], y[d]});
-        std::vector<int> ry = E.prods(p1);
-        std::vector<std::vector<Term>> ST(D);
-        for (int d = 0; d < D; ++d) ST[d] = {{Coef{2.0, 0, d}, one}, {Coef{-1.0, 0, d}, ry[d]}};
-        std::vector<int> t = E.sums(ST, rho0);
-        std::vector<std::pair<int, int>> p2;
-        for (int d = 0; d < D; ++d) p2.push_back({y[d], t[d]});
-        std::vector<int> y2 = E.prods(p2);
-        for (int d = 0; d < D; ++d) {
-          E.release(ry[d]);
-          E.release(t[d]);
-          E.release(y[d]);
-        }
-        y = y2;
-      }
-      r = y;
+      r = inverse_density(E, one, rho, SJ, &jq);
+    }
+    for (size_t q = 0; q < which.size(); ++q) {
+      E.release(j[which[q]]);
+      jeq[which[q]] = jq[q];
     }
     // 4b. u = j_eq (.) r, Pi_ab = j_eq,a (.) u_b
     std::vector<std::pair<int, int>> pu;
@@ -580,8 +706,8 @@ struct SimT : Sim {
     }
     for (int d = 0; d < D; ++d)
       for (int i = 0; i < 19; ++i) dom[d].f[i] = fs[19 * d + i];
-    last_roundings = E.roundings;
-    last_products = E.products;
+    last_roundings = E.roundings + (X ? X->roundings : 0);
+    last_products = E.products + (X ? X->products : 0);
   }
 
   void step(int nsteps) override {
@@ -654,22 +780,24 @@ struct SimT : Sim {
   }
 
   void to_dense(int d, int what, double* out) override {
-    T* buf = nullptr;
-    T* work = nullptr;
-    double* mom = nullptr;
-    double* res = nullptr;
+    std::vector<void*> tmp;
+    auto tdalloc = [&](size_t b) {
+      void* q = E.dalloc(b);
+      tmp.push_back(q);
+      return q;
+    };
     size_t bytes = sizeof(T) * N3 * 19;
-    HIP_OK(hipMalloc(&buf, bytes));
-    HIP_OK(hipMalloc(&work, bytes));
+    T* buf = (T*)tdalloc(bytes);
+    T* work = (T*)tdalloc(bytes);
     std::vector<int> objs(dom[d].f, dom[d].f + 19);
     E.to_dense(objs, buf, work);
     long nout = (what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3);
-    HIP_OK(hipMalloc(&res, 8 * nout));
+    double* res = (double*)tdalloc(8 * nout);
     if (what == MPS_LBM_POPS) {
       hipLaunchKernelGGL((k_scale_permute<T, double>), dim3(dense_chunks(19 * N3)), dim3(256), 0,
                          st, (const T*)buf, res, n, 19, 0);
     } else {
-      HIP_OK(hipMalloc(&mom, 8 * nout));
+      double* mom = (double*)tdalloc(8 * nout);
       hipLaunchKernelGGL(k_moments_dense<T>, dim3(dense_chunks(N3)), dim3(256), 0, st,
                          (const T*)buf, mom, N3, what, (const int*)cvec_dev);
       hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(nout)), dim3(256), 0,
@@ -677,10 +805,49 @@ struct SimT : Sim {
     }
     HIP_OK(hipMemcpyAsync(out, res, 8 * nout, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
-    (void)hipFree(buf);
-    (void)hipFree(work);
-    (void)hipFree(res);
-    if (mom) (void)hipFree(mom);
+    for (void* q : tmp) E.free_alloc(q);
+  }
+
+  // Numerical health after a synchronisation: a non-finite value seen in
+  // the state is sticky (every later data read and step reports it); new
+  // Jacobi sweep-limit hits are reported once.
+  int seen_fail = 0;
+  bool nonfinite_seen = false;
+  int numeric_status() override {
+    int ist[2] = {0, 0}, isx[2] = {0, 0};
+    HIP_OK(hipMemcpyAsync(ist, E.istats, 8, hipMemcpyDeviceToHost, st));
+    if (X) HIP_OK(hipMemcpyAsync(isx, X->istats, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    ist[0] += isx[0];
+    ist[1] += isx[1];
+    if (ist[1] > 0) nonfinite_seen = true;
+    if (nonfinite_seen) return fail(MPS_LBM_ENUMERIC, "a non-finite value appeared in the state");
+    if (ist[0] > seen_fail) {
+      const int k = ist[0] - seen_fail;
+      seen_fail = ist[0];
+      return fail(MPS_LBM_ENUMERIC, std::to_string(k) +
+                                        " singular value decompositions hit the sweep limit");
+    }
+    return MPS_LBM_OK;
+  }
+  bool fatal_seen() const override { return nonfinite_seen; }
+  void raise_flags(int nonfinite, int sweep_limit) override {
+    hipLaunchKernelGGL(k_add_flags, dim3(1), dim3(64), 0, st, E.istats, sweep_limit, nonfinite);
+    HIP_OK(hipGetLastError());
+  }
+
+  void rank_model(float* w, int load) override {
+    if (!E.mlp_on) throw Error(MPS_LBM_EUNSUPPORTED, "the learned rank predictor is off");
+    const size_t b = sizeof(float) * MLP_NPARAM;
+    if (load) {
+      if (gexec) throw Error(MPS_LBM_EUNSUPPORTED, "loading weights after graph capture");
+      HIP_OK(hipMemcpyAsync(E.mlp.p, w, b, hipMemcpyHostToDevice, st));
+      HIP_OK(hipStreamSynchronize(st));
+      E.mlp_trained = true;
+    } else {
+      HIP_OK(hipMemcpyAsync(w, E.mlp.p, b, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+    }
   }
 
   int get_mps(int d, int which, double* out, size_t out_len, int* bonds) override {
@@ -813,6 +980,25 @@ struct mps_lbm {
   std::unique_ptr<Sim> sim;
 };
 
+// process-wide allocator, read when a handle is created
+static Allocator g_alloc;
+
+// Runs an entry point body; no C++ exception leaves it.
+template <typename F>
+static int guarded(F&& body) {
+  try {
+    return body();
+  } catch (const Error& e) {
+    return fail(e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(MPS_LBM_ENOMEM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(MPS_LBM_EHIP, e.what());
+  } catch (...) {
+    return fail(MPS_LBM_EHIP, "unknown exception");
+  }
+}
+
 extern "C" {
 
 void mps_lbm_default_config(mps_lbm_config* c) {
@@ -832,6 +1018,16 @@ void mps_lbm_default_config(mps_lbm_config* c) {
   c->seed = 2512;
   c->rank_predictor = 0;
   c->rank_oversample = 16;
+}
+
+int mps_lbm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_)(void*, void*, void*),
+                          void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr))
+    return fail(MPS_LBM_EINVAL, "alloc and free must both be given or both be NULL");
+  g_alloc.alloc = alloc;
+  g_alloc.free_ = free_;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return MPS_LBM_OK;
 }
 
 static int validate(const mps_lbm_config* c) {
@@ -872,7 +1068,7 @@ static int validate(const mps_lbm_config* c) {
 static int create(const mps_lbm_config* cfgs, int count, const double* const* rho,
                   const double* const* u, const double* const* f, const uint8_t* const* solid,
                   void* hip_stream, mps_lbm_t** out) {
-  try {
+  return guarded([&]() -> int {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
       (void)hipGetLastError();
@@ -881,14 +1077,14 @@ static int create(const mps_lbm_config* cfgs, int count, const double* const* rh
     std::unique_ptr<mps_lbm> h(new mps_lbm());
     hipStream_t st = (hipStream_t)hip_stream;
     if (cfgs[0].precision == MPS_LBM_FP64) {
-      auto* s = new SimT<double>(cfgs, count, st);
+      auto* s = new SimT<double>(cfgs, count, st, g_alloc);
       h->sim.reset(s);
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
                        solid ? solid[d] : nullptr);
       s->finish_init();
     } else {
-      auto* s = new SimT<float>(cfgs, count, st);
+      auto* s = new SimT<float>(cfgs, count, st, g_alloc);
       h->sim.reset(s);
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
@@ -898,11 +1094,7 @@ static int create(const mps_lbm_config* cfgs, int count, const double* const* rh
     *out = h.release();
     g_last_error.clear();
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const double* u,
@@ -932,24 +1124,20 @@ int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* cons
     if (a.n != b.n || a.chi_max != b.chi_max || a.precision != b.precision ||
         a.tol != b.tol || a.sweeps != b.sweeps || a.inv_rho_mode != b.inv_rho_mode ||
         a.inv_rho_iters != b.inv_rho_iters || a.rank_predictor != b.rank_predictor ||
-        a.rank_oversample != b.rank_oversample)
+        a.rank_oversample != b.rank_oversample || a.chi_mask_max != b.chi_mask_max)
       return fail(MPS_LBM_EINVAL,
-                  "batched domains must share n, chi_max, precision, tol, sweeps and the "
-                  "inverse-density mode");
+                  "batched domains must share n, chi_max, chi_mask_max, precision, tol, sweeps "
+                  "and the inverse-density mode");
   }
   return create(cfgs, count, rho, u, nullptr, solid, hip_stream, out);
 }
 
 int mps_lbm_capture_step(mps_lbm_t* h) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
-  try {
+  return guarded([&]() -> int {
     h->sim->capture();
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_domains(const mps_lbm_t* h) {
@@ -960,14 +1148,12 @@ int mps_lbm_domains(const mps_lbm_t* h) {
 int mps_lbm_step(mps_lbm_t* h, int nsteps) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (nsteps < 0) return fail(MPS_LBM_EINVAL, "nsteps < 0");
-  try {
+  if (h->sim->fatal_seen())
+    return fail(MPS_LBM_ENUMERIC, "the state holds non-finite values; no step taken");
+  return guarded([&]() -> int {
     h->sim->step(nsteps);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, size_t out_len) {
@@ -978,14 +1164,12 @@ int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, siz
   const long N3 = h->sim->cells();
   size_t need = (size_t)((what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3));
   if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
-  try {
+  return guarded([&]() -> int {
+    const int ns = h->sim->numeric_status();
+    if (ns) return ns;
     h->sim->to_dense(domain, what, out);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len) {
@@ -996,27 +1180,21 @@ int mps_lbm_get_mps(mps_lbm_t* h, int which, double* out, size_t out_len, int* b
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!bonds) return fail(MPS_LBM_EINVAL, "bonds is NULL");
   if (which < 0 || which > MPS_LBM_MPS_MASK) return fail(MPS_LBM_EINVAL, "bad which");
-  try {
+  return guarded([&]() -> int {
+    const int ns = h->sim->numeric_status();
+    if (ns) return ns;
     return h->sim->get_mps(0, which, out, out_len, bonds);
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_observables_domain(mps_lbm_t* h, int domain, mps_lbm_obs* out) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
   if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
-  try {
+  return guarded([&]() -> int {
     h->sim->observables(domain, out);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  } catch (const std::exception& e) {
-    return fail(MPS_LBM_EHIP, e.what());
-  }
+  });
 }
 
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out) {
@@ -1026,58 +1204,77 @@ int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out) {
 int mps_lbm_kernel_timing(mps_lbm_t* h, int kind) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (kind < MPS_LBM_K_NONE || kind > MPS_LBM_K_CHOLESKY) return fail(MPS_LBM_EINVAL, "bad kind");
-  try {
+  return guarded([&]() -> int {
     h->sim->set_timing(kind);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  }
+  });
 }
 
 int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
-  try {
+  return guarded([&]() -> int {
     h->sim->kstats(out);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  }
+  });
 }
 
 int mps_lbm_train_rank_predictor(mps_lbm_t* h, int epochs, double lr, double* loss_out) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (epochs < 1) return fail(MPS_LBM_EINVAL, "epochs < 1");
   if (!(lr > 0.0) || !(lr < 1.0)) return fail(MPS_LBM_EINVAL, "lr outside (0, 1)");
-  try {
+  return guarded([&]() -> int {
     const float l = h->sim->train_predictor(epochs, (float)lr);
     if (loss_out) *loss_out = l;
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  }
+  });
+}
+
+int mps_lbm_load_rank_model(mps_lbm_t* h, const float* weights, size_t n) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!weights) return fail(MPS_LBM_EINVAL, "weights is NULL");
+  if (n != (size_t)MLP_NPARAM) return fail(MPS_LBM_EINVAL, "weights must hold 37505 floats");
+  return guarded([&]() -> int {
+    h->sim->rank_model(const_cast<float*>(weights), 1);
+    return MPS_LBM_OK;
+  });
+}
+
+int mps_lbm_get_rank_model(mps_lbm_t* h, float* weights, size_t n) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!weights) return fail(MPS_LBM_EINVAL, "weights is NULL");
+  if (n < (size_t)MLP_NPARAM) return fail(MPS_LBM_EINVAL, "n below 37505");
+  return guarded([&]() -> int {
+    h->sim->rank_model(weights, 0);
+    return MPS_LBM_OK;
+  });
 }
 
 int mps_lbm_autotune(mps_lbm_t* h, int* classes_tuned) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
-  try {
+  return guarded([&]() -> int {
     const int n = h->sim->autotune();
     if (classes_tuned) *classes_tuned = n;
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  }
+  });
 }
 
 int mps_lbm_rank_predictor_info(mps_lbm_t* h, mps_lbm_predictor_info* out) {
   if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
-  try {
+  return guarded([&]() -> int {
     h->sim->predictor_info(out);
     return MPS_LBM_OK;
-  } catch (const Error& e) {
-    return fail(e.code, e.what());
-  }
+  });
+}
+
+int mps_lbm_debug_raise_flags(mps_lbm_t* h, int nonfinite, int sweep_limit) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (nonfinite < 0 || sweep_limit < 0) return fail(MPS_LBM_EINVAL, "negative count");
+  return guarded([&]() -> int {
+    h->sim->raise_flags(nonfinite, sweep_limit);
+    return MPS_LBM_OK;
+  });
 }
 
 int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, int batch,
@@ -1085,17 +1282,29 @@ int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, in
   if (!params || !x || !t || !loss || !grad) return fail(MPS_LBM_EINVAL, "NULL argument");
   if (batch < 1 || batch > 1024) return fail(MPS_LBM_EINVAL, "batch outside [1, 1024]");
   std::vector<void*> mem;
-  auto alloc = [&mem](size_t b) -> void* {
-    void* p = nullptr;
-    if (hipMalloc(&p, b) != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(MPS_LBM_ENOMEM, "device allocation failed");
+  const Allocator al = g_alloc;
+  auto release = [&]() {
+    for (void* p : mem) {
+      if (al.free_)
+        al.free_(p, nullptr, al.ctx);
+      else
+        (void)hipFree(p);
     }
-    mem.push_back(p);
-    return p;
+    mem.clear();
   };
-  int rc = MPS_LBM_OK;
-  try {
+  const int rc = guarded([&]() -> int {
+    auto alloc = [&mem, &al](size_t b) -> void* {
+      void* p = nullptr;
+      if (al.alloc) {
+        p = al.alloc(b, nullptr, al.ctx);
+      } else if (hipMalloc(&p, b) != hipSuccess) {
+        (void)hipGetLastError();
+        p = nullptr;
+      }
+      if (!p) throw Error(MPS_LBM_ENOMEM, "device allocation failed");
+      mem.push_back(p);
+      return p;
+    };
     Mlp m;
     m.setup(batch, alloc, 0, nullptr);
     float* dx = (float*)alloc(4L * batch * MLP_IN);
@@ -1107,17 +1316,22 @@ int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, in
     m.backward(dx, dt, batch, nullptr);
     HIP_OK(hipMemcpy(grad, m.g, 4L * MLP_NPARAM, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(loss, m.loss, 4, hipMemcpyDeviceToHost));
-  } catch (const Error& e) {
-    rc = fail(e.code, e.what());
-  }
-  for (void* p : mem) (void)hipFree(p);
+    return MPS_LBM_OK;
+  });
+  (void)hipDeviceSynchronize();
+  release();
   return rc;
 }
 
-void mps_lbm_destroy(mps_lbm_t* h) { delete h; }
+void mps_lbm_destroy(mps_lbm_t* h) {
+  try {
+    delete h;
+  } catch (...) {
+  }
+}
 
 const char* mps_lbm_last_error(void) { return g_last_error.c_str(); }
 
-const char* mps_lbm_version(void) { return "mps-lbm-gfx950 0.1"; }
+const char* mps_lbm_version(void) { return "mps-lbm-gfx950 0.2"; }
 
 }  // extern "C"

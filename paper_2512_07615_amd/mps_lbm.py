@@ -35,7 +35,9 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_domains", "mps_lbm_to_dense_domain",
                    "mps_lbm_observables_domain", "mps_lbm_capture_step",
                    "mps_lbm_train_rank_predictor", "mps_lbm_rank_predictor_info",
-                   "mps_lbm_mlp_gradient", "mps_lbm_autotune"])
+                   "mps_lbm_mlp_gradient", "mps_lbm_autotune", "mps_lbm_set_allocator",
+                   "mps_lbm_load_rank_model", "mps_lbm_get_rank_model",
+                   "mps_lbm_debug_raise_flags"])
 
 
 class Config(C.Structure):
@@ -78,6 +80,11 @@ class KStats(C.Structure):
 
 
 _lib = None
+
+# device allocator callbacks: alloc(bytes, stream, ctx) -> ptr, free(ptr, stream, ctx)
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+_callbacks = []  # registered callbacks stay referenced while the library may call them
 
 
 def load(path: str = LIB_PATH):
@@ -133,6 +140,14 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_mlp_gradient.restype = C.c_int
     lib.mps_lbm_autotune.argtypes = [P, C.POINTER(C.c_int)]
     lib.mps_lbm_autotune.restype = C.c_int
+    lib.mps_lbm_set_allocator.argtypes = [ALLOC_FN, FREE_FN, P]
+    lib.mps_lbm_set_allocator.restype = C.c_int
+    lib.mps_lbm_load_rank_model.argtypes = [P, FP, C.c_size_t]
+    lib.mps_lbm_load_rank_model.restype = C.c_int
+    lib.mps_lbm_get_rank_model.argtypes = [P, FP, C.c_size_t]
+    lib.mps_lbm_get_rank_model.restype = C.c_int
+    lib.mps_lbm_debug_raise_flags.argtypes = [P, C.c_int, C.c_int]
+    lib.mps_lbm_debug_raise_flags.restype = C.c_int
     _lib = lib
     return lib
 
@@ -206,6 +221,51 @@ def mps_lbm_mlp_gradient(params, x, t):
                                        t.ctypes.data_as(fp), int(len(t)), C.byref(loss),
                                        grad.ctypes.data_as(fp)))
     return float(loss.value), grad
+
+
+def mps_lbm_set_allocator(alloc=None, free=None):
+    """Register device allocator callbacks (Python callables or ctypes
+    function pointers); both None restore hipMalloc / hipFree."""
+    lib = load()
+    if alloc is None and free is None:
+        _check(lib.mps_lbm_set_allocator(ALLOC_FN(), FREE_FN(), None))
+        return
+    a = alloc if isinstance(alloc, ALLOC_FN) else (ALLOC_FN(alloc) if alloc else ALLOC_FN())
+    f = free if isinstance(free, FREE_FN) else (FREE_FN(free) if free else FREE_FN())
+    _callbacks.extend([a, f])
+    _check(lib.mps_lbm_set_allocator(a, f, None))
+
+
+def use_torch_allocator():
+    """Take the library's device memory from PyTorch's caching allocator,
+    on the stream each handle runs on."""
+    import torch
+
+    def alloc(size, stream, ctx):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(size), stream=int(stream or 0))
+        except Exception:
+            return None
+
+    def free(ptr, stream, ctx):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    mps_lbm_set_allocator(alloc, free)
+
+
+def mps_lbm_load_rank_model(h, weights):
+    w = np.ascontiguousarray(weights, dtype=np.float32)
+    _check(load().mps_lbm_load_rank_model(h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+
+
+def mps_lbm_get_rank_model(h) -> np.ndarray:
+    w = np.empty(MLP_NPARAM, dtype=np.float32)
+    _check(load().mps_lbm_get_rank_model(h, w.ctypes.data_as(C.POINTER(C.c_float)), w.size))
+    return w
+
+
+def mps_lbm_debug_raise_flags(h, nonfinite: int = 0, sweep_limit: int = 0):
+    _check(load().mps_lbm_debug_raise_flags(h, int(nonfinite), int(sweep_limit)))
 
 
 def mps_lbm_step(h, nsteps: int = 1):
@@ -379,6 +439,15 @@ class BatchSimulation:
     def kernel_stats(self):
         return mps_lbm_kernel_stats(self.h)
 
+    def load_rank_model(self, weights):
+        mps_lbm_load_rank_model(self.h, weights)
+
+    def get_rank_model(self) -> np.ndarray:
+        return mps_lbm_get_rank_model(self.h)
+
+    def debug_raise_flags(self, nonfinite=0, sweep_limit=0):
+        mps_lbm_debug_raise_flags(self.h, nonfinite, sweep_limit)
+
     def close(self):
         if self.h:
             mps_lbm_destroy(self.h)
@@ -429,6 +498,15 @@ class Simulation:
 
     def predictor_info(self) -> PredictorInfo:
         return mps_lbm_rank_predictor_info(self.h)
+
+    def load_rank_model(self, weights):
+        mps_lbm_load_rank_model(self.h, weights)
+
+    def get_rank_model(self) -> np.ndarray:
+        return mps_lbm_get_rank_model(self.h)
+
+    def debug_raise_flags(self, nonfinite=0, sweep_limit=0):
+        mps_lbm_debug_raise_flags(self.h, nonfinite, sweep_limit)
 
     def close(self):
         if self.h:

@@ -154,3 +154,55 @@ def test_predictor_entry_points_validate_without_gpu():
     assert so.mps_lbm_train_rank_predictor(None, 1, 1e-3, None) == -1
     info = L.PredictorInfo()
     assert so.mps_lbm_rank_predictor_info(None, C.byref(info)) == -1
+
+
+def test_allocator_registration_validates_and_resets():
+    """mps_lbm_set_allocator takes both callbacks or neither."""
+    L = lib()
+    so = L.load()
+    a = L.ALLOC_FN(lambda size, stream, ctx: None)
+    f = L.FREE_FN(lambda ptr, stream, ctx: None)
+    assert so.mps_lbm_set_allocator(a, L.FREE_FN(), None) == L.EINVAL
+    assert so.mps_lbm_set_allocator(L.ALLOC_FN(), f, None) == L.EINVAL
+    assert so.mps_lbm_set_allocator(a, f, None) == L.OK
+    assert so.mps_lbm_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == L.OK
+
+
+def test_model_and_debug_entry_points_validate_without_gpu():
+    L = lib()
+    so = L.load()
+    fp = C.POINTER(C.c_float)
+    w = (C.c_float * L.MLP_NPARAM)()
+    assert so.mps_lbm_load_rank_model(None, C.cast(w, fp), L.MLP_NPARAM) == L.EINVAL
+    assert so.mps_lbm_get_rank_model(None, C.cast(w, fp), L.MLP_NPARAM) == L.EINVAL
+    assert so.mps_lbm_debug_raise_flags(None, 1, 0) == L.EINVAL
+
+
+def test_every_entry_point_that_reaches_the_engine_is_guarded():
+    """No C++ exception may cross the C ABI: every exported function whose
+    body calls into a handle's simulation (or creates one) runs that call
+    inside guarded(), which catches Error, std::bad_alloc, std::exception
+    and anything else."""
+    src = open(os.path.join(ROOT, "paper_2512_07615_amd", "csrc", "mps_lbm.hip")).read()
+    body_of = {}
+    start = src.index('extern "C" {')
+    for m in re.finditer(r"\n(?:int|void|const char\*) (mps_lbm_[a-z_]+)\([^)]*\)[^{;]*\{", src[start:]):
+        i = start + m.end()
+        depth = 1
+        j = i
+        while depth:
+            depth += {"{": 1, "}": -1}.get(src[j], 0)
+            j += 1
+        body_of[m.group(1)] = src[i:j]
+    assert len(body_of) >= 24
+    no_engine = ("->domains()", "->cells()", "->fatal_seen()")
+    for name, body in body_of.items():
+        calls = re.findall(r"->sim->[a-z_]+\(\)?", body)
+        calls = [c for c in calls if not any(c.startswith("->sim" + x[:-2]) for x in no_engine)]
+        if calls or "new " in body or "hipMemcpy" in body:
+            assert "guarded(" in body or name == "mps_lbm_destroy", name
+    # create(), which the two init entry points call, runs inside guarded()
+    c0 = src.index("static int create(")
+    assert "return guarded(" in src[c0:src.index("int mps_lbm_init_from_field", c0)]
+    assert "catch (...)" in src[src.index("static int guarded"):start]
+    assert "catch (...)" in body_of["mps_lbm_destroy"]

@@ -162,8 +162,11 @@ def test_porous32_chi16_truncated_vs_mps_oracle():
         out[p] = rel(s.dense(L.POPS), ref)
         s.close()
     print("porous32 chi16 rel vs MPS oracle", out, flush=True)
-    assert out["fp64"] < 1e-7
-    assert out["fp32"] < 1e-3
+    # FP64: the rounding level of the algebra through two truncated steps
+    # (3e-13 measured); FP32: storage rounding (6e-8) through some 300
+    # roundings per step (2.7e-6 measured), bound about 7x that
+    assert out["fp64"] < 1e-10
+    assert out["fp32"] < 2e-5
 
 
 def test_batched_domains_match_single_domains():
@@ -483,29 +486,80 @@ def test_rest_state_rank_one_fixed_point():
     assert o.max_bond == 1
 
 
-def test_vascular128_full_size_velocity_vs_fp64():
+def _read_velocity_fixture(path):
+    cells, u = [], []
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        v = line.split()
+        cells.append([int(t) for t in v[:3]])
+        u.append([float(t) for t in v[3:]])
+    return np.array(cells), np.array(u).T
+
+
+def test_vascular128_full_size_velocity_vs_oracle():
     """The 128^3, chi = 128 branching-tube configuration (velocity inlet,
-    pressure outlet) at full size: FP32 and BF16X3 against the library's
-    FP64 policy (itself pinned to the oracle at smaller sizes), two steps
-    from a seeded flow; velocity within the 1e-4 relative L2 asked of the
-    reduced-precision step, on fluid cells."""
-    from oracle.dense_lbm import moments
+    pressure outlet, obstacle mask at machine precision) at full size and in
+    the launch configuration the benchmark times: FP32 and BF16X3 policies,
+    two steps from a seeded flow, against the CPU FP64 MPS oracle on the
+    same schedule.  The oracle's velocity u = j / rho after the two steps is
+    stored at 6000 seeded fluid cells (tests/golden, written by the
+    committed script beside it, which calls only the oracle); the relative
+    L2 difference over those cells must stay below the 1e-4 asked of the
+    reduced-precision step."""
+    import os
     L = lib()
+    path = os.path.join(os.path.dirname(__file__), "golden",
+                        "vascular128_chi128_velocity_samples.txt")
+    from oracle import mps as M
+    cells, u_ref = _read_velocity_fixture(path)
     case = _case_with_flow(WL.case_vascular(n=7, chi=128, tau=0.55, tol=1e-8))
-    fluid = ~np.asarray(case.solid, dtype=bool)
-    u = {}
-    for prec in ("fp64", "fp32", "bf16x3"):
+    x, y, z = cells.T
+    assert not case.solid[x, y, z].any()
+    mask_bond = max(M.bonds(M.from_dense(case.solid.astype(np.float64), 7, 1 << 30, 1e-12)))
+    for prec in ("fp32", "bf16x3"):
+        print("vascular128 chi128", prec, "two steps", flush=True)
         s = L.Simulation(case, precision=prec)
         s.step(2)
-        f = s.dense(L.POPS).astype(np.float64)
+        vel = s.dense(L.VEL)
+        o = s.observables()
         s.close()
-        r, j = moments(f)
-        u[prec] = j[:, fluid] / r[fluid]
-        del f
-    for prec in ("fp32", "bf16x3"):
-        du = _vel_rel_l2(u[prec], u["fp64"])
-        print("vascular128", prec, "velocity rel L2 vs fp64", du, flush=True)
+        du = _vel_rel_l2(vel[:, x, y, z], u_ref)
+        print("vascular128", prec, "velocity rel L2 vs MPS oracle (6000 fluid cells)", du,
+              "mask bond", o.mask_bond, "mask err", o.mask_trunc_err, flush=True)
+        # the mask is decided in FP64 (the oracle's ranks) and stored in FP32
+        assert o.mask_bond == mask_bond and o.mask_trunc_err < 1e-6
         assert du < 1e-4
+
+
+def test_porous64_chi128_wide_factorisations_vs_mps_oracle():
+    """64^3 porous medium at chi = 128: the sums carry bonds of 256, so the
+    truncations run the factorisation paths wider than 128 columns (global
+    memory Cholesky and Jacobi).  Two FP32 steps against the CPU FP64 MPS
+    oracle on the same schedule."""
+    from oracle.dense_lbm import moments
+    L = lib()
+    case = _case_with_flow(WL.case_porous(n=6, chi=128, tau=0.6, tol=1e-8, precision="fp32"))
+    print("porous64 chi128 fp32: oracle two steps", flush=True)
+    m = MPSLBM(case)
+    for _ in range(2):
+        m.step()
+    fr = m.dense_populations()
+    s = L.Simulation(case)
+    s.step(2)
+    fg = s.dense(L.POPS)
+    o = s.observables()
+    s.close()
+    rr, jr = moments(fr)
+    rg, jg = moments(fg)
+    fluid = ~np.asarray(case.solid, dtype=bool)
+    du = _vel_rel_l2(jg[:, fluid] / rg[fluid], jr[:, fluid] / rr[fluid])
+    df = float(np.sqrt(((fg - fr) ** 2).sum() / (fr ** 2).sum()))
+    print("porous64 chi128: max bond", o.max_bond, "velocity rel L2", du, "populations", df,
+          flush=True)
+    assert o.max_bond > 64
+    assert du < 1e-4
+    assert df < 1e-5
 
 
 @pytest.mark.parametrize("prec,bound", [("fp64", 1e-10), ("fp32", 5e-5)])
@@ -553,8 +607,12 @@ def test_newton_inverse_density_truncated_vs_mps_oracle():
         out[p] = rel(s.dense(L.POPS), ref)
         s.close()
     print("channel16 chi8 newton rel vs MPS oracle", out, flush=True)
-    assert out["fp64"] < 1e-7
-    assert out["fp32"] < 1e-3
+    # FP64: 8.8e-13 measured.  FP32: 1.5e-4 measured: at chi 8 every
+    # truncation of this flow is held at chi with closely spaced singular
+    # values at the cut, where an FP32-level perturbation turns the kept
+    # subspace; bound about 3x the measured value
+    assert out["fp64"] < 1e-10
+    assert out["fp32"] < 5e-4
 
 
 def test_batched_domains_beyond_one_launch():
