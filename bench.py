@@ -1,10 +1,14 @@
 """Benchmark of the MPS lattice Boltzmann step on one MI355X.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload porous64]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload vascular128]
 
 A step is one full D3Q19 MPS-LBM step (moments, 1/rho, variational
 products, BGK sums, streaming, open faces, bounce-back, all roundings) on
-the synthetic workload, inputs resident in HBM.  Prints one JSON line.
+the synthetic workload, inputs resident in HBM.  The default workload is
+the 128^3 branching-tube configuration at chi = 128 with BF16X3
+contractions (the largest configuration of the target that one GPU runs
+whole); the 64^3 porous medium at chi = 64 (FP32) is timed as an extra
+field.  Prints one JSON line.
 """
 import argparse
 import re
@@ -112,13 +116,12 @@ def batched_rate(case, count, stream, steps):
 
 def stored_traffic(kind, workload):
     """HBM bytes per launch of the roofline kernel from the committed
-    rocprofv3 counter summary, when it covers this kernel and workload and
-    the kernel's sources still hash to what was measured; else None."""
+    rocprofv3 counter summary (profiles/<workload>_<kind>_hbm_traffic.md),
+    when it exists and the kernel's sources still hash to what was
+    measured; else None."""
     import hashlib
-    if kind != "jacobi" or workload != "porous64":
-        return None
     root = os.path.dirname(os.path.abspath(__file__))
-    path = os.path.join(root, "profiles", "porous64_fp32_jacobi_hbm_traffic.md")
+    path = os.path.join(root, "profiles", f"{workload}_{kind}_hbm_traffic.md")
     try:
         text = open(path).read()
     except OSError:
@@ -156,10 +159,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="porous64")
+    ap.add_argument("--workload", default="vascular128")
+    ap.add_argument("--extra-workload", default="porous64",
+                    help="also time this workload's step (empty = skip)")
+    ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--fp64-steps", type=int, default=3)
-    ap.add_argument("--batch", type=int, default=8,
+    ap.add_argument("--fp64-steps", type=int, default=1)
+    ap.add_argument("--graph-steps", type=int, default=3,
+                    help="steps timed as HIP graph replays")
+    ap.add_argument("--batch", type=int, default=0,
                     help="also time this many domains of the workload advanced together "
                          "(0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -242,7 +250,8 @@ def main():
                    "roundings_per_step": obs.roundings, "products_per_step": obs.products,
                    "jacobi_sweeps_mean": obs.jacobi_sweeps, "jacobi_sweep_limit_hits": obs.svd_failures,
                    "lds_bytes": obs.lds_bytes, "autotuned_classes": tuned,
-                   "compression": obs.compression},
+                   "compression": obs.compression, "face_trunc_err": obs.face_trunc_err,
+                   "inverse_density": "taylor2, FP64 island"},
     }
     out["roofline"] = roofline(args.roofline_kernel, ks, case.precision)
     out["roofline"]["traffic"] = stored_traffic(args.roofline_kernel, args.workload)
@@ -266,12 +275,13 @@ def main():
         sim.capture()
         torch.cuda.synchronize()
         e0.record(stream)
-        for _ in range(args.steps):
+        for _ in range(args.graph_steps):
             sim.step(1)
         e1.record(stream)
         torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1) / args.steps
+        gms = e0.elapsed_time(e1) / args.graph_steps
         out["config"]["hip_graph_steps_per_s"] = 1000.0 / gms
+        progress(f"graph replay: {gms:.1f} ms/step")
     sim.close()
     if args.predictor_steps > 0 and case.precision != "fp64":
         # the same workload with the rank predictor on: two steps to seed the
@@ -309,8 +319,28 @@ def main():
         out["config"]["fp64_steps_per_s"] = 1000.0 / ms64
         out["config"]["speedup_vs_fp64_path"] = ms64 / ms
         sim64.close()
+        progress(f"FP64 policy: {ms64:.1f} ms/step")
     if args.batch > 0:
         out["config"]["batched"] = batched_rate(case, args.batch, stream, args.batch_steps)
+    if args.extra_workload and args.extra_workload != args.workload and args.extra_steps > 0:
+        xc = make_case(args.extra_workload)
+        xs = L.Simulation(xc, hip_stream=stream.cuda_stream)
+        xs.step(1)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.extra_steps):
+            xs.step(1)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        xms = e0.elapsed_time(e1) / args.extra_steps
+        xo = xs.observables()
+        xs.close()
+        out["config"]["extra"] = {"workload": xc.name, "precision": xc.precision,
+                                  "chi": xc.chi, "steps_per_s": 1000.0 / xms,
+                                  "ms_per_step": xms,
+                                  "equiv_mlups": xc.N ** 3 * 1000.0 / xms / 1e6,
+                                  "mask_bond": xo.mask_bond, "max_bond": xo.max_bond}
+        progress(f"{xc.name}: {xms:.1f} ms/step")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, obs.roundings, obs.products)
     print(json.dumps(out), flush=True)

@@ -159,6 +159,14 @@ struct SimT : Sim {
       X->al = al;
       X->sweeps = c.sweeps;
       X->setup(n, c.chi_max, c.tol, s, 8 + 8 * D, std::min(MAXB, D));
+      // its truncations use the factorisations of the reduced-precision
+      // policies (rank-revealing Cholesky-QR2 and Gram eigendecomposition,
+      // all in FP64) on FP64 data: directions below about 3e-8 of the
+      // largest singular value count as zero (FP64 Gram resolution) and the
+      // eigenvectors are orthonormal to 1e-12
+      X->fast = true;
+      X->eps_rank = 1e-15;
+      X->eig_orth_tol = 1e-12;
       one64 = X->acquire();
       X->set_ones(one64);
     }
