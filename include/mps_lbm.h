@@ -362,6 +362,21 @@ int mps_lbm_rank_predictor_info(mps_lbm_t* h, mps_lbm_predictor_info* out);
 int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, int batch,
                          float* loss, float* grad);
 
+/*
+ * mps_lbm_mlp_gradient without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, serving loops,
+ * harnesses that forbid hipMalloc).  params (37505 floats), x (batch x 33),
+ * t (batch), loss (1 float) and grad (37505 floats) are DEVICE pointers
+ * owned by the caller; the activations live in a fixed device array of the
+ * library (4.7 MB per GPU, held until the process ends), so batch is at
+ * most 1024.  Enqueued on hip_stream (NULL = default stream) without
+ * synchronising; the results are those of mps_lbm_mlp_gradient.  Calls
+ * that overlap on one GPU (any streams) share that array and race.
+ * Errors: EINVAL (NULL pointer, batch outside [1, 1024]), EHIP.
+ */
+int mps_lbm_mlp_gradient_device(const float* params, const float* x, const float* t, int batch,
+                                float* loss, float* grad, void* hip_stream);
+
 /* Release every device buffer of the handle; NULL is ignored. */
 void mps_lbm_destroy(mps_lbm_t* h);
 

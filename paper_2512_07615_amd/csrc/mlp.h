@@ -105,7 +105,8 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int n, floa
 }
 
 // He-uniform weights (bound sqrt(6 / fan_in)) from a counter-based
-// generator, zero biases
+// generator (the SplitMix64 finaliser of Steele, Lea and Flood, 2014, applied
+// to seed + golden-ratio increment times the element index), zero biases
 __global__ void k_mlp_init(float* p, uint64_t seed) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= MLP_NPARAM) return;

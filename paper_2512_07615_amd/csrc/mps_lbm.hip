@@ -26,6 +26,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -130,7 +131,7 @@ struct SimT : Sim {
   int one = -1;
   double* rho0 = nullptr;   // device [D]
   double* nfl = nullptr;    // device [D]: fluid cell counts
-  double* scratch = nullptr;
+  double* sbuf = nullptr;   // device sums of a step (rho_0 numerators, norms)
   int* cvec_dev = nullptr;
   double* w_dev = nullptr;
   long long steps = 0;
@@ -174,7 +175,7 @@ struct SimT : Sim {
     if (c.rank_predictor == 2) E.enable_mlp(c.seed);
     rho0 = (double*)E.dalloc(8 * (D + 8));
     nfl = (double*)E.dalloc(8 * (D + 8));
-    scratch = (double*)E.dalloc(8 * (19 * D + 64));
+    sbuf = (double*)E.dalloc(8 * (19 * D + 64));
     int cvec[57];
     double w[19];
     for (int i = 0; i < 19; ++i) {
@@ -238,11 +239,11 @@ struct SimT : Sim {
     T* back = (T*)E.dalloc(sizeof(T) * N3);
     T* work = (T*)E.dalloc(sizeof(T) * N3);
     E.to_dense({obj}, back, work);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, scratch, 0.0, 2L);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, sbuf, 0.0, 2L);
     hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st,
-                       (const T*)back, Wref, N3, scratch);
+                       (const T*)back, Wref, N3, sbuf);
     double hnorm[2];
-    HIP_OK(hipMemcpyAsync(hnorm, scratch, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(hnorm, sbuf, 16, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     E.free_alloc(work);
     E.free_alloc(back);
@@ -294,10 +295,10 @@ struct SimT : Sim {
       const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
       dense_to_mps(dd, W, 1, {dm.mask}, chi_mask, cfg.tol_mask, cap);
       dm.mask_err = decomposition_error(dm.mask, Wkeep);
-      E.inner_ones({dm.mask}, scratch + 2);
+      E.inner_ones({dm.mask}, sbuf + 2);
       double ones_m = 0.0;
       MpsDev<T> md;
-      HIP_OK(hipMemcpyAsync(&ones_m, scratch + 2, 8, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipMemcpyAsync(&ones_m, sbuf + 2, 8, hipMemcpyDeviceToHost, st));
       HIP_OK(hipMemcpyAsync(&md, E.D(dm.mask), sizeof(md), hipMemcpyDeviceToHost, st));
       HIP_OK(hipStreamSynchronize(st));
       dm.n_fluid = (double)N3 - ones_m;
@@ -464,9 +465,9 @@ struct SimT : Sim {
       for (int a = 0; a < 3; ++a) j[3 * d + a] = mom[4 * d + 1 + a];
     }
     // 2. rho_0 = <1, rho> / N_fluid
-    E.inner_ones(rho, scratch);
+    E.inner_ones(rho, sbuf);
     hipLaunchKernelGGL(k_div_vec, dim3(1), dim3(std::max(64, ((D + 63) / 64) * 64)), 0, st,
-                       (const double*)scratch, (const double*)nfl, rho0, D);
+                       (const double*)sbuf, (const double*)nfl, rho0, D);
     // 4a. j_eq = j + tau g rho on the forced axes; these sums need only the
     // moments, so they are rounded together with the first sums of step 3
     std::vector<int> jeq(3 * D);
@@ -926,11 +927,11 @@ struct SimT : Sim {
     memset(o, 0, sizeof(*o));
     const Domain& dm = dom[d];
     std::vector<int> objs(dm.f, dm.f + 19);
-    E.inner_ones(objs, scratch);
+    E.inner_ones(objs, sbuf);
     double s[19];
     double stat[2] = {0, 0};
     int ist[4] = {0, 0, 0, 0};
-    HIP_OK(hipMemcpyAsync(s, scratch, 8 * 19, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s, sbuf, 8 * 19, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(stat, E.stats, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(ist, E.istats, 16, hipMemcpyDeviceToHost, st));
     double r0 = 0.0;
@@ -990,6 +991,35 @@ struct mps_lbm {
 
 // process-wide allocator, read when a handle is created
 static Allocator g_alloc;
+
+// Scratch of mps_lbm_mlp_gradient_device: the activations and deltas of the
+// predictor network for one batch of at most MLP_SCRATCH_BATCH samples
+// (nine B x 128 layers and two B-vectors, 4.7 MB).  Every GPU the library
+// runs on holds its own copy until the process ends; its address on a
+// device comes from hipGetSymbolAddress, once per device.
+constexpr int MLP_SCRATCH_BATCH = 1024;
+constexpr long MLP_SCRATCH_FLOATS = (9L * MLP_H + 2) * MLP_SCRATCH_BATCH;
+static __device__ __align__(256) float scratch[MLP_SCRATCH_FLOATS];
+
+constexpr int SCRATCH_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[SCRATCH_DEVICES];
+
+// device address of `scratch` on the current device
+static float* scratch_on_current_device() {
+  int dev = 0;
+  HIP_OK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= SCRATCH_DEVICES)
+    throw Error(MPS_LBM_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIP_OK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw Error(MPS_LBM_EHIP, "no device address for the scratch array");
+    g_scratch_ptr[dev] = (float*)p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 // Runs an entry point body; no C++ exception leaves it.
 template <typename F>
@@ -1329,6 +1359,37 @@ int mps_lbm_mlp_gradient(const float* params, const float* x, const float* t, in
   (void)hipDeviceSynchronize();
   release();
   return rc;
+}
+
+int mps_lbm_mlp_gradient_device(const float* params, const float* x, const float* t, int batch,
+                                float* loss, float* grad, void* hip_stream) {
+  if (!params || !x || !t || !loss || !grad) return fail(MPS_LBM_EINVAL, "NULL argument");
+  if (batch < 1 || batch > MLP_SCRATCH_BATCH)
+    return fail(MPS_LBM_EINVAL, "batch outside [1, 1024] (the scratch holds 1024 samples)");
+  return guarded([&]() -> int {
+    float* s = scratch_on_current_device();
+    hipStream_t st = (hipStream_t)hip_stream;
+    // the network's buffers: the caller's parameters, gradient and loss, the
+    // activations and deltas packed into the scratch
+    Mlp m;
+    m.p = const_cast<float*>(params);
+    m.g = grad;
+    m.loss = loss;
+    m.bmax = batch;
+    float** acts[] = {&m.z1, &m.a1, &m.z2, &m.a2, &m.z3, &m.a3, &m.d3, &m.d2, &m.d1};
+    long off = 0;
+    for (float** a : acts) {
+      *a = s + off;
+      off += (long)batch * MLP_H;
+    }
+    m.y = s + off;
+    off += batch;
+    m.dy = s + off;
+    m.forward(x, batch, st);
+    m.backward(x, t, batch, st);
+    HIP_OK(hipGetLastError());
+    return MPS_LBM_OK;
+  });
 }
 
 void mps_lbm_destroy(mps_lbm_t* h) {

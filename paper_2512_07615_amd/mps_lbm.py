@@ -37,7 +37,7 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_train_rank_predictor", "mps_lbm_rank_predictor_info",
                    "mps_lbm_mlp_gradient", "mps_lbm_autotune", "mps_lbm_set_allocator",
                    "mps_lbm_load_rank_model", "mps_lbm_get_rank_model",
-                   "mps_lbm_debug_raise_flags"])
+                   "mps_lbm_debug_raise_flags", "mps_lbm_mlp_gradient_device"])
 
 
 class Config(C.Structure):
@@ -148,6 +148,8 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_get_rank_model.restype = C.c_int
     lib.mps_lbm_debug_raise_flags.argtypes = [P, C.c_int, C.c_int]
     lib.mps_lbm_debug_raise_flags.restype = C.c_int
+    lib.mps_lbm_mlp_gradient_device.argtypes = [P, P, P, C.c_int, P, P, P]
+    lib.mps_lbm_mlp_gradient_device.restype = C.c_int
     _lib = lib
     return lib
 
@@ -266,6 +268,15 @@ def mps_lbm_get_rank_model(h) -> np.ndarray:
 
 def mps_lbm_debug_raise_flags(h, nonfinite: int = 0, sweep_limit: int = 0):
     _check(load().mps_lbm_debug_raise_flags(h, int(nonfinite), int(sweep_limit)))
+
+
+def mps_lbm_mlp_gradient_device(params_ptr, x_ptr, t_ptr, batch, loss_ptr, grad_ptr,
+                                hip_stream=None):
+    """The network's loss and gradient on device buffers (pointers as ints),
+    enqueued on hip_stream without allocating."""
+    _check(load().mps_lbm_mlp_gradient_device(
+        C.c_void_p(params_ptr), C.c_void_p(x_ptr), C.c_void_p(t_ptr), int(batch),
+        C.c_void_p(loss_ptr), C.c_void_p(grad_ptr), C.c_void_p(hip_stream or 0)))
 
 
 def mps_lbm_step(h, nsteps: int = 1):
