@@ -1148,6 +1148,104 @@ __device__ __forceinline__ int jacobi_sweeps(double* A, int m, double* W, int nw
   return sweep;
 }
 
+// Round-robin sweeps for columns of 129 to 256 rows in global memory (no W):
+// one group of 16 lanes per pair, every row of both columns of the pair held
+// in registers (16 per lane), so that a pair's rows are loaded once and
+// stored once per round and the sixteen loads of a lane are in flight
+// together; the pairs of a round are taken in passes of (threads / 16).
+// Same pairing, test and rotation as jacobi_sweeps.
+__device__ __forceinline__ int jacobi_sweeps_r16(double* A, int m, int n, int max_sweeps,
+                                                 double tol, double small2, double& work,
+                                                 int* flag) {
+  constexpr int G = 16, RPL = 16;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nwaves = blockDim.x >> 6;
+  const int P = (n % 2) ? n + 1 : n;
+  const int gpw = 64 / G, gl = lane % G, grp = lane / G;
+  const int par = nwaves * gpw;
+  int sweep = 0;
+  for (; sweep < max_sweeps && n > 1; ++sweep) {
+    if (tid == 0) *flag = 0;
+    __syncthreads();
+    int rot = 0;
+    for (int t = 0; t < P - 1; ++t) {
+      for (int base = 0; base < P / 2; base += par) {
+        const int k = base + wv * gpw + grp;
+        int i1 = n, i2 = n;
+        if (k < P / 2) {
+          if (k == 0) {
+            i1 = t; i2 = P - 1;
+          } else {
+            i1 = t + k;
+            if (i1 >= P - 1) i1 -= P - 1;
+            i2 = t - k;
+            if (i2 < 0) i2 += P - 1;
+          }
+        }
+        const bool act = i1 < n && i2 < n;
+        const int a = act ? (i1 < i2 ? i1 : i2) : 0, b = act ? (i1 < i2 ? i2 : i1) : 0;
+        double* ca = A + (long)a * m;
+        double* cb = A + (long)b * m;
+        double xr[RPL], yr[RPL];
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = gl + q * G;
+          xr[q] = (act && r < m) ? ca[r] : 0.0;
+          yr[q] = (act && r < m) ? cb[r] : 0.0;
+        }
+        double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          al += xr[q] * xr[q];
+          be += yr[q] * yr[q];
+          ga += xr[q] * yr[q];
+        }
+        al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
+        if (!act) continue;
+        if (gl == 0) work += 6.0 * m;
+        if (ga == 0.0 || !pair_coupled(ga, al, be, tol)) continue;
+        if (al <= small2 || be <= small2) continue;
+        const double g2 = 2.0 * ga;
+        double ig = __builtin_amdgcn_rcp(g2);
+        ig = ig * (2.0 - g2 * ig);
+        ig = ig * (2.0 - g2 * ig);
+        const double zeta = (be - al) * ig;
+        const double q1 = 1.0 + zeta * zeta;
+        double rq = __builtin_amdgcn_rsq(q1);
+        rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+        rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+        const double den = fabs(zeta) + q1 * rq;
+        double id = __builtin_amdgcn_rcp(den);
+        id = id * (2.0 - den * id);
+        id = id * (2.0 - den * id);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+        const double q2 = 1.0 + tt * tt;
+        double cs = __builtin_amdgcn_rsq(q2);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        const double sn = cs * tt;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const int r = gl + q * G;
+          if (r < m) {
+            ca[r] = cs * xr[q] - sn * yr[q];
+            cb[r] = sn * xr[q] + cs * yr[q];
+          }
+        }
+        if (gl == 0) work += 6.0 * m;
+        rot = 1;
+      }
+      __syncthreads();
+    }
+    if (rot) *flag = 1;
+    __syncthreads();
+    const int any = *flag;
+    __syncthreads();
+    if (!any) break;
+  }
+  return sweep;
+}
+
 // Ring variant of the sweeps (no W; every row of a column held in registers,
 // m <= 8 G with G the lanes per pair for P = the power of two >= n columns,
 // n > 1, and at least P / 2 groups of G lanes in the workgroup).  The ordering halves the column set recursively: in a phase on a
@@ -1406,7 +1504,8 @@ __global__ void k_eig_prep(F f, EigProb* ep, int nprob) {
 // a pointer of known address space so that LDS is reached by ds_* ops).
 __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sweeps, double* flops,
                                          int* flag, int* nonfin, int* rsel, int* perm,
-                                         double* nrm, double* red, double orth_tol) {
+                                         double* nrm, double* red, double orth_tol,
+                                         bool in_global) {
   const int s = p.s, c = p.c, tid = threadIdx.x;
   const long sc = (long)s * c;
   double fro2 = 0.0;
@@ -1422,10 +1521,12 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
   const int Gr = jacobi_group_lanes(P2, blockDim.x >> 6);
   const bool ring = c > 1 && 5 * c > 4 * P2 && s <= 8 * Gr &&
                     P2 / 2 <= (int)(blockDim.x >> 6) * (64 / Gr);  // one pair per group
-  const int sw = ring ? jacobi_sweeps_ring(A, s, c, max_sweeps, tol, eps * eps * fro2, work, flag,
-                                           nrm)
-                      : jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2, work,
-                                      flag);
+  const bool r16 = !ring && in_global && s > 128 && s <= 256 && blockDim.x >= 1024;
+  const int sw = ring  ? jacobi_sweeps_ring(A, s, c, max_sweeps, tol, eps * eps * fro2, work,
+                                            flag, nrm)
+                 : r16 ? jacobi_sweeps_r16(A, s, c, max_sweeps, tol, eps * eps * fro2, work, flag)
+                       : jacobi_sweeps(A, s, nullptr, 0, c, max_sweeps, tol, eps * eps * fro2,
+                                       work, flag);
   if (tid == 0 && p.fail) {
     if (sw >= max_sweeps) atomicAdd(p.fail, 1);
     atomicAdd(p.fail + 2, sw);
@@ -1489,9 +1590,9 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
   if (sc <= lds_elems) {
     block_copy(sh, p.A, sc);
     __syncthreads();
-    eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol);
+    eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol, false);
   } else {
-    eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol);
+    eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol, true);
   }
 }
 
