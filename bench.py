@@ -248,7 +248,10 @@ def main():
                    "equiv_mlups": N3 * sps / 1e6, "max_bond": obs.max_bond,
                    "mask_bond": obs.mask_bond, "mask_trunc_err": obs.mask_trunc_err,
                    "roundings_per_step": obs.roundings, "products_per_step": obs.products,
-                   "jacobi_sweeps_mean": obs.jacobi_sweeps, "jacobi_sweep_limit_hits": obs.svd_failures,
+                   "jacobi_sweeps_mean": obs.jacobi_sweeps,
+                   "jacobi_sweeps_wide": obs.jacobi_sweeps_wide,
+                   "jacobi_cols_wide": obs.jacobi_cols_wide,
+                   "jacobi_sweep_limit_hits": obs.svd_failures,
                    "lds_bytes": obs.lds_bytes, "autotuned_classes": tuned,
                    "compression": obs.compression, "face_trunc_err": obs.face_trunc_err,
                    "inverse_density": "taylor2, FP64 island"},

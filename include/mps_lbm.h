@@ -132,6 +132,8 @@ typedef struct {
   int lds_bytes;           /* LDS per workgroup the factorisation kernels use */
   long long rs_attempted;  /* truncations tried on a randomized sketch (total) */
   long long rs_accepted;   /* of those, accepted without fallback (total)    */
+  double jacobi_sweeps_wide; /* the same for factors wider than 128 columns */
+  double jacobi_cols_wide; /* their mean column count (numerical rank)      */
   double face_trunc_err;   /* largest ||m_B - m_B~|| / ||m_B|| of the open-face
                               masks (fluid cells of the face plane), which are
                               decomposed at tol_mask with rank cap chi_max */

@@ -1014,22 +1014,21 @@ class Engine {
     typedef double D;
     launch_gemm<T, D, D, D>(FRsMOm<T>{L, k, rw}, cnt, scap, scap, 1, st);
     launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Y, rw.T, rw.ell, sq}, cnt, scap, scap, 1, st);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rw.ell, 1, rw.T, sq,
-                       rw.B, rw.R, rw.rank1, eps_rank, lds_elems, cnt, 1, (double*)nullptr, 0.0);
+    launch_chol(scap, cnt, (const int*)rw.ell, 1, rw.T, sq, rw.B, rw.R, rw.rank1, eps_rank,
+                lds_elems, cnt, 1, (double*)nullptr, 0.0);
     launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Y, rw.B, rw.Q, rw.ell, rw.rank1, sq}, cnt, scap,
                             scap, 1, st);
     launch_gemm<D, D, D, D>(FRsGram<T>{L, k, rw.Q, rw.T, rw.rank1, sq}, cnt, scap, scap, 1, st);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rw.rank1, 1, rw.T,
-                       sq, rw.B2, rw.R2, rw.rank2, 1e-28, lds_elems, cnt, 1, (double*)nullptr,
-                       cq_skip);
+    launch_chol(scap, cnt, (const int*)rw.rank1, 1, rw.T, sq, rw.B2, rw.R2, rw.rank2, 1e-28,
+                lds_elems, cnt, 1, (double*)nullptr, cq_skip);
     launch_gemm<D, D, D, D>(FRsXB<T>{L, k, rw.Q, rw.B2, rw.Q2, rw.rank1, rw.rank2, sq}, cnt, scap,
                             scap, 1, st);
     launch_gemm<D, D, D, D>(FRsGQ<T>{L, k, cw.G, rw}, cnt, scap, scap, 1, st);
     launch_gemm<D, D, D, D>(FRsQtW<T>{L, k, rw}, cnt, scap, scap, 1, st);
     hipLaunchKernelGGL(k_rs_budget, dim3(cnt), dim3(256), 0, st, (const double*)rdelta, rw, cnt);
     hipLaunchKernelGGL(k_rs_dims_T, dim3(1), dim3(64), 0, st, rw, rs_dims, cnt);
-    hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), lds, st, (const int*)rs_dims, 1, rw.T, sq,
-                       rw.B, rw.R, rw.rankT, eps_rank, lds_elems, cnt, 0, (double*)nullptr, 0.0);
+    launch_chol(scap, cnt, (const int*)rs_dims, 1, rw.T, sq, rw.B, rw.R, rw.rankT, eps_rank,
+                lds_elems, cnt, 0, (double*)nullptr, 0.0);
     hipLaunchKernelGGL(k_eig_prep<FnRsEig>, dim3(1), dim3(64), 0, st,
                        FnRsEig{rw, chi_cap, istats, featk, 0.001f * (float)step_count}, rs_ep,
                        cnt);
@@ -1042,6 +1041,19 @@ class Engine {
     hipLaunchKernelGGL(k_rs_dims_full<T>, dim3(1), dim3(64), 0, st, L, k, rw, cq_n, cnt);
     HIP_OK(hipGetLastError());
   }
+  // Pivoted Cholesky of nprob Grams of order at most ncap: the 1024-thread
+  // kernel up to CPB_MAXN, the 512-thread one (blocked with the Gram in
+  // global memory up to CHOL_WIDE_MAXN) above.
+  template <typename... A>
+  void launch_chol(int ncap, int nprob, A... args) {
+    if (ncap > CPB_MAXN)
+      hipLaunchKernelGGL(k_chol_piv_wide, dim3(nprob), dim3(CHOL_WIDE_THREADS),
+                         (size_t)lds_elems * 8, st, args...);
+    else
+      hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), (size_t)lds_elems * 8, st,
+                         args...);
+  }
+
   // timing of one kernel class: HIP events around each of its launches
   int tkind = 0;
   std::vector<hipEvent_t> evs;
@@ -1151,6 +1163,9 @@ class Engine {
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_elems * 8) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_chol_piv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_chol_piv_wide,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_elems * 8) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_jacobi_eig,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -1500,17 +1515,15 @@ class Engine {
                                       ksplit(nprob, scap, scap, 1, mcap));
     tbegin(4);
     // ranks land interleaved: pass 1 in rank[2 i], pass 2 in rank[2 i + 1]
-    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)cq_n, 1, w.G,
-                       w.sq, w.B1, w.R1, w.rank, eps_rank, lds_elems, nprob, 1, kf(4), 0.0, 2,
-                       cq_n + MAXB);
+    launch_chol(scap, nprob, (const int*)cq_n, 1, w.G, w.sq, w.B1, w.R1, w.rank, eps_rank,
+                lds_elems, nprob, 1, kf(4), 0.0, 2, cq_n + MAXB);
     tend(4);
     launch_gemm<T, double, double, double>(FCqQ1<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqGram2<T>{qp, w}, nprob, scap, scap, 1, st,
                                                 nullptr, ksplit(nprob, scap, scap, 1, mcap));
     tbegin(4);
-    hipLaunchKernelGGL(k_chol_piv, dim3(nprob), dim3(CHOL_THREADS), lds, st, (const int*)(cq_n + MAXB), 1,
-                       w.G, w.sq, w.B2, w.R2, w.rank + 1, 1e-28, lds_elems, nprob, 1,
-                       kf(4), cq_skip, 2);
+    launch_chol(scap, nprob, (const int*)(cq_n + MAXB), 1, w.G, w.sq, w.B2, w.R2, w.rank + 1,
+                1e-28, lds_elems, nprob, 1, kf(4), cq_skip, 2);
     tend(4);
     launch_gemm<double, double, T, double>(FCqQ<T>{qp, w}, nprob, mcap, scap, 1, st);
     launch_gemm<double, double, double, double>(FCqR<T>{qp, w}, nprob, scap, scap, 1, st);
@@ -1565,9 +1578,8 @@ class Engine {
       else
         hipLaunchKernelGGL(k_rank_dims<T>, dim3(1), dim3(64), 0, st, L, k, cq_n, cnt);
       tbegin(4);
-      hipLaunchKernelGGL(k_chol_piv, dim3(cnt), dim3(CHOL_THREADS), (size_t)lds_elems * 8, st,
-                         (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
-                         lds_elems, cnt, 0, kf(4));
+      launch_chol(scap, cnt, (const int*)cq_n, 1, cw.G, cw.sq, cw.B1, cw.R1, cw.rank, eps_rank,
+                  lds_elems, cnt, 0, kf(4));
       tend(4);
       hipLaunchKernelGGL(k_eig_prep<FnEigTrunc<T>>, dim3(1), dim3(64), 0, st,
                          FnEigTrunc<T>{L, k, cw.R1, cw.sq, (const int*)cw.rank, svdUS, svdWk,

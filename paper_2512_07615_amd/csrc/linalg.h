@@ -604,12 +604,167 @@ __device__ __forceinline__ void chol_blocked(double* G, int n, double thr, int* 
   __syncthreads();
 }
 
+// Blocked pivoted Cholesky for CPB_MAXN < n <= CHOL_WIDE_MAXN with G in
+// global memory (it no longer fits LDS) and the panel of L in LDS (Lp, n
+// rows of stride LPS).  As chol_blocked, with four physical rows per lane of
+// the panel wave (l, l + 64, l + 128, l + 192): the panel is factored in
+// registers, the trailing rank-CPB update runs once per panel on FP64 MFMA
+// over the global matrix, so that the order-n Schur complement is read and
+// written n / CPB times instead of n times.  Needs a workgroup of at most
+// 512 threads (the panel wave holds 64 entries of L per lane).
+constexpr int CHOL_WIDE_MAXN = 256;
+constexpr int CHOL_WIDE_THREADS = 512;
+__device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, int* perm,
+                                                  double* dg, double* Lp, int* rho_s, int* kdone) {
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
+  constexpr double DONE = -1e300;
+  constexpr int RQ = CHOL_WIDE_MAXN / 64;  // rows per lane of the panel wave
+  int* posn = perm + 512;
+  for (int i = tid; i < n; i += blockDim.x) {
+    dg[i] = G[(long)i * n + i];
+    posn[i] = n;
+  }
+  __syncthreads();
+  int rho = n;
+  for (int j0 = 0; j0 < n; j0 += CPB) {
+    const int bw = n - j0 < CPB ? n - j0 : CPB;
+    if (wv == 0) {
+      double d[RQ], L[RQ][CPB];
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int i = lane + 64 * q;
+        d[q] = i < n && posn[i] == n ? dg[i] : DONE;
+#pragma unroll
+        for (int k = 0; k < CPB; ++k) L[q][k] = 0.0;
+      }
+      int kd = 0;
+      bool stop = false;
+#pragma unroll
+      for (int k = 0; k < CPB; ++k) {
+        if (k < bw && !stop) {
+          double cand = d[0];
+#pragma unroll
+          for (int q = 1; q < RQ; ++q) cand = d[q] > cand ? d[q] : cand;
+          const double best = wave_max_f64(cand);
+          // lowest physical row holding the maximum
+          int bi = -1;
+#pragma unroll
+          for (int q = RQ - 1; q >= 0; --q) {
+            const unsigned long long mq = __ballot(d[q] == best);
+            if (mq) bi = 64 * q + __builtin_ctzll(mq);
+          }
+          if (!(best > thr) || !(best > 0.0) || bi < 0) {
+            stop = true;  // the same decision in every lane
+          } else {
+            const int p = bi, pl = p & 63, pq = p >> 6;
+            double lp[CPB];
+#pragma unroll
+            for (int qq = 0; qq < k; ++qq) {
+              double v = L[0][qq];
+#pragma unroll
+              for (int q = 1; q < RQ; ++q)
+                if (pq == q) v = L[q][qq];
+              lp[qq] = readlane_f64(v, pl);
+            }
+            double invr = __builtin_amdgcn_rsq(best);
+            invr = invr * (1.5 - 0.5 * best * invr * invr);
+            invr = invr * (1.5 - 0.5 * best * invr * invr);
+            const double r = best * invr;
+            const double* gp = G + (long)p * n;  // row p (G is kept symmetric)
+            double gv[RQ];
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+              const int i = lane + 64 * q;
+              gv[q] = (d[q] > DONE && i != p) ? gp[i] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < RQ; ++q) {
+              const int i = lane + 64 * q;
+              if (d[q] > DONE && i != p) {
+                double acc = gv[q];
+#pragma unroll
+                for (int qq = 0; qq < k; ++qq) acc -= L[q][qq] * lp[qq];
+                const double l = acc * invr;
+                L[q][k] = l;
+                d[q] -= l * l;
+              }
+              if (i == p) {
+                L[q][k] = r;
+                d[q] = DONE;
+              }
+            }
+            if (lane == 0) {
+              perm[j0 + k] = p;
+              posn[p] = j0 + k;
+            }
+            kd = k + 1;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < RQ; ++q) {
+        const int i = lane + 64 * q;
+        if (i < n) {
+#pragma unroll
+          for (int k = 0; k < CPB; ++k) Lp[i * LPS + k] = L[q][k];
+          dg[i] = d[q];
+        }
+      }
+      if (lane == 0) *kdone = kd;
+    }
+    __syncthreads();
+    const int kd = *kdone;
+    for (int e = tid; e < kd * n; e += blockDim.x) {
+      const int k = e / n, i = e - k * n, j = j0 + k;
+      if (posn[i] >= j) G[(long)perm[j] * n + i] = Lp[i * LPS + k];
+    }
+    if (kd < bw) {
+      rho = j0 + kd;
+      __syncthreads();
+      break;
+    }
+    // trailing update G -= L L^T of the unpivoted rows and columns, one
+    // 16 x 16 tile per wave at a time on FP64 MFMA (layouts as in
+    // chol_blocked); tiles holding no unpivoted row are skipped
+    typedef double dv4 __attribute__((ext_vector_type(4)));
+    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4;
+    for (int t = wv; t < nb * nb; t += nw) {
+      const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
+      const int ar = a0 + l16, bc = b0 + l16;
+      dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int q0 = 0; q0 < CPB; q0 += 4) {
+        const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
+        const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+      }
+      if (bc < n && posn[bc] == n) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int a = a0 + lq + 4 * v;
+          if (a < n && posn[a] == n) G[(long)a * n + bc] -= acc[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  for (int i = tid; i < n; i += blockDim.x) {
+    if (posn[i] < n) continue;
+    int c = 0;
+    for (int i2 = 0; i2 < i; ++i2) c += posn[i2] == n ? 1 : 0;
+    perm[rho + c] = i;
+  }
+  if (tid == 0) *rho_s = rho;
+  __syncthreads();
+}
+
 // Body of k_chol_piv for G in LDS or in global memory.
 __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, double* Bbase,
                                           double* Rbase, int* rank_out, double eps_rank,
                                           int want_b, int* perm, double* red, int* ired,
                                           int* rho_s, double* dmax0, double* dpiv, double* xd,
-                                          double* Lp, int* kdone, int rank_stride) {
+                                          double* Lp, int* kdone, int rank_stride,
+                                          bool wide = false) {
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, nw = blockDim.x >> 6;
   for (int i = tid; i < n; i += blockDim.x) perm[i] = i;
   __syncthreads();
@@ -628,7 +783,10 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
   const double thr = eps_rank * (*dmax0);
   int prev = -1;
   double inv_prev = 0.0;
-  if (Lp) chol_blocked(G, n, thr, perm, xd, Lp, rho_s, kdone);
+  if (Lp && wide)
+    chol_blocked_wide(G, n, thr, perm, xd, Lp, rho_s, kdone);
+  else if (Lp)
+    chol_blocked(G, n, thr, perm, xd, Lp, rho_s, kdone);
   for (int j = 0; j < n && !Lp; ++j) {
     // deferred scaling of the previous pivot row; pivot search on the diagonal
     if (prev >= 0)
@@ -896,14 +1054,19 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
 
 constexpr int CHOL_THREADS = 1024;  // threads of k_chol_piv: 16 waves hide the
                                     // LDS latency of the parallel phases
-__global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
+// Body of the pivoted Cholesky kernels (NT threads): orders up to CPB_MAXN
+// whose Gram fits LDS are factored blockwise in LDS; with NT <= 512, orders
+// up to CHOL_WIDE_MAXN blockwise with the Gram in global memory; others by
+// the unblocked right-looking loop in global memory.
+template <int NT>
+__device__ __forceinline__ void chol_piv_kernel_body(const int* dims, int dim_stride, double* Gbase,
                                                   long sq, double* Bbase, double* Rbase,
                                                   int* rank_out, double eps_rank, int lds_elems,
-                                                  int nprob, int want_b = 1,
-                                                  double* flops = nullptr,
-                                                  double skip_tol = 0.0,
-                                                  int rank_stride = 1,
-                                                  int* dims_next = nullptr) {
+                                                  int nprob, int want_b,
+                                                  double* flops,
+                                                  double skip_tol,
+                                                  int rank_stride,
+                                                  int* dims_next) {
   extern __shared__ double sh[];
   __shared__ int perm[1024];
   __shared__ double red[16];
@@ -961,6 +1124,11 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
     block_copy(sh, Gg, (long)n * n);
     chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone, rank_stride);
+  } else if (NT <= CHOL_WIDE_THREADS && n <= CHOL_WIDE_MAXN &&
+             (long)n * LPS <= lds_elems) {
+    // the panel of L in the (otherwise unused) dynamic LDS
+    chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+              &dmax0, &dpiv, xd, sh, &kdone, rank_stride, true);
   } else {
     chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, nullptr, &kdone, rank_stride);
@@ -975,6 +1143,31 @@ __global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int 
     if (want_b) f += (double)rho * rho * rho / 3.0;
     atomicAdd(flops, f);
   }
+}
+
+__global__ __launch_bounds__(CHOL_THREADS) void k_chol_piv(const int* dims, int dim_stride, double* Gbase,
+                                                  long sq, double* Bbase, double* Rbase,
+                                                  int* rank_out, double eps_rank, int lds_elems,
+                                                  int nprob, int want_b = 1,
+                                                  double* flops = nullptr,
+                                                  double skip_tol = 0.0,
+                                                  int rank_stride = 1,
+                                                  int* dims_next = nullptr) {
+  chol_piv_kernel_body<CHOL_THREADS>(dims, dim_stride, Gbase, sq, Bbase, Rbase, rank_out, eps_rank,
+                                     lds_elems, nprob, want_b, flops, skip_tol, rank_stride,
+                                     dims_next);
+}
+
+// The same for Grams of capacity above CPB_MAXN: 512 threads, so that orders
+// up to CHOL_WIDE_MAXN are factored blockwise with the Gram in global memory.
+__global__ __launch_bounds__(CHOL_WIDE_THREADS) void k_chol_piv_wide(
+    const int* dims, int dim_stride, double* Gbase, long sq, double* Bbase, double* Rbase,
+    int* rank_out, double eps_rank, int lds_elems, int nprob, int want_b = 1,
+    double* flops = nullptr, double skip_tol = 0.0, int rank_stride = 1,
+    int* dims_next = nullptr) {
+  chol_piv_kernel_body<CHOL_WIDE_THREADS>(dims, dim_stride, Gbase, sq, Bbase, Rbase, rank_out,
+                                          eps_rank, lds_elems, nprob, want_b, flops, skip_tol,
+                                          rank_stride, dims_next);
 }
 
 // ---------------------------------------------------------------------------
@@ -1531,6 +1724,11 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
     if (sw >= max_sweeps) atomicAdd(p.fail, 1);
     atomicAdd(p.fail + 2, sw);
     atomicAdd(p.fail + 3, 1);
+    if (c > 128) {  // factors wider than the LDS-resident paths
+      atomicAdd(p.fail + 4, sw);
+      atomicAdd(p.fail + 5, 1);
+      atomicAdd(p.fail + 6, c);
+    }
   }
   if (flops && work > 0.0) atomicAdd(flops, work);
   jacobi_sorted_norms(A, s, c, nrm, perm, nonfin);
@@ -1618,7 +1816,9 @@ struct SvdProb {
   double* Wk;      // cols x r
   double* sv;      // singular values (sorted) out, length cols (may be null)
   double* disc;    // discarded weight out (may be null)
-  int* fail;       // [0] sweep-limit hits, [1] non-finite values, [2] sweeps, [3] problems
+  int* fail;       // [0] sweep-limit hits, [1] non-finite values, [2] sweeps, [3] problems,
+                   // [4] sweeps, [5] problems and [6] columns of factors wider than
+                   // 128 columns
 };
 
 template <typename F>

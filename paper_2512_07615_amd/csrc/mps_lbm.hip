@@ -930,10 +930,10 @@ struct SimT : Sim {
     E.inner_ones(objs, sbuf);
     double s[19];
     double stat[2] = {0, 0};
-    int ist[4] = {0, 0, 0, 0};
+    int ist[7] = {0, 0, 0, 0, 0, 0, 0};
     HIP_OK(hipMemcpyAsync(s, sbuf, 8 * 19, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(stat, E.stats, 8, hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(ist, E.istats, 16, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(ist, E.istats, 28, hipMemcpyDeviceToHost, st));
     double r0 = 0.0;
     HIP_OK(hipMemcpyAsync(&r0, rho0 + d, 8, hipMemcpyDeviceToHost, st));
     std::vector<MpsDev<T>> descs(19);
@@ -973,6 +973,8 @@ struct SimT : Sim {
     o->svd_failures = ist[0];
     o->nonfinite = ist[1];
     o->jacobi_sweeps = ist[3] > 0 ? (double)ist[2] / ist[3] : 0.0;
+    o->jacobi_sweeps_wide = ist[5] > 0 ? (double)ist[4] / ist[5] : 0.0;
+    o->jacobi_cols_wide = ist[5] > 0 ? (double)ist[6] / ist[5] : 0.0;
     o->lds_bytes = E.lds_elems * 8;
     if (E.rs_pred) {
       int t[2] = {0, 0};

@@ -61,6 +61,7 @@ class Obs(C.Structure):
         ("products", C.c_longlong), ("svd_failures", C.c_int), ("nonfinite", C.c_int),
         ("jacobi_sweeps", C.c_double), ("lds_bytes", C.c_int),
         ("rs_attempted", C.c_longlong), ("rs_accepted", C.c_longlong),
+        ("jacobi_sweeps_wide", C.c_double), ("jacobi_cols_wide", C.c_double),
         ("face_trunc_err", C.c_double),
     ]
 
