@@ -1360,7 +1360,7 @@ __device__ __forceinline__ int jacobi_sweeps_r16(double* A, int m, int n, int ma
   for (; sweep < max_sweeps && n > 1; ++sweep) {
     if (tid == 0) *flag = 0;
     __syncthreads();
-    int rot = 0;
+    float mx = 0.0f;  // largest relative coupling this thread rotated away
     for (int t = 0; t < P - 1; ++t) {
       for (int base = 0; base < P / 2; base += par) {
         const int k = base + wv * gpw + grp;
@@ -1398,6 +1398,7 @@ __device__ __forceinline__ int jacobi_sweeps_r16(double* A, int m, int n, int ma
         if (gl == 0) work += 6.0 * m;
         if (ga == 0.0 || !pair_coupled(ga, al, be, tol)) continue;
         if (al <= small2 || be <= small2) continue;
+        mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
         const double g2 = 2.0 * ga;
         double ig = __builtin_amdgcn_rcp(g2);
         ig = ig * (2.0 - g2 * ig);
@@ -1426,15 +1427,21 @@ __device__ __forceinline__ int jacobi_sweeps_r16(double* A, int m, int n, int ma
           }
         }
         if (gl == 0) work += 6.0 * m;
-        rot = 1;
       }
       __syncthreads();
     }
-    if (rot) *flag = 1;
+    // the sweep's largest coupling (positive floats order as their bits)
+    if (mx > 0.0f) atomicMax(flag, __float_as_int(mx));
     __syncthreads();
     const int any = *flag;
     __syncthreads();
     if (!any) break;
+    // quadratic convergence: once every rotated pair of a sweep was coupled
+    // by less than sqrt(tol) / 10, the next sweep would rotate nothing
+    if (__int_as_float(any) < (float)(0.1 * sqrt(tol))) {
+      ++sweep;
+      break;
+    }
   }
   return sweep;
 }
