@@ -1041,6 +1041,28 @@ class Engine {
     hipLaunchKernelGGL(k_rs_dims_full<T>, dim3(1), dim3(64), 0, st, L, k, rw, cq_n, cnt);
     HIP_OK(hipGetLastError());
   }
+  // Truncation eigendecompositions of the cnt problems in ep whose factors
+  // may have 129-256 rows: rows split over JS_PARTS workgroups per problem
+  // (k_jacobi_eig_split), at most JS_LAUNCH problems per launch so that the
+  // workgroups of a launch fit the GPU together.
+  static constexpr int JS_LAUNCH = 32;
+  JsSync js{};
+  void eig_split(int cnt) {
+    if (!js.part) {
+      js.part = (double*)dalloc(8 * JS_PART_SLOT * JS_LAUNCH);
+      js.nrm = (double*)dalloc(8 * JS_NRM_SLOT * JS_LAUNCH);
+      js.count = (unsigned*)dalloc(4 * JS_LAUNCH);
+    }
+    for (int off = 0; off < cnt; off += JS_LAUNCH) {
+      const int c = std::min(JS_LAUNCH, cnt - off);
+      hipLaunchKernelGGL(k_js_reset, dim3(1), dim3(64), 0, st, js.count, c);
+      const int blocks = ((c + 7) / 8) * 8 * JS_PARTS;
+      hipLaunchKernelGGL(k_jacobi_eig_split, dim3(blocks), dim3(1024), (size_t)lds_elems * 8, st,
+                         (const EigProb*)(ep + off), c, js, lds_elems, 40, kf(1), eig_orth_tol);
+    }
+    HIP_OK(hipGetLastError());
+  }
+
   // Pivoted Cholesky of nprob Grams of order at most ncap: the 1024-thread
   // kernel up to CPB_MAXN, the 512-thread one (blocked with the Gram in
   // global memory up to CHOL_WIDE_MAXN) above.
@@ -1168,6 +1190,9 @@ class Engine {
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_elems * 8) != hipSuccess ||
         hipFuncSetAttribute((const void*)k_jacobi_eig,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lds_elems * 8) != hipSuccess ||
+        hipFuncSetAttribute((const void*)k_jacobi_eig_split,
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             lds_elems * 8) != hipSuccess) {
       (void)hipGetLastError();
@@ -1589,9 +1614,12 @@ class Engine {
                                        0.001f * (float)step_count},
                          ep, cnt);
       tbegin(1);
-      hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)),
-                         (size_t)lds_elems * 8, st,
-                         (const EigProb*)ep, lds_elems, 40, kf(1), eig_orth_tol);
+      if (scap > 128 && std::min(scap, full_bound(n, k)) > 128)
+        eig_split(cnt);
+      else
+        hipLaunchKernelGGL(k_jacobi_eig, dim3(cnt), dim3(eig_threads(scap, k)),
+                           (size_t)lds_elems * 8, st, (const EigProb*)ep, lds_elems, 40, kf(1),
+                           eig_orth_tol);
       tend(1);
       launch_gemm<double, T, T, double>(FUtM<T>{L, ep, qtmp, qslot, k}, cnt, scap, ccap, 1, st);
       launch_gemm<T, double, T, double>(FCoreUS2<T>{L, ep, ctmp, maxcore, k}, cnt,

@@ -1802,6 +1802,303 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
 }
 
 // ---------------------------------------------------------------------------
+// The truncation eigendecomposition of a factor of 129 to 256 rows with its
+// rows split over JS_PARTS workgroups, so that every part (64 rows of all c
+// columns) fits LDS.  The round-robin sweeps run in lockstep: in a round
+// each workgroup sums (al, be, ga) of every pair over its rows, publishes
+// them, and after an inter-workgroup barrier adds the JS_PARTS partial sums
+// in a fixed order, so that every part takes the same rotation decisions and
+// angles and rotates its own rows.  Column norms are summed the same way
+// before the shared rank rule; each part writes its rows of U S and
+// Sigma^-1 U^T.  The barrier is a counter per problem (zeroed before the
+// launch) with release / acquire at device scope and a bounded wait: a wait
+// that runs out (workgroups of a problem not resident together) counts as a
+// non-finite result and stops further waiting, so every workgroup exits.
+constexpr int JS_PARTS = 4;
+constexpr int JS_ROWS = 64;          // rows per part: factors of at most 256 rows
+constexpr int JS_PAIRS = 128;        // pairs per round: at most 256 columns
+constexpr long JS_SPIN = 1L << 21;   // polls of a barrier wait before it gives up
+constexpr long JS_PART_SLOT = 2L * JS_PARTS * JS_PAIRS * 3;  // per problem
+constexpr long JS_NRM_SLOT = (long)JS_PARTS * 256 + JS_PARTS;  // per problem
+
+struct JsSync {
+  double* part;       // [problem][2 rounds][JS_PARTS][JS_PAIRS][3]
+  double* nrm;        // [problem]: [JS_PARTS][256] squared column norms of a
+                      // part, then [JS_PARTS] squared Frobenius norms
+  unsigned* count;    // [problem] barrier arrivals
+};
+
+__global__ void k_js_reset(unsigned* count, int n) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) count[i] = 0u;
+}
+
+__device__ inline void js_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double js_load(double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// every thread calls it; returns false once a wait of this workgroup ran out.
+// Every wave first waits until its own stores (device-scope atomic stores,
+// written through to the device's coherence point) have completed, so that
+// the arrival counted by thread 0 follows all stores of the workgroup.
+__device__ inline bool js_barrier(unsigned* cnt, unsigned target, int* broken) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(cnt, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (!*broken) {
+      long it = 0;
+      while (__hip_atomic_load(cnt, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++it >= JS_SPIN) {
+          *broken = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+    }
+  }
+  __syncthreads();
+  return !*broken;
+}
+
+__global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, int nprob,
+                                                           JsSync js, int lds_elems,
+                                                           int max_sweeps, double* flops,
+                                                           double orth_tol) {
+  extern __shared__ double sh[];
+  __shared__ int flag, nonfin, rsel, broken;
+  __shared__ int perm[1024];
+  __shared__ double nrm[1024];
+  __shared__ double red[16];
+  // the parts of a problem are 8 workgroups apart (the same XCD when
+  // workgroups are dealt round-robin to the 8 XCDs)
+  const int b = blockIdx.x;
+  const int pr = (b / (8 * JS_PARTS)) * 8 + (b % 8);
+  const int part = (b % (8 * JS_PARTS)) / 8;
+  if (pr >= nprob) return;
+  EigProb p = ep[pr];
+  if (!p.valid) return;
+  const int s = p.s, c = p.c, tid = threadIdx.x;
+  if (s <= 128 || s > JS_PARTS * JS_ROWS || c > 2 * JS_PAIRS || (long)s * c <= lds_elems ||
+      (long)JS_ROWS * c > lds_elems) {
+    // the single-workgroup kernel's cases: the first part does it
+    if (part != 0) return;
+    if (c > 1024) {
+      if (tid == 0 && p.fail) atomicAdd(p.fail + 1, 1);
+      return;
+    }
+    const long sc = (long)s * c;
+    if (sc <= lds_elems) {
+      block_copy(sh, p.A, sc);
+      __syncthreads();
+      eig_body(p, sh, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol, false);
+    } else {
+      eig_body(p, p.A, max_sweeps, flops, &flag, &nonfin, &rsel, perm, nrm, red, orth_tol, true);
+    }
+    return;
+  }
+  double* const jp = js.part + pr * JS_PART_SLOT;
+  double* const jn = js.nrm + pr * JS_NRM_SLOT;
+  unsigned* const cnt = js.count + pr;
+  unsigned gen = 0;
+  if (tid == 0) broken = 0;
+  // this part's rows [r0, r0 + nr) of every column, column-major, ld JS_ROWS
+  const int r0 = part * JS_ROWS;
+  const int nr = s - r0 < 0 ? 0 : (s - r0 < JS_ROWS ? s - r0 : JS_ROWS);
+  for (long e = tid; e < (long)JS_ROWS * c; e += blockDim.x) {
+    const int col = (int)(e / JS_ROWS), rr = (int)(e % JS_ROWS);
+    sh[e] = rr < nr ? p.A[(long)col * s + r0 + rr] : 0.0;
+  }
+  // Frobenius norm of the whole factor (for the zero-column test)
+  double fro2 = 0.0;
+  for (long e = tid; e < (long)JS_ROWS * c; e += blockDim.x) fro2 += sh[e] * sh[e];
+  fro2 = block_sum(fro2, red);
+  double* const jf = jn + (long)JS_PARTS * 256;
+  if (tid == 0) js_store(jf + part, fro2);
+  js_barrier(cnt, JS_PARTS * (++gen), &broken);
+  fro2 = 0.0;
+  for (int q = 0; q < JS_PARTS; ++q) fro2 += js_load(jf + q);
+  const double eps = 2.220446049250313e-16;
+  const double small2 = eps * eps * fro2;
+  const double tol = orth_tol > 0.0 ? orth_tol : eps * sqrt((double)s);
+  constexpr int G = 8, RPL = JS_ROWS / G;
+  const int lane = tid & 63, wv = tid >> 6, gl = lane % G;
+  const int k = wv * (64 / G) + lane / G;  // this group's pair of a round
+  const int P = (c % 2) ? c + 1 : c;
+  double work = 0.0;
+  int sweep = 0;
+  for (; sweep < max_sweeps && c > 1; ++sweep) {
+    if (tid == 0) flag = 0;
+    __syncthreads();
+    float mx = 0.0f;
+    for (int t = 0; t < P - 1; ++t) {
+      int i1 = c, i2 = c;
+      if (k < P / 2) {
+        if (k == 0) {
+          i1 = t; i2 = P - 1;
+        } else {
+          i1 = t + k;
+          if (i1 >= P - 1) i1 -= P - 1;
+          i2 = t - k;
+          if (i2 < 0) i2 += P - 1;
+        }
+      }
+      const bool act = i1 < c && i2 < c;
+      const int a = act ? (i1 < i2 ? i1 : i2) : 0, bb = act ? (i1 < i2 ? i2 : i1) : 0;
+      double* ca = sh + (long)a * JS_ROWS;
+      double* cb = sh + (long)bb * JS_ROWS;
+      double xr[RPL], yr[RPL];
+      double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        xr[q] = act ? ca[gl + q * G] : 0.0;
+        yr[q] = act ? cb[gl + q * G] : 0.0;
+        al += xr[q] * xr[q];
+        be += yr[q] * yr[q];
+        ga += xr[q] * yr[q];
+      }
+      al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
+      double* slot = jp + (long)(gen & 1) * JS_PARTS * JS_PAIRS * 3;
+      if (act && gl == 0) {
+        double* o = slot + ((long)part * JS_PAIRS + k) * 3;
+        js_store(o, al);
+        js_store(o + 1, be);
+        js_store(o + 2, ga);
+      }
+      js_barrier(cnt, JS_PARTS * (++gen), &broken);
+      if (act) {
+        al = 0.0; be = 0.0; ga = 0.0;
+        for (int q = 0; q < JS_PARTS; ++q) {
+          double* o = slot + ((long)q * JS_PAIRS + k) * 3;
+          al += js_load(o);
+          be += js_load(o + 1);
+          ga += js_load(o + 2);
+        }
+        if (gl == 0) work += 6.0 * s;
+        const bool rotate = ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 &&
+                            be > small2;
+        if (rotate) {
+          mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
+          const double g2 = 2.0 * ga;
+          double ig = __builtin_amdgcn_rcp(g2);
+          ig = ig * (2.0 - g2 * ig);
+          ig = ig * (2.0 - g2 * ig);
+          const double zeta = (be - al) * ig;
+          const double q1 = 1.0 + zeta * zeta;
+          double rq = __builtin_amdgcn_rsq(q1);
+          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+          const double den = fabs(zeta) + q1 * rq;
+          double id = __builtin_amdgcn_rcp(den);
+          id = id * (2.0 - den * id);
+          id = id * (2.0 - den * id);
+          const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+          const double q2 = 1.0 + tt * tt;
+          double cs = __builtin_amdgcn_rsq(q2);
+          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+          const double sn = cs * tt;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) {
+            ca[gl + q * G] = cs * xr[q] - sn * yr[q];
+            cb[gl + q * G] = sn * xr[q] + cs * yr[q];
+          }
+          if (gl == 0) work += 6.0 * s;
+        }
+      }
+      __syncthreads();
+    }
+    // the same pairs and sums in every part: the same decisions
+    if (mx > 0.0f) atomicMax(&flag, __float_as_int(mx));
+    __syncthreads();
+    const int any = flag;
+    __syncthreads();
+    if (!any) break;
+    if (__int_as_float(any) < (float)(0.1 * sqrt(tol))) {
+      ++sweep;
+      break;
+    }
+  }
+  // column norms: this part's squared sums, then all parts in a fixed order
+  for (int col = wv; col < c; col += (int)(blockDim.x >> 6)) {
+    const double v = sh[(long)col * JS_ROWS + lane];
+    const double acc = wave_sum(v * v);
+    if (lane == 0) js_store(jn + (long)part * 256 + col, acc);
+  }
+  const bool ok = js_barrier(cnt, JS_PARTS * (++gen), &broken);
+  if (tid == 0) nonfin = ok ? 0 : 1;
+  __syncthreads();
+  for (int col = tid; col < c; col += blockDim.x) {
+    double acc = 0.0;
+    for (int q = 0; q < JS_PARTS; ++q) acc += js_load(jn + (long)q * 256 + col);
+    double v = sqrt(acc);
+    if (!(v <= 1.7976931348623157e308)) {
+      nonfin = 1;
+      v = -1.0;
+    }
+    nrm[col] = v;
+  }
+  __syncthreads();
+  for (int col = tid; col < c; col += blockDim.x) {
+    int pos = 0;
+    const double v = nrm[col];
+    for (int o = 0; o < c; ++o) {
+      const double u = nrm[o];
+      if (u > v || (u == v && o < col)) ++pos;
+    }
+    perm[pos] = col;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const double smax = nrm[perm[0]] > 0 ? nrm[perm[0]] : 0.0;
+    int nz = 0;
+    for (int j = 0; j < c; ++j)
+      if (nrm[perm[j]] * nrm[perm[j]] > 1e-14 * smax * smax) ++nz;
+    double tail = 0.0;
+    const int r = rank_rule_dev(nrm, perm, c, true, p.delta2, p.chi, nz, &tail);
+    rsel = r;
+    if (part == 0) {
+      if (p.rank_out) *p.rank_out = r;
+      if (p.disc) *p.disc = tail;
+      if (p.fail) {
+        if (sweep >= max_sweeps) atomicAdd(p.fail, 1);
+        if (nonfin) atomicAdd(p.fail + 1, 1);
+        atomicAdd(p.fail + 2, sweep);
+        atomicAdd(p.fail + 3, 1);
+        atomicAdd(p.fail + 4, sweep);
+        atomicAdd(p.fail + 5, 1);
+        atomicAdd(p.fail + 6, c);
+      }
+    } else if (nonfin && p.fail) {
+      atomicAdd(p.fail + 1, 1);
+    }
+  }
+  if (part == 0 && flops && tid % G == 0 && work > 0.0) atomicAdd(flops, work);
+  __syncthreads();
+  const int r = rsel;
+  if (part == 0 && p.feat && tid <= 32) {
+    float f = p.stepf;
+    if (tid < 32) {
+      const int q = r - 16 + tid;
+      const double s1 = nrm[perm[0]];
+      const double v = (q >= 0 && q < c && s1 > 0.0) ? nrm[perm[q]] : 0.0;
+      f = v > 0.0 ? (float)fmax(log10(v / s1) / 8.0, -2.0) : -2.0f;
+    }
+    p.feat[tid] = f;
+  }
+  // this part's rows of U S (s x r) and Sigma^-1 U^T (r x s)
+  for (long e = tid; e < (long)nr * r; e += blockDim.x) {
+    const int rr = (int)(e / r), j = (int)(e % r), row = r0 + rr;
+    const double sg = nrm[perm[j]];
+    const double g = sh[(long)perm[j] * JS_ROWS + rr];
+    p.US[(long)row * r + j] = g;
+    p.Ut[(long)j * s + row] = sg > 0.0 ? g / (sg * sg) : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // One-sided Jacobi SVD (FP64) with truncation.
 // L (rows x cols, column-major, ld = rows) is copied to LDS (or to the
 // scratch L2 when it does not fit) and rotated together with W (cols x
