@@ -67,11 +67,7 @@ template <> struct MfmaT<float> {
 constexpr int GT = 64;   // tile edge
 constexpr int GK = 64;   // K slice staged through LDS per step
 
-// BF16 operands for v_mfma_f32_16x16x16bf16_1k: lane l supplies
-// A[l % 16][4 (l / 16) + j] and B[4 (l / 16) + j][l % 16], j = 0..3 (one
-// K tile of 16 per instruction); the accumulator layout is that of the FP32
-// 16x16x4 MFMA (checked on gfx950 with a one-wave probe).
-typedef short bf4 __attribute__((ext_vector_type(4)));
+// Round to nearest even BF16 (bit pattern) and back.
 __device__ inline short bf16_bits(float f) {
   unsigned u = __float_as_uint(f);
   u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
@@ -106,12 +102,30 @@ struct KSplit {
   int split;
 };
 
+// BF16 modes on gfx950's v_mfma_f32_16x16x32_bf16: lane l supplies
+// A[l % 16][8 (l / 16) + j] and B[8 (l / 16) + j][l % 16], j = 0..7 (one K
+// tile of 32 per instruction), with the accumulator layout of the 16x16x4
+// FP32 MFMA (checked with a one-wave probe of exact integer products).  The
+// operands are converted once, when a K slice is staged: rounded (MODE 1)
+// or split into three BF16 terms (MODE 2), stored K-contiguous per row of A
+// and per column of B (row stride BKP) so that a lane's eight K values are
+// one 16-byte LDS read.
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+constexpr int BKP = GK + 8;
+
 template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
 __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops,
                                               KSplit ks) {
   typedef typename MfmaT<Tacc>::V V;
-  __shared__ Tacc As[GK][GT + 1];
-  __shared__ Tacc Bs[GK][GT + 1];
+  constexpr size_t SM0 = 2 * sizeof(Tacc) * GK * (GT + 1);
+  constexpr size_t SMB = (MODE == 2 ? 6 : 2) * sizeof(short) * GT * BKP;
+  __shared__ __attribute__((aligned(16))) char smem[MODE == 0 ? SM0 : SMB];
+  Tacc (*As)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem);
+  Tacc (*Bs)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem + sizeof(Tacc) * GK * (GT + 1));
+  // BF16 tiles: A terms [GT rows][BKP], then B terms [GT columns][BKP]
+  short* const Ab = reinterpret_cast<short*>(smem);
+  constexpr int NT = MODE == 2 ? 3 : 1;
+  short* const Bb = Ab + NT * GT * BKP;
   long wg = blockIdx.x;
   const int kseg = (int)(wg % ks.split);
   wg /= ks.split;
@@ -169,34 +183,45 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       const int e = tid + 256 * q;
       int mm, kk;
       if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
-      As[kk][mm] = ra[q];
       int nn, kb;
       if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
-      Bs[kb][nn] = rb[q];
+      if constexpr (MODE == 0) {
+        As[kk][mm] = ra[q];
+        Bs[kb][nn] = rb[q];
+      } else if constexpr (MODE == 1) {
+        Ab[mm * BKP + kk] = bf16_bits((float)ra[q]);
+        Bb[nn * BKP + kb] = bf16_bits((float)rb[q]);
+      } else {
+        short x0, x1, x2;
+        bf16_split3((float)ra[q], x0, x1, x2);
+        Ab[mm * BKP + kk] = x0;
+        Ab[GT * BKP + mm * BKP + kk] = x1;
+        Ab[2 * GT * BKP + mm * BKP + kk] = x2;
+        bf16_split3((float)rb[q], x0, x1, x2);
+        Bb[nn * BKP + kb] = x0;
+        Bb[GT * BKP + nn * BKP + kb] = x1;
+        Bb[2 * GT * BKP + nn * BKP + kb] = x2;
+      }
     }
     __syncthreads();
     if (k0 + GK < ke) fetch(k0 + GK);
     const int kvalid = ke - k0;  // K columns of this slice that are not padding
     if constexpr (MODE == 2) {
 #pragma unroll
-      for (int ks = 0; ks < GK / 16; ++ks) {
-        if (ks * 16 < kvalid) {
-          bf4 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
+      for (int ks = 0; ks < GK / 32; ++ks) {
+        if (ks * 32 < kvalid) {
+          const int kof = ks * 32 + 8 * (lane >> 4);
+          bf8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int kr = ks * 16 + 4 * (lane >> 4) + j;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              short x0, x1, x2;
-              bf16_split3((float)As[kr][wm * 32 + 16 * h + (lane & 15)], x0, x1, x2);
-              ah[h][j] = x0;
-              am[h][j] = x1;
-              al[h][j] = x2;
-              bf16_split3((float)Bs[kr][wn * 32 + 16 * h + (lane & 15)], x0, x1, x2);
-              bh[h][j] = x0;
-              bm[h][j] = x1;
-              bl[h][j] = x2;
-            }
+          for (int h = 0; h < 2; ++h) {
+            const int ra_ = (wm * 32 + 16 * h + (lane & 15)) * BKP + kof;
+            const int cb_ = (wn * 32 + 16 * h + (lane & 15)) * BKP + kof;
+            ah[h] = *reinterpret_cast<const bf8*>(Ab + ra_);
+            am[h] = *reinterpret_cast<const bf8*>(Ab + GT * BKP + ra_);
+            al[h] = *reinterpret_cast<const bf8*>(Ab + 2 * GT * BKP + ra_);
+            bh[h] = *reinterpret_cast<const bf8*>(Bb + cb_);
+            bm[h] = *reinterpret_cast<const bf8*>(Bb + GT * BKP + cb_);
+            bl[h] = *reinterpret_cast<const bf8*>(Bb + 2 * GT * BKP + cb_);
           }
 #pragma unroll
           for (int i = 0; i < 2; ++i)
@@ -204,33 +229,31 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
             for (int jj = 0; jj < 2; ++jj) {
               // smallest terms first
               V c = acc[i][jj];
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al[i], bh[jj], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bm[jj], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bl[jj], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(am[i], bh[jj], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bm[jj], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah[i], bh[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bm[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bl[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(am[i], bh[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bm[jj], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[i], bh[jj], c, 0, 0, 0);
               acc[i][jj] = c;
             }
         }
       }
     } else if constexpr (MODE == 1) {
 #pragma unroll
-      for (int ks = 0; ks < GK / 16; ++ks) {
-        if (ks * 16 < kvalid) {
-          bf4 a0, a1, b0, b1;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int kr = ks * 16 + 4 * (lane >> 4) + j;
-            a0[j] = bf16_bits(As[kr][wm * 32 + (lane & 15)]);
-            a1[j] = bf16_bits(As[kr][wm * 32 + 16 + (lane & 15)]);
-            b0[j] = bf16_bits(Bs[kr][wn * 32 + (lane & 15)]);
-            b1[j] = bf16_bits(Bs[kr][wn * 32 + 16 + (lane & 15)]);
-          }
-          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc[1][1], 0, 0, 0);
+      for (int ks = 0; ks < GK / 32; ++ks) {
+        if (ks * 32 < kvalid) {
+          const int kof = ks * 32 + 8 * (lane >> 4);
+          const bf8 a0 = *reinterpret_cast<const bf8*>(Ab + (wm * 32 + (lane & 15)) * BKP + kof);
+          const bf8 a1 =
+              *reinterpret_cast<const bf8*>(Ab + (wm * 32 + 16 + (lane & 15)) * BKP + kof);
+          const bf8 b0 = *reinterpret_cast<const bf8*>(Bb + (wn * 32 + (lane & 15)) * BKP + kof);
+          const bf8 b1 =
+              *reinterpret_cast<const bf8*>(Bb + (wn * 32 + 16 + (lane & 15)) * BKP + kof);
+          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
         }
       }
     } else {
