@@ -271,6 +271,12 @@ def main():
         kp = sim.kernel_stats()
         out["roofline_mfma"] = roofline("prodgemm", kp, case.precision)
         out["roofline_mfma"]["share_of_step"] = kp.total_ms / (mms * args.mfma_steps)
+        if case.precision == "bf16x3":
+            # achieved counts one useful product per multiply-add; the
+            # matrix cores run six BF16 products for each (three-term split)
+            rm = out["roofline_mfma"]
+            rm["mfma_products_per_useful"] = 6
+            rm["matrix_core_frac"] = 6 * rm["frac"]
     if not args.no_graph:
         # the same step recorded once as a HIP graph and replayed (the timed
         # region above issues it kernel by kernel, with per-launch events)
