@@ -11,6 +11,7 @@ paper's definition of the operation:
   sigma_k = 4 x_k + 2 y_k + z_k;
 * TT-SVD construction (Section 2.1, svd-comp equation) and the centre
   shift by SVD with truncation (svd-move equation);
+* the tensor-product composition of a coarse and a fine mask (Appendix D);
 * elementwise addition by block-diagonal cores (Section 2.2, add equation),
   the exact Hadamard product (mul equation), MPO application (applympo
   equation);
@@ -105,6 +106,16 @@ def to_dense(cores) -> np.ndarray:
 
 def bonds(cores):
     return [c.shape[2] for c in cores[:-1]]
+
+
+def tensor_product(outer, inner):
+    """MPS of the composition m(x) = outer(x >> k) inner(x mod 2^k) per axis
+    (Appendix D): with scale ordering the l sites of the coarse grid come
+    first and the k sites of the fine grid after them, so the cores of the
+    two MPS are simply chained; the bond between them is 1 (outer's last
+    and inner's first bond)."""
+    assert outer[-1].shape[2] == 1 and inner[0].shape[0] == 1
+    return [c.copy() for c in outer] + [c.copy() for c in inner]
 
 
 def ones(n: int):

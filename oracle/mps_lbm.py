@@ -70,7 +70,17 @@ class MPSLBM:
         # the mask bond dimension; case.chi_mask caps it explicitly.
         chi_mask = int(case.chi_mask) if case.chi_mask else 1 << 30
         fluid = None
-        if case.solid is not None:
+        if case.solid is not None and case.mask_parts is not None:
+            # a geometry repeated on a coarse grid (Appendix D): each part is
+            # decomposed on its own grid and the two MPS are chained
+            outer, inner = case.mask_parts
+            l = int(round(np.log2(outer.shape[0])))
+            self.mask = M.tensor_product(
+                M.from_dense(outer.astype(np.float64), l, chi_mask, case.tol_mask),
+                M.from_dense(inner.astype(np.float64), n - l, chi_mask, case.tol_mask))
+            self.n_fluid = float(self.N ** 3) - M.inner_ones(self.mask)
+            fluid = 1.0 - case.solid.astype(np.float64)
+        elif case.solid is not None:
             self.mask = M.from_dense(case.solid.astype(np.float64), n, chi_mask,
                                      case.tol_mask)
             self.n_fluid = float(self.N ** 3) - M.inner_ones(self.mask)

@@ -7,8 +7,8 @@ their inputs from here without sharing any code of the method itself.
 
 The paper's own geometries (an idealised aneurysm and a pin-fin heat sink,
 Section 4.1) are not available; the generators below stand in for them with
-seeded shapes of the same kind: a porous medium of random spheres and a
-branching tube tree with Murray's-law radii.
+seeded shapes of the same kind: a porous medium of random spheres, a
+branching tube tree with Murray's-law radii and an array of cylindrical pins.
 
 Conventions: a field on an N^3 grid is a C-order array indexed [x][y][z];
 solid masks are uint8 with 1 = solid; N = 2**n.
@@ -48,6 +48,9 @@ class Case:
     precision: str = "fp64"
     chi_mask: Optional[int] = None
     tol_mask: float = 1e-12
+    # (outer [L][L][L], inner [K][K][K]) uint8 with L K = N: the solid is the
+    # inner geometry placed in every solid cell of the coarse outer grid
+    mask_parts: Optional[Tuple[np.ndarray, np.ndarray]] = None
     meta: dict = field(default_factory=dict)
 
     @property
@@ -170,6 +173,41 @@ def vascular_tree_mask(n: int, seed: int, generations: int = 3,
     return (~fluid).astype(np.uint8), segments
 
 
+def pin_fin_parts(n: int, l: int = 3, seed: int = 2512 + 6, radius_frac: float = 0.25,
+                  x_range: Tuple[int, int] = (1, 7), z_cells: Optional[int] = None,
+                  missing: float = 0.2) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """Array of vertical (z) cylindrical pins on a coarse grid of 2**l cells
+    per axis, each coarse cell of side K = 2**(n - l) holding one pin of
+    radius radius_frac * K about its centre line.  Pins stand in the coarse
+    columns x_range[0] <= X < x_range[1] (every Y), over the lower z_cells
+    coarse layers (default half the height); each (X, Y) column is left
+    empty with probability `missing` (seeded).  Returns (outer [L]^3,
+    inner [K]^3, solid [N]^3), all uint8; solid is drawn directly from the
+    pin axes on the fine grid."""
+    N, L, K = 1 << n, 1 << l, 1 << (n - l)
+    zc = L // 2 if z_cells is None else z_cells
+    rng = np.random.default_rng(seed)
+    present = rng.uniform(size=(L, L)) >= missing
+    present[:x_range[0], :] = False
+    present[x_range[1]:, :] = False
+    outer = np.zeros((L, L, L), dtype=np.uint8)
+    outer[:, :, :zc] = present[:, :, None]
+    c = (K - 1) / 2.0
+    r2 = (radius_frac * K) ** 2
+    a = np.arange(K, dtype=np.float64) - c
+    disk = (a[:, None] ** 2 + a[None, :] ** 2) <= r2
+    inner = np.repeat(disk[:, :, None], K, axis=2).astype(np.uint8)
+    ax = np.arange(N, dtype=np.float64)
+    solid = np.zeros((N, N, N), dtype=np.uint8)
+    for X in range(L):
+        for Y in range(L):
+            if not present[X, Y]:
+                continue
+            d2 = ((ax[:, None] - (X * K + c)) ** 2 + (ax[None, :] - (Y * K + c)) ** 2)
+            solid[:, :, :zc * K] |= (d2 <= r2)[:, :, None].astype(np.uint8)
+    return outer, inner, solid
+
+
 # --------------------------------------------------------------------------
 # the benchmark / parity cases (synthetic stand-ins with the paper's shapes)
 # --------------------------------------------------------------------------
@@ -212,6 +250,21 @@ def case_vascular(n: int = 7, chi: int = 128, tau: float = 0.55,
                 steps=steps, precision=precision,
                 meta={"seed": seed, "solid_fraction": float(solid.mean()),
                       "segments": len(segs)})
+
+
+def case_pinfin(n: int = 7, l: int = 3, chi: int = 64, tau: float = 0.56,
+                u_in: float = 0.02, seed: int = 2512 + 6, tol: float = 1e-8,
+                steps: int = 100, precision: str = "fp32") -> Case:
+    """Pin-fin array (Section 4.1 stand-in): velocity inlet on x = 0, pressure
+    outlet on x = N-1, y and z periodic; pins on a 2**l coarse grid
+    (layer spacing L / 2**l), the mask given as its two parts."""
+    outer, inner, solid = pin_fin_parts(n, l, seed)
+    return Case(name=f"pinfin{1 << n}", n=n, tau=tau, chi=chi, tol=tol,
+                solid=solid, axis_open=(1, 0, 0),
+                face_bc=(BC_VELOCITY, BC_PRESSURE, 0, 0, 0, 0),
+                face_val=((u_in, 0, 0), (1.0, 0, 0)) + ((0, 0, 0),) * 4,
+                steps=steps, precision=precision, mask_parts=(outer, inner),
+                meta={"seed": seed, "solid_fraction": float(solid.mean()), "l": l})
 
 
 def random_flow_state(n: int, seed: int, amp: float = 0.02,
