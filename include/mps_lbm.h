@@ -180,6 +180,28 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho,
                             mps_lbm_t** out);
 
 /*
+ * Create a simulation whose obstacle geometry repeats a unit geometry on a
+ * coarse grid (Appendix D): solid_outer [L][L][L] (L = 2^l) marks the
+ * coarse cells that hold the unit geometry solid_inner [K][K][K]
+ * (K = 2^(n-l)), both C-order uint8 host arrays with 1 = solid, so that
+ * solid(x) = solid_outer(x >> (n-l)) * solid_inner(x mod K) per axis.  The
+ * obstacle mask m_O is the tensor product of the two parts: each part is
+ * decomposed on its own grid by successive truncated SVDs at tol_mask (rank
+ * cap chi_mask_max when > 0) and the two MPS are chained, the l coarse
+ * sites first, with bond 1 between them, so that the mask's largest bond is
+ * the larger of the parts' (no N^3 decomposition of the mask is made).  The
+ * dense composite solid is formed on the device for the initial
+ * populations, N_fluid and the face masks.  rho, u, f and hip_stream are
+ * as in mps_lbm_init_from_field.  The mask decomposition error reported in
+ * the observables is that of the chained mask against the composite.
+ * Errors: as mps_lbm_init_from_field; EINVAL also for NULL parts or
+ * l outside [2, n - 2].
+ */
+int mps_lbm_init_tensor_mask(const mps_lbm_config* cfg, const double* rho, const double* u,
+                             const double* f, const uint8_t* solid_outer, int l,
+                             const uint8_t* solid_inner, void* hip_stream, mps_lbm_t** out);
+
+/*
  * Numerical failures.  The factorisation kernels flag non-finite values and
  * Jacobi sweeps that stop at their iteration limit (Section 2.1 truncations)
  * in device memory.  Every call that synchronises with the device to read

@@ -80,6 +80,49 @@ __global__ void k_convert_mps(MpsList<Ts> S, MpsList<Td> Dl, int n) {
     y[e] = (Td)x[e];
 }
 
+// Chain of two MPS (Appendix D): the la cores of a (coarse grid) followed by
+// the lb cores of b (fine grid) form the MPS of their tensor product; the
+// bond between them is 1.  Grid (chunks, la + lb).
+template <typename Ts, typename Td>
+__global__ void k_chain_mps(const MpsDev<Ts>* a, int la, const MpsDev<Ts>* b, int lb,
+                            MpsDev<Td>* d) {
+  const int k = blockIdx.y;
+  if (blockIdx.x == 0 && k == 0) {
+    const int j = threadIdx.x;
+    if (j <= la) d->r[j] = a->r[j];
+    if (j >= 1 && j <= lb) d->r[la + j] = b->r[j];
+  }
+  const MpsDev<Ts>* src = k < la ? a : b;
+  const int ks = k < la ? k : k - la;
+  const long tot = (long)src->r[ks] * PHYS * src->r[ks + 1];
+  const Ts* x = src->data + src->off[ks];
+  Td* y = d->data + d->off[k];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x)
+    y[e] = (Td)x[e];
+}
+
+// Dense solid of a coarse layout (side 2^(n-k)) with the fine unit geometry
+// (side 2^k) in each of its solid cells (Appendix D composition).
+__global__ void k_compose_solid(const uint8_t* outer, const uint8_t* inner, uint8_t* out, int n,
+                                int k) {
+  const long N3 = 1L << (3 * n);
+  const int N = 1 << n, L = 1 << (n - k), K = 1 << k;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
+       e += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(e >> (2 * n)), y = (int)((e >> n) & (N - 1)), z = (int)(e & (N - 1));
+    const long eo = ((long)(x >> k) * L + (y >> k)) * L + (z >> k);
+    const long ei = ((long)(x & (K - 1)) * K + (y & (K - 1))) * K + (z & (K - 1));
+    out[e] = (outer[eo] != 0 && inner[ei] != 0) ? 1 : 0;
+  }
+}
+
+__global__ void k_u8_to_f64(const uint8_t* in, double* out, long count) {
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < count;
+       e += (long)gridDim.x * blockDim.x)
+    out[e] = in[e] ? 1.0 : 0.0;
+}
+
 __global__ void k_add_flags(int* istats, int sweep_limit, int nonfinite) {
   if (threadIdx.x == 0) {
     istats[0] += sweep_limit;
@@ -101,6 +144,15 @@ struct Domain {
   double n_fluid = 0.0;
   double mask_err = 0.0;
   double face_err = 0.0;
+};
+
+// Obstacle geometry given as a coarse layout outer [L][L][L] (L = 2^l) and
+// the fine unit geometry inner [K][K][K] (K = 2^(n-l)) repeated in each of
+// its solid cells (Appendix D); host arrays, 1 = solid.
+struct MaskParts {
+  const uint8_t* outer;
+  int l;
+  const uint8_t* inner;
 };
 
 // dense [x][y][z] field: 1 on the fluid cells of the plane x_ax = idx
@@ -259,9 +311,62 @@ struct SimT : Sim {
   int mcp[MAXN + 1];    // product launch capacities of the masks' bonds
   bool any_mask = false;
 
-  // Initial state of domain d from dense fields (all synchronous).
+  // Obstacle mask of domain d as the tensor product of a coarse layout
+  // (l sites) and a fine unit geometry (n - l sites), Appendix D: each part
+  // is decomposed by TT-SVD at tol_mask (rank cap chi_mask_max, if any) on
+  // its own grid in FP64, and the two MPS are chained into one mask object
+  // whose capacities are exactly the resulting bonds.
+  void tensor_mask(Domain& dm, const MaskParts& mp, std::vector<void*>& staged) {
+    const mps_lbm_config& cfg = dm.cfg;
+    const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
+    const int len[2] = {mp.l, n - mp.l};
+    const uint8_t* part[2] = {mp.outer, mp.inner};
+    Engine<double> sub[2];
+    int obj[2];
+    MpsDev<double> hd[2];
+    for (int p = 0; p < 2; ++p) {
+      const int m = len[p];
+      const long M3 = 1L << (3 * m);
+      sub[p].al = E.al;
+      sub[p].setup(m, std::min(cfg.chi_max, 16), cfg.tol_mask, st, 0, 1);
+      uint8_t* du8 = (uint8_t*)E.dalloc(M3);
+      staged.push_back(du8);
+      HIP_OK(hipMemcpyAsync(du8, part[p], M3, hipMemcpyHostToDevice, st));
+      double* dv = (double*)sub[p].dalloc(8 * M3);
+      double* Wv = (double*)sub[p].dalloc(8 * M3);
+      hipLaunchKernelGGL(k_u8_to_f64, dim3(dense_chunks(M3)), dim3(256), 0, st,
+                         (const uint8_t*)du8, dv, M3);
+      hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(M3)), dim3(256), 0,
+                         st, (const double*)dv, Wv, m, 1, 1);
+      int cap[MAXN + 1];
+      for (int k = 0; k <= m; ++k)
+        cap[k] = (k == 0 || k == m) ? 1 : std::min(chi_mask, Engine<double>::full_bound(m, k));
+      obj[p] = sub[p].add_fixed(cap);
+      sub[p].tt_svd(Wv, 1, {obj[p]}, chi_mask, cfg.tol_mask);
+      HIP_OK(hipMemcpyAsync(&hd[p], sub[p].D(obj[p]), sizeof(MpsDev<double>),
+                            hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      sub[p].free_alloc(Wv);
+      sub[p].free_alloc(dv);
+    }
+    int cap[MAXN + 1];
+    for (int k = 0; k <= mp.l; ++k) cap[k] = hd[0].r[k];
+    for (int k = 0; k <= n - mp.l; ++k) cap[mp.l + k] = hd[1].r[k];
+    if (cap[mp.l] != 1) throw Error(-3, "tensor-product mask: parts are not closed MPS");
+    dm.mask = E.add_fixed(cap);
+    hipLaunchKernelGGL((k_chain_mps<double, T>), dim3(E.chunks(), n), dim3(256), 0, st,
+                       (const MpsDev<double>*)sub[0].D(obj[0]), mp.l,
+                       (const MpsDev<double>*)sub[1].D(obj[1]), n - mp.l, E.D(dm.mask));
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    for (int p = 0; p < 2; ++p) sub[p].drop_fixed(obj[p]);
+  }
+
+  // Initial state of domain d from dense fields (all synchronous).  The
+  // obstacle geometry is the dense solid field, or, when mp is given, the
+  // composition of its two parts.
   void init_domain(int d, const double* rho, const double* u, const double* fin,
-                   const uint8_t* solid) {
+                   const uint8_t* solid, const MaskParts* mp = nullptr) {
     Domain& dm = dom[d];
     const mps_lbm_config& cfg = dm.cfg;
     // dense staging, released at the end (the masks allocated on the way
@@ -278,22 +383,36 @@ struct SimT : Sim {
     if (solid) {
       dsolid = (uint8_t*)stage(N3);
       HIP_OK(hipMemcpy(dsolid, solid, N3, hipMemcpyHostToDevice));
-      std::vector<double> hs(N3);
-      for (long e = 0; e < N3; ++e) hs[e] = solid[e] ? 1.0 : 0.0;
-      HIP_OK(hipMemcpy(dd, hs.data(), 8 * N3, hipMemcpyHostToDevice));
+    } else if (mp) {
+      const long L3 = 1L << (3 * mp->l), K3 = 1L << (3 * (n - mp->l));
+      uint8_t* o = (uint8_t*)stage(L3);
+      uint8_t* i = (uint8_t*)stage(K3);
+      HIP_OK(hipMemcpy(o, mp->outer, L3, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(i, mp->inner, K3, hipMemcpyHostToDevice));
+      dsolid = (uint8_t*)stage(N3);
+      hipLaunchKernelGGL(k_compose_solid, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                         (const uint8_t*)o, (const uint8_t*)i, dsolid, n, n - mp->l);
+    }
+    if (dsolid) {
+      hipLaunchKernelGGL(k_u8_to_f64, dim3(dense_chunks(N3)), dim3(256), 0, st,
+                         (const uint8_t*)dsolid, dd, N3);
       hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(N3)), dim3(256), 0, st,
                          (const double*)dd, W, n, 1, 1);
-      // obstacle mask (objects equation): TT-SVD of the solid field at
-      // tol_mask in an MPS of its own capacity, by default uncapped, i.e.
-      // at machine precision (the mask bond dimension of Section 5.2)
-      int cap[MAXN + 1];
-      for (int k = 0; k <= n; ++k) cap[k] = mask_cap(k);
-      dm.mask = E.add_fixed(cap);
       T* Wkeep = (T*)stage(sizeof(T) * N3);
       hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W,
                          Wkeep, N3);
-      const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
-      dense_to_mps(dd, W, 1, {dm.mask}, chi_mask, cfg.tol_mask, cap);
+      if (mp) {
+        tensor_mask(dm, *mp, staged);
+      } else {
+        // obstacle mask (objects equation): TT-SVD of the solid field at
+        // tol_mask in an MPS of its own capacity, by default uncapped, i.e.
+        // at machine precision (the mask bond dimension of Section 5.2)
+        int cap[MAXN + 1];
+        for (int k = 0; k <= n; ++k) cap[k] = mask_cap(k);
+        dm.mask = E.add_fixed(cap);
+        const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
+        dense_to_mps(dd, W, 1, {dm.mask}, chi_mask, cfg.tol_mask, cap);
+      }
       dm.mask_err = decomposition_error(dm.mask, Wkeep);
       E.inner_ones({dm.mask}, sbuf + 2);
       double ones_m = 0.0;
@@ -1107,7 +1226,7 @@ static int validate(const mps_lbm_config* c) {
 
 static int create(const mps_lbm_config* cfgs, int count, const double* const* rho,
                   const double* const* u, const double* const* f, const uint8_t* const* solid,
-                  void* hip_stream, mps_lbm_t** out) {
+                  void* hip_stream, mps_lbm_t** out, const MaskParts* mp = nullptr) {
   return guarded([&]() -> int {
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1121,14 +1240,14 @@ static int create(const mps_lbm_config* cfgs, int count, const double* const* rh
       h->sim.reset(s);
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
-                       solid ? solid[d] : nullptr);
+                       solid ? solid[d] : nullptr, mp);
       s->finish_init();
     } else {
       auto* s = new SimT<float>(cfgs, count, st, g_alloc);
       h->sim.reset(s);
       for (int d = 0; d < count; ++d)
         s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
-                       solid ? solid[d] : nullptr);
+                       solid ? solid[d] : nullptr, mp);
       s->finish_init();
     }
     *out = h.release();
@@ -1146,6 +1265,22 @@ int mps_lbm_init_from_field(const mps_lbm_config* cfg, const double* rho, const 
   if (v) return v;
   if (!f && (!rho || !u)) return fail(MPS_LBM_EINVAL, "need f or both rho and u");
   return create(cfg, 1, &rho, &u, &f, &solid, hip_stream, out);
+}
+
+int mps_lbm_init_tensor_mask(const mps_lbm_config* cfg, const double* rho, const double* u,
+                             const double* f, const uint8_t* solid_outer, int l,
+                             const uint8_t* solid_inner, void* hip_stream, mps_lbm_t** out) {
+  if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  int v = validate(cfg);
+  if (v) return v;
+  if (!f && (!rho || !u)) return fail(MPS_LBM_EINVAL, "need f or both rho and u");
+  if (!solid_outer || !solid_inner) return fail(MPS_LBM_EINVAL, "mask parts are NULL");
+  if (l < 2 || cfg->n - l < 2)
+    return fail(MPS_LBM_EINVAL, "each mask part needs at least 2 sites (2 <= l <= n - 2)");
+  const MaskParts mp{solid_outer, l, solid_inner};
+  const uint8_t* none = nullptr;
+  return create(cfg, 1, &rho, &u, &f, &none, hip_stream, out, &mp);
 }
 
 int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* const* rho,

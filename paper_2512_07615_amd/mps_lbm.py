@@ -37,7 +37,8 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_train_rank_predictor", "mps_lbm_rank_predictor_info",
                    "mps_lbm_mlp_gradient", "mps_lbm_autotune", "mps_lbm_set_allocator",
                    "mps_lbm_load_rank_model", "mps_lbm_get_rank_model",
-                   "mps_lbm_debug_raise_flags", "mps_lbm_mlp_gradient_device"])
+                   "mps_lbm_debug_raise_flags", "mps_lbm_mlp_gradient_device",
+                   "mps_lbm_init_tensor_mask"])
 
 
 class Config(C.Structure):
@@ -103,6 +104,10 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_init_from_field.argtypes = [C.POINTER(Config), DP, DP, DP,
                                             C.POINTER(C.c_uint8), P, C.POINTER(P)]
     lib.mps_lbm_init_from_field.restype = C.c_int
+    lib.mps_lbm_init_tensor_mask.argtypes = [C.POINTER(Config), DP, DP, DP,
+                                             C.POINTER(C.c_uint8), C.c_int,
+                                             C.POINTER(C.c_uint8), P, C.POINTER(P)]
+    lib.mps_lbm_init_tensor_mask.restype = C.c_int
     lib.mps_lbm_step.argtypes = [P, C.c_int]
     lib.mps_lbm_step.restype = C.c_int
     lib.mps_lbm_to_dense.argtypes = [P, C.c_int, DP, C.c_size_t]
@@ -190,6 +195,30 @@ def mps_lbm_init_from_field(cfg: Config, rho=None, u=None, f=None, solid=None,
     h = C.c_void_p()
     _check(lib.mps_lbm_init_from_field(C.byref(cfg), _dp(rho), _dp(u), _dp(f), s,
                                        C.c_void_p(hip_stream or 0), C.byref(h)))
+    return h
+
+
+def mps_lbm_init_tensor_mask(cfg: Config, solid_outer, solid_inner, rho=None, u=None, f=None,
+                             hip_stream: Optional[int] = None):
+    """Create a simulation whose obstacle mask is solid_outer (x) solid_inner
+    (cubic uint8 arrays of sides 2**l and 2**(n - l))."""
+    lib = load()
+    rho = None if rho is None else np.ascontiguousarray(rho, dtype=np.float64)
+    u = None if u is None else np.ascontiguousarray(u, dtype=np.float64)
+    f = None if f is None else np.ascontiguousarray(f, dtype=np.float64)
+    outer = np.ascontiguousarray(solid_outer, dtype=np.uint8)
+    inner = np.ascontiguousarray(solid_inner, dtype=np.uint8)
+    L = outer.shape[0] if outer.ndim == 3 else 0
+    if L < 1 or outer.shape != (L, L, L) or L & (L - 1):
+        raise ValueError("solid_outer must be a cube of side 2**l")
+    K = (1 << cfg.n) // L
+    if inner.shape != (K, K, K):
+        raise ValueError("solid_inner must be a cube of side 2**(n - l)")
+    h = C.c_void_p()
+    _check(lib.mps_lbm_init_tensor_mask(
+        C.byref(cfg), _dp(rho), _dp(u), _dp(f), outer.ctypes.data_as(C.POINTER(C.c_uint8)),
+        int(L).bit_length() - 1, inner.ctypes.data_as(C.POINTER(C.c_uint8)),
+        C.c_void_p(hip_stream or 0), C.byref(h)))
     return h
 
 
@@ -478,8 +507,14 @@ class Simulation:
     def __init__(self, case, precision=None, hip_stream=None, **kw):
         self.case = case
         self.cfg = config_from_case(case, precision, **kw)
-        self.h = mps_lbm_init_from_field(self.cfg, rho=case.rho0_field(), u=case.u0_field(),
-                                         solid=case.solid, hip_stream=hip_stream)
+        if case.mask_parts is not None:
+            outer, inner = case.mask_parts
+            self.h = mps_lbm_init_tensor_mask(self.cfg, outer, inner, rho=case.rho0_field(),
+                                              u=case.u0_field(), hip_stream=hip_stream)
+        else:
+            self.h = mps_lbm_init_from_field(self.cfg, rho=case.rho0_field(),
+                                             u=case.u0_field(), solid=case.solid,
+                                             hip_stream=hip_stream)
 
     def step(self, n=1):
         mps_lbm_step(self.h, n)

@@ -95,6 +95,35 @@ def test_bc_on_periodic_axis_and_missing_fields_rejected():
                                       None, None, None, None, C.byref(h)) == L.EINVAL
 
 
+def test_tensor_mask_init_validates_its_parts_before_device_use():
+    L = lib()
+    so = L.load()
+    c = L.mps_lbm_default_config()
+    c.n = 5
+    rho = np.ones((32, 32, 32))
+    u = np.zeros((3, 32, 32, 32))
+    outer = np.zeros((8, 8, 8), dtype=np.uint8)
+    inner = np.zeros((4, 4, 4), dtype=np.uint8)
+    DP = C.POINTER(C.c_double)
+    U8 = C.POINTER(C.c_uint8)
+    h = C.c_void_p()
+    args = (rho.ctypes.data_as(DP), u.ctypes.data_as(DP), None)
+    # NULL parts
+    assert so.mps_lbm_init_tensor_mask(C.byref(c), *args, None, 3, inner.ctypes.data_as(U8),
+                                       None, C.byref(h)) == L.EINVAL
+    assert so.mps_lbm_init_tensor_mask(C.byref(c), *args, outer.ctypes.data_as(U8), 3, None,
+                                       None, C.byref(h)) == L.EINVAL
+    # each part needs at least two sites
+    for l in (1, 4, 0, 7):
+        assert so.mps_lbm_init_tensor_mask(C.byref(c), *args, outer.ctypes.data_as(U8), l,
+                                           inner.ctypes.data_as(U8), None,
+                                           C.byref(h)) == L.EINVAL
+    assert not h.value
+    # the binding checks the shapes of the parts
+    with pytest.raises(ValueError):
+        L.mps_lbm_init_tensor_mask(c, outer, np.zeros((8, 8, 8), np.uint8), rho=rho, u=u)
+
+
 def test_null_handle_calls_fail_cleanly():
     L = lib()
     so = L.load()
@@ -201,7 +230,7 @@ def test_every_entry_point_that_reaches_the_engine_is_guarded():
         calls = [c for c in calls if not any(c.startswith("->sim" + x[:-2]) for x in no_engine)]
         if calls or "new " in body or "hipMemcpy" in body:
             assert "guarded(" in body or name == "mps_lbm_destroy", name
-    # create(), which the two init entry points call, runs inside guarded()
+    # create(), which the init entry points call, runs inside guarded()
     c0 = src.index("static int create(")
     assert "return guarded(" in src[c0:src.index("int mps_lbm_init_from_field", c0)]
     assert "catch (...)" in src[src.index("static int guarded"):start]
