@@ -23,6 +23,7 @@ from __future__ import annotations
 
 import numpy as np
 
+from .inflow import face_velocity
 from .lattice import C, W, OPP, Q, PI_PAIRS
 
 INV_EXACT = "exact"
@@ -154,7 +155,7 @@ class DenseLBM:
                     c = C[i].astype(np.float64)
                     fo = fpost[OPP[i]][sl]
                     if typ == 1:  # velocity: Ladd bounce-back with rho_b = rho_0
-                        ub = np.array(case.face_val[face], dtype=np.float64)
+                        ub = np.array(face_velocity(case, face, self.step_count))
                         b = fo + 6.0 * W[i] * mac["rho0"] * float(c @ ub) * fl
                     elif typ == 2:  # pressure: anti-bounce-back, u_b = local u
                         rho_b = float(case.face_val[face][0])

@@ -31,7 +31,9 @@ from __future__ import annotations
 import numpy as np
 
 from . import mps as M
+from .inflow import face_velocity
 from .lattice import C, W, OPP, Q, PI_PAIRS
+from .metrics import pressure_drop
 
 INV_TAYLOR2 = "taylor2"
 INV_NEWTON = "newton"
@@ -237,7 +239,7 @@ class MPSLBM:
                     c = C[i].astype(np.float64)
                     fo = M.plane_slice(fpost[OPP[i]], ax, idx)
                     if typ == 1:
-                        ub = np.array(case.face_val[face], dtype=np.float64)
+                        ub = np.array(face_velocity(case, face, self.step_count))
                         terms = [(1.0, fo), (6.0 * W[i] * mac["rho0"] * float(c @ ub), fp)]
                     else:
                         rho_b = float(case.face_val[face][0])
@@ -276,6 +278,12 @@ class MPSLBM:
     # ---- observables -------------------------------------------------------
     def dense_populations(self):
         return np.stack([M.to_dense(x) for x in self.f])
+
+    def pressure_drop(self, lo, hi, rho_ref: float) -> float:
+        """Delta p / p_0 over the fluid cells of a box (Section 4.2), from the
+        dense density sum_i f_i."""
+        rho = sum(M.to_dense(x) for x in self.f)
+        return pressure_drop(rho, self.case.solid, lo, hi, rho_ref)
 
     def mass(self):
         return sum(M.inner_ones(x) for x in self.f)

@@ -51,6 +51,10 @@ class Case:
     # (outer [L][L][L], inner [K][K][K]) uint8 with L K = N: the solid is the
     # inner geometry placed in every solid cell of the coarse outer grid
     mask_parts: Optional[Tuple[np.ndarray, np.ndarray]] = None
+    # velocity faces with a time-dependent inflow: face -> (c0..c5, dt), the
+    # face velocity scaled by c0 + c1 (1 - e^(-c2 t)) + c3 t^c4 e^(-c5 t)
+    # with t = (steps taken) dt
+    face_profile: Optional[dict] = None
     meta: dict = field(default_factory=dict)
 
     @property
