@@ -137,6 +137,10 @@ typedef struct {
   double face_trunc_err;   /* largest ||m_B - m_B~|| / ||m_B|| of the open-face
                               masks (fluid cells of the face plane), which are
                               decomposed at tol_mask with rank cap chi_max */
+  double dp_p0;            /* Delta p / p_0 over the region set by
+                              mps_lbm_set_region (Section 4.2); 0 if none   */
+  double region_cells;     /* |D|: fluid cells of that region               */
+  double region_trunc_err; /* ||m_D - m_D~|| / ||m_D|| of its MPS            */
 } mps_lbm_obs;
 
 /*
@@ -222,6 +226,39 @@ int mps_lbm_init_tensor_mask(const mps_lbm_config* cfg, const double* rho, const
  * no host synchronisation.  Errors: EINVAL (NULL handle, nsteps < 0), EHIP.
  */
 int mps_lbm_step(mps_lbm_t* h, int nsteps);
+
+/*
+ * Time-dependent inflow (Section 4.1: the aneurysm's pulse, the pin-fin
+ * ramp).  From the next step on, velocity face `face` (0..5 as in
+ * face_bc) of domain `domain` uses u_b(t) = face_val[face] * phi(t) with
+ *   phi(t) = c0 + c1 (1 - exp(-c2 t)) + c3 t^c4 exp(-c5 t),
+ * coef = {c0, ..., c5}, and t = k dt for the step that starts after k
+ * steps since init (k counted on the device, so captured graphs follow the
+ * profile too).  Examples: the ramp u_0 (1 - e^{-1.5 t}) is {0, 1, 1.5, 0,
+ * 0, 0} with dt = 1 / (steps per flow-through time L / u_0); the pulse
+ * 0.1 + 18 t^1.5 e^{-10 t} is {0.1, 0, 0, 18, 1.5, 10} with dt in seconds per
+ * step and face_val the lattice velocity of 1 m/s.  coef = NULL restores
+ * the constant face (phi = 1).  Synchronises the handle's stream.
+ * Errors: EINVAL (NULL handle, domain or face out of range, the face is not
+ * a velocity face, a non-finite coefficient, c4 < 0, dt < 0), EHIP.
+ */
+int mps_lbm_set_face_profile(mps_lbm_t* h, int domain, int face, const double* coef,
+                             double dt);
+
+/*
+ * Region of interest of the pressure metric (Section 4.2):
+ *   Delta p / p_0 = (1 / (p_0 |D|)) sum_{x in D} (p_x - p_0),
+ * p = c_s^2 rho, p_0 = c_s^2 rho_ref (the density prescribed at the
+ * outflow), D = the fluid cells of the box lo[a] <= x_a < hi[a].  The
+ * indicator of D is decomposed into an MPS m_D at tol_mask without a rank
+ * cap (like the obstacle mask; the solid cells are read from it), |D| is
+ * counted exactly, and mps_lbm_observables then reports dp_p0 =
+ * sum_i <m_D, f_i> / (rho_ref |D|) - 1, an exact contraction of the state.
+ * A later call replaces the region.  Synchronises the handle's stream.
+ * Errors: EINVAL (NULL handle or box, domain out of range, empty box or box
+ * outside the grid, no fluid cell in it, rho_ref <= 0), ENOMEM, EHIP.
+ */
+int mps_lbm_set_region(mps_lbm_t* h, int domain, const int* lo, const int* hi, double rho_ref);
 
 /* Testing hook for the numerical-failure path: adds nonfinite to the
    device's non-finite count and sweep_limit to its sweep-limit count, as a

@@ -55,24 +55,31 @@ struct MpsList {
   MpsDev<T>* p[MAXB];
 };
 
-// Coefficient a * rho0^p where rho0 is a device scalar (p in {-2..1}).
 // Coefficient a * rho_0^p of a term (p in {1, 0, -1, -2}); d selects the
 // domain whose rho_0 applies when several domains are advanced together.
+// The scalars live in one device array (rho_0 of the domains first); s > 0
+// multiplies the coefficient by entry s of that array as well (a factor the
+// device updates every step, such as a time-dependent face velocity).
 struct Coef {
   double a;
-  int p;
-  int d;
+  int p : 4;
+  int d : 12;
+  int s : 16;
 };
 
 __host__ __device__ inline double coef_value(Coef c, const double* rho0) {
-  if (c.p == 0) return c.a;
-  double r = rho0[c.d];
-  switch (c.p) {
-    case 1: return c.a * r;
-    case -1: return c.a / r;
-    case -2: return c.a / (r * r);
-    default: return c.a;
+  double v = c.a;
+  if (c.p != 0) {
+    const double r = rho0[c.d];
+    switch (c.p) {
+      case 1: v *= r; break;
+      case -1: v /= r; break;
+      case -2: v /= r * r; break;
+      default: break;
+    }
   }
+  if (c.s > 0) v *= rho0[c.s];
+  return v;
 }
 
 __device__ inline double wave_sum(double v) {

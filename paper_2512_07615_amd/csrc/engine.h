@@ -2014,6 +2014,34 @@ class Engine {
 
   // ------------------------------------------------------------ dense I/O
   // Contract objects to dense scale-ordered arrays: out[i * N^3 + ...]
+  // <a, b> of two objects into out[0] (device, FP64), by the left
+  // environment (k_ip_half / k_ip_env); workspaces from the allocator.
+  void inner_pair(int a, int b, double* out) {
+    long ecap = 1, tcap = 1;
+    for (int k = 0; k < n; ++k) {
+      ecap = std::max(ecap, (long)pool[a].cap[k + 1] * pool[b].cap[k + 1]);
+      tcap = std::max(tcap, (long)pool[a].cap[k] * PHYS * pool[b].cap[k + 1]);
+    }
+    double* Ev = (double*)dalloc(8 * ecap);
+    double* Tm = (double*)dalloc(8 * tcap);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, Ev, 1.0, 1L);
+    for (int k = 0; k < n; ++k) {
+      const long th = (long)pool[a].cap[k] * PHYS * pool[b].cap[k + 1];
+      const long te = (long)pool[a].cap[k + 1] * pool[b].cap[k + 1];
+      hipLaunchKernelGGL(k_ip_half<T>, dim3(ceil_div(std::min(th, 2048L * 256), 256)), dim3(256),
+                         0, st, (const MpsDev<T>*)D(a), (const MpsDev<T>*)D(b), k,
+                         (const double*)Ev, Tm);
+      hipLaunchKernelGGL(k_ip_env<T>, dim3(ceil_div(std::min(te, 2048L * 256), 256)), dim3(256),
+                         0, st, (const MpsDev<T>*)D(a), (const MpsDev<T>*)D(b), k,
+                         (const double*)Tm, Ev);
+    }
+    hipLaunchKernelGGL(k_copy_plain<double>, dim3(1), dim3(64), 0, st, (const double*)Ev, out, 1L);
+    HIP_OK(hipGetLastError());
+    HIP_OK(hipStreamSynchronize(st));
+    free_alloc(Tm);
+    free_alloc(Ev);
+  }
+
   void to_dense(const std::vector<int>& src, T* out, T* work) {
     long N3 = 1L << (3 * n);
     for (size_t off = 0; off < src.size(); off += MAXB) {

@@ -61,6 +61,8 @@ struct Sim {
   virtual bool fatal_seen() const = 0;
   virtual void raise_flags(int nonfinite, int sweep_limit) = 0;
   virtual void rank_model(float* w, int load) = 0;
+  virtual void set_face_profile(int d, int face, const double* coef, double dt) = 0;
+  virtual void set_region(int d, const int* lo, const int* hi, double rho_ref) = 0;
 };
 
 // Copy MPS i of S into MPS i of D (same capacity profile), converting the
@@ -144,7 +146,66 @@ struct Domain {
   double n_fluid = 0.0;
   double mask_err = 0.0;
   double face_err = 0.0;
+  // region of interest of the pressure metric (Section 4.2)
+  int region = -1;
+  double region_cells = 0.0;
+  double region_rho = 1.0;
+  double region_err = 0.0;
 };
+
+// Time profile of a velocity face: the face velocity is scaled by
+// phi(t) = c0 + c1 (1 - e^(-c2 t)) + c3 t^c4 e^(-c5 t), t = steps taken x dt
+// (Section 4.1 inflows: a ramp and a pulse).
+struct FaceProf {
+  double c[6];
+  double dt;
+  int on;
+  int pad;
+};
+
+// Per-step face scales: entry fs + j (j = 6 d + face) of the scalar array
+// becomes phi(t) for a profiled face and 1 otherwise; entry cnt counts the
+// steps taken, read before it is advanced.  One workgroup.
+__global__ void k_face_time(const FaceProf* prof, double* sc, int fs, int cnt, int nf) {
+  const int j = threadIdx.x;
+  const double steps = sc[cnt];
+  if (j < nf) {
+    const FaceProf p = prof[j];
+    double v = 1.0;
+    if (p.on) {
+      const double t = steps * p.dt;
+      v = p.c[0] + p.c[1] * (1.0 - exp(-p.c[2] * t));
+      if (p.c[3] != 0.0) v += p.c[3] * pow(t, p.c[4]) * exp(-p.c[5] * t);
+    }
+    sc[fs + j] = v;
+  }
+  __syncthreads();
+  if (j == 0) sc[cnt] = steps + 1.0;
+}
+
+// Dense [x][y][z] indicator of the fluid cells of the box lo <= x < hi
+// (solid read from the scale-ordered mask field, > 1/2 = solid; NULL = no
+// solid), and its cell count added to *count.
+template <typename T>
+__global__ __launch_bounds__(256) void k_box_fluid(const T* mask_s, double* out, int n, int x0,
+                                                   int y0, int z0, int x1, int y1, int z1,
+                                                   double* count) {
+  __shared__ double red[4];
+  const long N3 = 1L << (3 * n);
+  const int N = 1 << n;
+  double c = 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
+       e += (long)gridDim.x * blockDim.x) {
+    const int x = (int)(e >> (2 * n)), y = (int)((e >> n) & (N - 1)), z = (int)(e & (N - 1));
+    const bool in = x >= x0 && x < x1 && y >= y0 && y < y1 && z >= z0 && z < z1;
+    const bool solid = mask_s && (double)mask_s[scale_index(x, y, z, n)] > 0.5;
+    const double v = (in && !solid) ? 1.0 : 0.0;
+    out[e] = v;
+    c += v;
+  }
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) atomicAdd(count, c);
+}
 
 // Obstacle geometry given as a coarse layout outer [L][L][L] (L = 2^l) and
 // the fine unit geometry inner [K][K][K] (K = 2^(n-l)) repeated in each of
@@ -184,6 +245,10 @@ struct SimT : Sim {
   double* rho0 = nullptr;   // device [D]
   double* nfl = nullptr;    // device [D]: fluid cell counts
   double* sbuf = nullptr;   // device sums of a step (rho_0 numerators, norms)
+  FaceProf* fprof = nullptr;     // device [6 D] velocity-face time profiles
+  std::vector<FaceProf> hprof;   // host copy
+  int fs_off() const { return D + 8; }
+  int cnt_off() const { return D + 8 + 6 * D; }
   int* cvec_dev = nullptr;
   double* w_dev = nullptr;
   long long steps = 0;
@@ -225,7 +290,14 @@ struct SimT : Sim {
     }
     if (c.rank_predictor) E.enable_rsvd(c.rank_oversample, c.seed);
     if (c.rank_predictor == 2) E.enable_mlp(c.seed);
-    rho0 = (double*)E.dalloc(8 * (D + 8));
+    // scalars of the step: rho_0 per domain, then the per-step face scales
+    // (6 per domain, Coef::s) and the count of steps taken
+    rho0 = (double*)E.dalloc(8 * (cnt_off() + 1));
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(256), 0, st, rho0 + fs_off(), 1.0, 6L * D);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, rho0 + cnt_off(), 0.0, 1L);
+    hprof.assign(6 * D, FaceProf{});
+    fprof = (FaceProf*)E.dalloc(sizeof(FaceProf) * 6 * D);
+    HIP_OK(hipMemcpy(fprof, hprof.data(), sizeof(FaceProf) * 6 * D, hipMemcpyHostToDevice));
     nfl = (double*)E.dalloc(8 * (D + 8));
     sbuf = (double*)E.dalloc(8 * (19 * D + 64));
     int cvec[57];
@@ -564,6 +636,8 @@ struct SimT : Sim {
   // ---------------------------------------------------------------- step
   void step_once() {
     hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, E.stats, 0.0, 1L);
+    hipLaunchKernelGGL(k_face_time, dim3(1), dim3(((6 * D + 63) / 64) * 64), 0, st,
+                       (const FaceProf*)fprof, rho0, fs_off(), cnt_off(), 6 * D);
     E.rs_call = 0;
     E.roundings = 0;
     E.products = 0;
@@ -730,7 +804,9 @@ struct SimT : Sim {
           const double* ub = dm.cfg.face_val[face];
           const double cu = c[0] * ub[0] + c[1] * ub[1] + c[2] * ub[2];
           bt.push_back({Coef{1.0, 0, F.d}, fo[t]});
-          bt.push_back({Coef{6.0 * kW(i) * cu, cu == 0.0 ? 0 : 1, F.d}, fp});
+          // u_b(t) = u_b phi(t): phi is the face's per-step scale
+          bt.push_back({Coef{6.0 * kW(i) * cu, cu == 0.0 ? 0 : 1, F.d, fs_off() + 6 * F.d + face},
+                        fp});
         } else {
           const double rb = dm.cfg.face_val[face][0];
           const double kk = 2.0 * kW(i) * rb;
@@ -1042,6 +1118,81 @@ struct SimT : Sim {
     o->flops = fl;
   }
 
+  void set_face_profile(int d, int face, const double* coef, double dt) override {
+    const mps_lbm_config& cfg = dom[d].cfg;
+    if (cfg.face_bc[face] != MPS_LBM_BC_VELOCITY)
+      throw Error(-1, "a time profile applies to a velocity face");
+    FaceProf p{};
+    for (int c = 0; c < 6; ++c) p.c[c] = coef ? coef[c] : 0.0;
+    p.dt = dt;
+    p.on = coef ? 1 : 0;
+    hprof[6 * d + face] = p;
+    HIP_OK(hipMemcpyAsync(fprof + 6 * d + face, &hprof[6 * d + face], sizeof(FaceProf),
+                          hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+  }
+
+  // Region of interest of the pressure metric (Section 4.2): the fluid
+  // cells of the box lo <= x < hi as an MPS, decomposed from that dense
+  // indicator like the obstacle mask (tol_mask, no cap, FP64 ranks); the
+  // solid cells are read back from the obstacle mask.
+  void set_region(int d, const int* lo, const int* hi, double rho_ref) override {
+    for (int a = 0; a < 3; ++a)
+      if (lo[a] < 0 || hi[a] > N || lo[a] >= hi[a]) throw Error(-1, "region box outside the grid");
+    Domain& dm = dom[d];
+    const mps_lbm_config& cfg = dm.cfg;
+    std::vector<void*> staged;
+    auto stage = [&](size_t bytes) {
+      void* p = E.dalloc(bytes);
+      staged.push_back(p);
+      return p;
+    };
+    try {
+      T* ms = nullptr;
+      if (dm.mask >= 0) {
+        ms = (T*)stage(sizeof(T) * N3);
+        T* work = (T*)stage(sizeof(T) * N3);
+        E.to_dense({dm.mask}, ms, work);
+      }
+      double* dd = (double*)stage(8 * N3);
+      T* W = (T*)stage(sizeof(T) * N3);
+      T* Wkeep = (T*)stage(sizeof(T) * N3);
+      double* cnt = (double*)stage(8);
+      hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, cnt, 0.0, 1L);
+      hipLaunchKernelGGL(k_box_fluid<T>, dim3(std::min(1024, dense_chunks(N3))), dim3(256), 0, st,
+                         (const T*)ms, dd, n, lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], cnt);
+      double cells = 0.0;
+      HIP_OK(hipMemcpyAsync(&cells, cnt, 8, hipMemcpyDeviceToHost, st));
+      HIP_OK(hipStreamSynchronize(st));
+      if (!(cells > 0.0)) throw Error(-1, "the region holds no fluid cell");
+      hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(N3)), dim3(256), 0, st,
+                         (const double*)dd, W, n, 1, 1);
+      hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(N3)), dim3(256), 0, st, (const T*)W,
+                         Wkeep, N3);
+      int cap[MAXN + 1];
+      for (int k = 0; k <= n; ++k) cap[k] = mask_cap(k);
+      const int obj = E.add_fixed(cap);
+      try {
+        const int chi_mask = cfg.chi_mask_max > 0 ? cfg.chi_mask_max : (1 << 30);
+        dense_to_mps(dd, W, 1, {obj}, chi_mask, cfg.tol_mask, cap);
+        dm.region_err = decomposition_error(obj, Wkeep);
+      } catch (...) {
+        E.drop_fixed(obj);
+        throw;
+      }
+      if (dm.region >= 0) E.drop_fixed(dm.region);
+      dm.region = obj;
+      dm.region_cells = cells;
+      dm.region_rho = rho_ref;
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      for (void* p : staged) E.free_alloc(p);
+      throw;
+    }
+    HIP_OK(hipStreamSynchronize(st));
+    for (void* p : staged) E.free_alloc(p);
+  }
+
   void observables(int d, mps_lbm_obs* o) override {
     memset(o, 0, sizeof(*o));
     const Domain& dm = dom[d];
@@ -1100,6 +1251,20 @@ struct SimT : Sim {
       HIP_OK(hipMemcpy(t, E.rw.tries, 8, hipMemcpyDeviceToHost));
       o->rs_attempted = t[0];
       o->rs_accepted = t[1];
+    }
+    if (dm.region >= 0) {
+      // Delta p / p_0 = <m_D, rho> / (rho_ref |D|) - 1 with
+      // <m_D, rho> = sum_i <m_D, f_i> (Section 4.2)
+      double ip = 0.0;
+      for (int i = 0; i < 19; ++i) {
+        E.inner_pair(dm.f[i], dm.region, sbuf);
+        double v = 0.0;
+        HIP_OK(hipMemcpy(&v, sbuf, 8, hipMemcpyDeviceToHost));
+        ip += v;
+      }
+      o->dp_p0 = ip / (dm.region_rho * dm.region_cells) - 1.0;
+      o->region_cells = dm.region_cells;
+      o->region_trunc_err = dm.region_err;
     }
   }
 };
@@ -1439,6 +1604,34 @@ int mps_lbm_rank_predictor_info(mps_lbm_t* h, mps_lbm_predictor_info* out) {
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
   return guarded([&]() -> int {
     h->sim->predictor_info(out);
+    return MPS_LBM_OK;
+  });
+}
+
+int mps_lbm_set_face_profile(mps_lbm_t* h, int domain, int face, const double* coef,
+                             double dt) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "no such domain");
+  if (face < 0 || face > 5) return fail(MPS_LBM_EINVAL, "face outside [0, 5]");
+  if (coef) {
+    for (int c = 0; c < 6; ++c)
+      if (!std::isfinite(coef[c])) return fail(MPS_LBM_EINVAL, "non-finite profile coefficient");
+    if (coef[4] < 0.0) return fail(MPS_LBM_EINVAL, "profile exponent c4 < 0");
+    if (!std::isfinite(dt) || dt < 0.0) return fail(MPS_LBM_EINVAL, "dt < 0");
+  }
+  return guarded([&]() -> int {
+    h->sim->set_face_profile(domain, face, coef, dt);
+    return MPS_LBM_OK;
+  });
+}
+
+int mps_lbm_set_region(mps_lbm_t* h, int domain, const int* lo, const int* hi, double rho_ref) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "no such domain");
+  if (!lo || !hi) return fail(MPS_LBM_EINVAL, "lo or hi is NULL");
+  if (!std::isfinite(rho_ref) || !(rho_ref > 0.0)) return fail(MPS_LBM_EINVAL, "rho_ref <= 0");
+  return guarded([&]() -> int {
+    h->sim->set_region(domain, lo, hi, rho_ref);
     return MPS_LBM_OK;
   });
 }

@@ -227,6 +227,42 @@ __global__ __launch_bounds__(256) void k_inner_ones(MpsList<T> src, double* out,
 
 // delta2[pr] = tol^2 * ||core_{n-1}||^2 / (n-1) (centre at the last site
 // after left orthogonalisation); norm2 kept for the discarded-weight ratio.
+// Inner product <A, B> = sum over all indices of A B, by the left
+// environment E_k = sum_s A_k[s]^T E_{k-1} B_k[s] (E_0 = 1), two launches a
+// site.  First half: T[a][s][b'] = sum_b E[a][b] B_k[b][s][b'].
+template <typename T>
+__global__ __launch_bounds__(256) void k_ip_half(const MpsDev<T>* A, const MpsDev<T>* B, int k,
+                                                 const double* E, double* Tm) {
+  const int ra = A->r[k], rb = B->r[k], rb1 = B->r[k + 1];
+  const long row = (long)PHYS * rb1;
+  const long tot = (long)ra * row;
+  const T* Bk = B->data + B->off[k];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const long a = e / row, sb = e % row;
+    double acc = 0.0;
+    for (int b = 0; b < rb; ++b) acc += E[a * rb + b] * (double)Bk[b * row + sb];
+    Tm[e] = acc;
+  }
+}
+
+// Second half: E_k[a'][b'] = sum_{a, s} A_k[a][s][a'] T[a][s][b'].
+template <typename T>
+__global__ __launch_bounds__(256) void k_ip_env(const MpsDev<T>* A, const MpsDev<T>* B, int k,
+                                                const double* Tm, double* E) {
+  const int ra = A->r[k], ra1 = A->r[k + 1], rb1 = B->r[k + 1];
+  const long tot = (long)ra1 * rb1;
+  const T* Ak = A->data + A->off[k];
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < tot;
+       e += (long)gridDim.x * blockDim.x) {
+    const long a1 = e / rb1, b1 = e % rb1;
+    double acc = 0.0;
+    for (long as = 0; as < (long)ra * PHYS; ++as)
+      acc += (double)Ak[as * ra1 + a1] * Tm[as * rb1 + b1];
+    E[e] = acc;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_round_threshold(MpsList<T> src, double tol,
                                                          double* delta2, double* norm2,

@@ -38,7 +38,8 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_mlp_gradient", "mps_lbm_autotune", "mps_lbm_set_allocator",
                    "mps_lbm_load_rank_model", "mps_lbm_get_rank_model",
                    "mps_lbm_debug_raise_flags", "mps_lbm_mlp_gradient_device",
-                   "mps_lbm_init_tensor_mask"])
+                   "mps_lbm_init_tensor_mask", "mps_lbm_set_face_profile",
+                   "mps_lbm_set_region"])
 
 
 class Config(C.Structure):
@@ -64,6 +65,9 @@ class Obs(C.Structure):
         ("rs_attempted", C.c_longlong), ("rs_accepted", C.c_longlong),
         ("jacobi_sweeps_wide", C.c_double), ("jacobi_cols_wide", C.c_double),
         ("face_trunc_err", C.c_double),
+        ("dp_p0", C.c_double),
+        ("region_cells", C.c_double),
+        ("region_trunc_err", C.c_double),
     ]
 
 
@@ -108,6 +112,11 @@ def load(path: str = LIB_PATH):
                                              C.POINTER(C.c_uint8), C.c_int,
                                              C.POINTER(C.c_uint8), P, C.POINTER(P)]
     lib.mps_lbm_init_tensor_mask.restype = C.c_int
+    lib.mps_lbm_set_face_profile.argtypes = [P, C.c_int, C.c_int, DP, C.c_double]
+    lib.mps_lbm_set_face_profile.restype = C.c_int
+    lib.mps_lbm_set_region.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                       C.c_double]
+    lib.mps_lbm_set_region.restype = C.c_int
     lib.mps_lbm_step.argtypes = [P, C.c_int]
     lib.mps_lbm_step.restype = C.c_int
     lib.mps_lbm_to_dense.argtypes = [P, C.c_int, DP, C.c_size_t]
@@ -220,6 +229,28 @@ def mps_lbm_init_tensor_mask(cfg: Config, solid_outer, solid_inner, rho=None, u=
         int(L).bit_length() - 1, inner.ctypes.data_as(C.POINTER(C.c_uint8)),
         C.c_void_p(hip_stream or 0), C.byref(h)))
     return h
+
+
+def mps_lbm_set_face_profile(h, face: int, coef=None, dt: float = 0.0, domain: int = 0):
+    """Time profile u_b(t) = u_b phi(t) of a velocity face; coef = (c0..c5)
+    of phi = c0 + c1 (1 - e^(-c2 t)) + c3 t^c4 e^(-c5 t), t = steps x dt;
+    None restores the constant face."""
+    c = None
+    if coef is not None:
+        if len(coef) != 6:
+            raise ValueError("coef needs six entries")
+        c = (C.c_double * 6)(*[float(v) for v in coef])
+    _check(load().mps_lbm_set_face_profile(h, int(domain), int(face), c, float(dt)))
+
+
+def mps_lbm_set_region(h, lo, hi, rho_ref: float, domain: int = 0):
+    """Region (fluid cells of the box lo <= x < hi) of the Delta p / p_0
+    observable, with p_0 = c_s^2 rho_ref."""
+    if len(lo) != 3 or len(hi) != 3:
+        raise ValueError("lo and hi need three entries")
+    a = (C.c_int * 3)(*[int(v) for v in lo])
+    b = (C.c_int * 3)(*[int(v) for v in hi])
+    _check(load().mps_lbm_set_region(h, int(domain), a, b, float(rho_ref)))
 
 
 def mps_lbm_train_rank_predictor(h, epochs: int, lr: float) -> float:
@@ -515,6 +546,14 @@ class Simulation:
             self.h = mps_lbm_init_from_field(self.cfg, rho=case.rho0_field(),
                                              u=case.u0_field(), solid=case.solid,
                                              hip_stream=hip_stream)
+        for face, (coef, dt) in (case.face_profile or {}).items():
+            mps_lbm_set_face_profile(self.h, face, coef, dt)
+
+    def set_face_profile(self, face, coef=None, dt=0.0):
+        mps_lbm_set_face_profile(self.h, face, coef, dt)
+
+    def set_region(self, lo, hi, rho_ref):
+        mps_lbm_set_region(self.h, lo, hi, rho_ref)
 
     def step(self, n=1):
         mps_lbm_step(self.h, n)

@@ -124,6 +124,21 @@ def test_tensor_mask_init_validates_its_parts_before_device_use():
         L.mps_lbm_init_tensor_mask(c, outer, np.zeros((8, 8, 8), np.uint8), rho=rho, u=u)
 
 
+def test_profile_and_region_entry_points_validate_without_gpu():
+    L = lib()
+    so = L.load()
+    coef = (C.c_double * 6)(0, 1, 1.5, 0, 0, 0)
+    lo = (C.c_int * 3)(0, 0, 0)
+    hi = (C.c_int * 3)(2, 2, 2)
+    assert so.mps_lbm_set_face_profile(None, 0, 0, coef, 0.1) == L.EINVAL
+    assert so.mps_lbm_set_face_profile(None, 0, 0, None, 0.0) == L.EINVAL
+    assert so.mps_lbm_set_region(None, 0, lo, hi, 1.0) == L.EINVAL
+    with pytest.raises(ValueError):
+        L.mps_lbm_set_face_profile(None, 0, (1, 2, 3), 0.1)
+    with pytest.raises(ValueError):
+        L.mps_lbm_set_region(None, (0, 0), (1, 1, 1), 1.0)
+
+
 def test_null_handle_calls_fail_cleanly():
     L = lib()
     so = L.load()
