@@ -24,7 +24,7 @@ from __future__ import annotations
 import numpy as np
 
 from .inflow import face_velocity
-from .lattice import C, W, OPP, Q, PI_PAIRS
+from .lattice import D3Q19, PI_PAIRS, get as get_lattice
 
 INV_EXACT = "exact"
 INV_TAYLOR2 = "taylor2"
@@ -62,18 +62,20 @@ def inverse_density(rho, rho0, mode=INV_TAYLOR2, iters=2, fluid=None):
 
 
 def moments(f):
+    """rho and j of populations of any of the velocity sets (by their count)."""
+    lat = get_lattice(f.shape[0])
     rho = f.sum(axis=0)
-    j = np.einsum("ia,ixyz->axyz", C.astype(np.float64), f)
+    j = np.einsum("ia,ixyz->axyz", lat.c.astype(np.float64), f)
     return rho, j
 
 
-def equilibrium(rho, jeq, Pi):
+def equilibrium(rho, jeq, Pi, lat=D3Q19):
     """j-form equilibrium; Pi is a dict {(a,b): field} with a <= b."""
     trPi = Pi[(0, 0)] + Pi[(1, 1)] + Pi[(2, 2)]
     S0 = rho - 1.5 * trPi
-    feq = np.empty((Q,) + rho.shape)
-    for i in range(Q):
-        c = C[i]
+    feq = np.empty((lat.q,) + rho.shape)
+    for i in range(lat.q):
+        c = lat.c[i]
         acc = S0.copy()
         for a in range(3):
             if c[a]:
@@ -82,7 +84,7 @@ def equilibrium(rho, jeq, Pi):
             coef = c[a] * c[b] * (1 if a == b else 2)
             if coef:
                 acc += 4.5 * coef * Pi[(a, b)]
-        feq[i] = W[i] * acc
+        feq[i] = lat.w[i] * acc
     return feq
 
 
@@ -92,6 +94,7 @@ class DenseLBM:
 
     def __init__(self, case, inv_mode=INV_TAYLOR2, inv_iters=2, shape=None):
         self.case = case
+        self.lat = get_lattice(int(case.lattice))
         self.tau = float(case.tau)
         self.g = np.array(case.g, dtype=np.float64)
         self.inv_mode = inv_mode
@@ -116,7 +119,7 @@ class DenseLBM:
         """f_i = (1 - m) f_eq,i(rho, u) with the exact velocity/Pi."""
         j = rho[None] * u
         Pi = {(a, b): rho * u[a] * u[b] for (a, b) in PI_PAIRS}
-        return self.fluid[None] * equilibrium(rho, j, Pi)
+        return self.fluid[None] * equilibrium(rho, j, Pi, self.lat)
 
     def collide(self, f):
         rho, j = moments(f)
@@ -125,7 +128,7 @@ class DenseLBM:
         jeq = j + self.tau * self.g[:, None, None, None] * rho[None]
         u = jeq * r[None]
         Pi = {(a, b): jeq[a] * u[b] for (a, b) in PI_PAIRS}
-        feq = equilibrium(rho, jeq, Pi)
+        feq = equilibrium(rho, jeq, Pi, self.lat)
         fpost = f + (feq - f) / self.tau
         return fpost, dict(rho=rho, j=j, jeq=jeq, u=u, rho0=rho0, r=r)
 
@@ -134,6 +137,7 @@ class DenseLBM:
         entering through the face (boundaries equation).  Returns a list of
         (i, face_index_tuple, values) to add after streaming."""
         case = self.case
+        C, W, OPP = self.lat.c, self.lat.w, self.lat.opp
         out = []
         for ax in range(3):
             if not self.axis_open[ax]:
@@ -149,7 +153,7 @@ class DenseLBM:
                 sl = tuple(sl)
                 entering = 1 if side == 0 else -1
                 fl = self.fluid[sl]
-                for i in range(Q):
+                for i in range(self.lat.q):
                     if C[i][ax] != entering:
                         continue
                     c = C[i].astype(np.float64)
@@ -172,6 +176,7 @@ class DenseLBM:
         f = self.f
         fpost, mac = self.collide(f)
         bterms = self.boundary_terms(fpost, mac)
+        C, OPP, Q = self.lat.c, self.lat.opp, self.lat.q
         fs = np.empty_like(fpost)
         for i in range(Q):
             fs[i] = shift_field(fpost[i], C[i], self.axis_open)

@@ -2,8 +2,8 @@
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
-Each of the 19 D3Q19 populations is an MPS over scale-ordered sites
-(Section 3.2).  One step is, in this order:
+Each of the Q populations (D3Q19, or the paper's D3Q15) is an MPS over
+scale-ordered sites (Section 3.2).  One step is, in this order:
 
 1. moments rho = sum_i f_i, j_a = sum_i c_ia f_i (macro equation), each a
    sum with rounding after every pairwise addition;
@@ -32,7 +32,7 @@ import numpy as np
 
 from . import mps as M
 from .inflow import face_velocity
-from .lattice import C, W, OPP, Q, PI_PAIRS
+from .lattice import PI_PAIRS, get as get_lattice
 from .metrics import pressure_drop
 
 INV_TAYLOR2 = "taylor2"
@@ -52,6 +52,7 @@ class MPSLBM:
     def __init__(self, case, inv_mode=INV_TAYLOR2, inv_iters=2, sweeps=2,
                  f_init=None):
         self.case = case
+        self.lat = get_lattice(int(case.lattice))
         self.n = case.n
         self.N = case.N
         self.chi = int(case.chi)
@@ -111,12 +112,15 @@ class MPSLBM:
                                                           case.tol_mask)
         if f_init is None:
             f_init = self.initial_dense(case)
-        self.f = [M.from_dense(f_init[i], n, self.chi, self.tol) for i in range(Q)]
+        self.f = [M.from_dense(f_init[i], n, self.chi, self.tol)
+                  for i in range(self.lat.q)]
         self.step_count = 0
         self.last = {}
 
     @staticmethod
     def initial_dense(case):
+        lat = get_lattice(int(case.lattice))
+        C, W, Q = lat.c, lat.w, lat.q
         """f_i = (1 - m_O) f_eq,i(rho, u) evaluated densely (the initial
         state is given as fields, then decomposed)."""
         rho = case.rho0_field().astype(np.float64)
@@ -185,6 +189,7 @@ class MPSLBM:
     # ---- the step ---------------------------------------------------------
     def collide(self):
         f = self.f
+        C, W, Q = self.lat.c, self.lat.w, self.lat.q
         rho = self.lin_sum([(1.0, f[i]) for i in range(Q)])
         j = [self.lin_sum([(float(C[i, a]), f[i]) for i in range(Q) if C[i, a] != 0])
              for a in range(3)]
@@ -218,6 +223,7 @@ class MPSLBM:
     def boundary_terms(self, fpost, mac):
         """Terms of m_B (.) b for every population entering an open face."""
         case = self.case
+        C, W, OPP, Q = self.lat.c, self.lat.w, self.lat.opp, self.lat.q
         out = {}
         for ax in range(3):
             if not self.axis_open[ax]:
@@ -256,6 +262,7 @@ class MPSLBM:
         return out
 
     def step(self):
+        C, OPP, Q = self.lat.c, self.lat.opp, self.lat.q
         fpost, mac = self.collide()
         bterms = self.boundary_terms(fpost, mac)
         fs = [fpost[0]] + [self.stream(fpost[i], C[i]) for i in range(1, Q)]
@@ -290,6 +297,7 @@ class MPSLBM:
 
     def momentum(self):
         s = [M.inner_ones(x) for x in self.f]
+        C, Q = self.lat.c, self.lat.q
         return np.array([sum(C[i, a] * s[i] for i in range(Q)) for a in range(3)],
                         dtype=np.float64)
 

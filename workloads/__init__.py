@@ -55,6 +55,7 @@ class Case:
     # face velocity scaled by c0 + c1 (1 - e^(-c2 t)) + c3 t^c4 e^(-c5 t)
     # with t = (steps taken) dt
     face_profile: Optional[dict] = None
+    lattice: int = 19                        # 19 (D3Q19) or 15 (D3Q15)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -269,6 +270,38 @@ def case_pinfin(n: int = 7, l: int = 3, chi: int = 64, tau: float = 0.56,
                 face_val=((u_in, 0, 0), (1.0, 0, 0)) + ((0, 0, 0),) * 4,
                 steps=steps, precision=precision, mask_parts=(outer, inner),
                 meta={"seed": seed, "solid_fraction": float(solid.mean()), "l": l})
+
+
+def tgv_state(n: int, u_lat: float = 0.1) -> Tuple[np.ndarray, np.ndarray]:
+    """3D Taylor-Green vortex initial state of Section 4.1 in lattice units
+    on the 2 pi periodic cube (x_i = 2 pi i / N): u = -U sin x cos y cos z,
+    v = U cos x sin y cos z, w = 0 and the density as printed there,
+    rho = 1 + (cos 2x + cos 2y) cos 2z / (16 du^2).  U = u_lat = Ma c_s is the
+    lattice velocity of u_0 = 1 (Ma = 0.1 / c_s gives 0.1) and du = 1 / U
+    the velocity conversion factor."""
+    N = 1 << n
+    x = 2.0 * np.pi * np.arange(N) / N
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    u = np.stack([-u_lat * np.sin(X) * np.cos(Y) * np.cos(Z),
+                  u_lat * np.cos(X) * np.sin(Y) * np.cos(Z),
+                  np.zeros_like(X)])
+    rho = 1.0 + (u_lat ** 2 / 16.0) * (np.cos(2 * X) + np.cos(2 * Y)) * np.cos(2 * Z)
+    return rho, u
+
+
+def case_tgv(n: int = 5, chi: int = 32, re: float = 800.0, u_lat: float = 0.1,
+             lattice: int = 15, tol: float = 1e-8, steps: int = 100,
+             precision: str = "fp32") -> Case:
+    """Taylor-Green vortex (Section 4.1): periodic cube, Re = u_0 L / (2 pi nu)
+    = U N / (2 pi nu) in lattice units, so nu = U N / (2 pi Re) and
+    tau = 3 nu + 1/2; D3Q15 as in the paper by default."""
+    N = 1 << n
+    nu = u_lat * N / (2.0 * np.pi * re)
+    rho, u = tgv_state(n, u_lat)
+    return Case(name=f"tgv{N}", n=n, tau=3.0 * nu + 0.5, chi=chi, tol=tol,
+                rho_init=rho, u_init=u, steps=steps, precision=precision,
+                lattice=lattice, meta={"re": re, "nu": nu, "u_lat": u_lat,
+                                       "steps_per_T0": 2.0 * np.pi * N / (2.0 * np.pi * u_lat)})
 
 
 def random_flow_state(n: int, seed: int, amp: float = 0.02,
