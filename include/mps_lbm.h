@@ -2,8 +2,9 @@
  * mps_lbm.h - C ABI of the MI355X (gfx950) matrix-product-state lattice
  * Boltzmann library.
  *
- * The library advances a D3Q19 BGK lattice Boltzmann simulation whose 19
- * particle distribution functions are each held as a matrix product state
+ * The library advances a D3Q19 or D3Q15 BGK lattice Boltzmann simulation
+ * whose Q = 19 or 15 particle distribution functions are each held as a
+ * matrix product state
  * (MPS) over scale-ordered grid bits (paper: "Tensor Network Lattice
  * Boltzmann Method for Data-Compressed Fluid Simulations", Sections 2-3).
  * All state lives in device memory owned by the handle; every computation
@@ -12,9 +13,11 @@
  * Conventions for every entry point:
  *  - Dense fields are C-order FP64 arrays indexed [x][y][z] (x slowest),
  *    side N = 2^n; vector fields are [3][N][N][N]; population arrays are
- *    [19][N][N][N] in the D3Q19 order: rest, +x,-x, +y,-y, +z,-z, then the
+ *    [Q][N][N][N].  D3Q19 order: rest, +x,-x, +y,-y, +z,-z, then the
  *    twelve edges as opposite pairs (+x+y,-x-y), (+x-y,-x+y), (+x+z,-x-z),
- *    (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z).
+ *    (+x-z,-x+z), (+y+z,-y-z), (+y-z,-y+z).  D3Q15 order: rest, +x,-x,
+ *    +y,-y, +z,-z, then the eight corners as opposite pairs (+++,---),
+ *    (++-,--+), (+-+,-+-), (-++,+--).
  *  - Host buffers are owned by the caller; the library copies inputs during
  *    the call and writes only into the output buffer it is given.
  *  - Return value 0 is success; negative values are the MPS_LBM_E* codes
@@ -40,7 +43,9 @@ extern "C" {
 #define MPS_LBM_ENUMERIC (-4)     /* NaN/Inf or SVD non-convergence       */
 #define MPS_LBM_EUNSUPPORTED (-5) /* valid but not implemented            */
 
-#define MPS_LBM_D3Q19 19
+#define MPS_LBM_D3Q19 19 /* rest, 6 axis, 12 edge velocities (1/3, 1/18, 1/36) */
+#define MPS_LBM_D3Q15 15 /* rest, 6 axis, 8 corner velocities (2/9, 1/9, 1/72): the
+                            set of the paper's 3D runs (Section 4.1) */
 
 /* arithmetic of the step (storage and contractions); the R-factor SVDs,
    rank selection and 1/rho coefficients are FP64 under every policy, and
@@ -71,7 +76,7 @@ extern "C" {
 #define MPS_LBM_BC_PRESSURE 2 /* anti-bounce-back with density rho_b, u_b = local u */
 
 /* what mps_lbm_to_dense writes */
-#define MPS_LBM_POPS 0 /* [19][N][N][N] populations                       */
+#define MPS_LBM_POPS 0 /* [Q][N][N][N] populations                        */
 #define MPS_LBM_RHO 1  /* [N][N][N]     rho = sum_i f_i                     */
 #define MPS_LBM_J 2    /* [3][N][N][N]  j = sum_i c_i f_i                   */
 #define MPS_LBM_VEL 3  /* [3][N][N][N]  u = j / rho (0 where rho = 0)       */
@@ -82,7 +87,7 @@ typedef struct mps_lbm mps_lbm_t; /* opaque handle; owns all device state */
 
 typedef struct {
   int n;            /* N = 2^n cells per axis, 2 <= n <= MPS_LBM_MAX_SITES */
-  int lattice;      /* MPS_LBM_D3Q19                                      */
+  int lattice;      /* MPS_LBM_D3Q19 | MPS_LBM_D3Q15                      */
   int chi_max;      /* bond dimension cap of every population MPS, >= 1    */
   int chi_mask_max; /* rank cap of the obstacle-mask MPS; <= 0 means no cap:
                        the mask is then decomposed to tol_mask, i.e. to
@@ -116,10 +121,11 @@ typedef struct {
   double momentum[3];      /* sum_i c_i <1, f_i>                            */
   double rho0;             /* mean fluid density used by the last step      */
   double n_fluid;          /* N^3 - <1, m_O>                                */
-  int max_bond;            /* largest bond over the 19 populations          */
-  int bonds[19][MPS_LBM_MAX_SITES]; /* bond dims r_1..r_{n-1} per population */
+  int max_bond;            /* largest bond over the Q populations           */
+  int bonds[19][MPS_LBM_MAX_SITES]; /* bond dims r_1..r_{n-1} per population
+                                       (rows Q..18 zero under D3Q15)      */
   double nvps;             /* sum over populations of the core entries in use */
-  double compression;      /* 19 N^3 / nvps                                 */
+  double compression;      /* Q N^3 / nvps                                  */
   double max_discarded;    /* largest relative discarded weight of a rounding
                               in the last step                              */
   int mask_bond;           /* largest bond of the obstacle-mask MPS          */
@@ -169,7 +175,7 @@ void mps_lbm_default_config(mps_lbm_config* cfg);
  * Create a simulation.  Initial populations are the equilibrium
  * f_i = (1 - m_O) w_i rho (1 + 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u)
  * of the given rho [N][N][N] and u [3][N][N][N] (equilibrium equation),
- * or, when f is non-NULL, the given populations [19][N][N][N] (rho and u
+ * or, when f is non-NULL, the given populations [Q][N][N][N] (rho and u
  * are then ignored and may be NULL).  solid [N][N][N] (1 = solid) defines
  * the obstacle mask m_O (Section 3.2.1, objects equation); NULL = none.
  * Each field is decomposed into an MPS by successive truncated SVDs
@@ -274,6 +280,20 @@ int mps_lbm_debug_raise_flags(mps_lbm_t* h, int nonfinite, int sweep_limit);
  */
 int mps_lbm_to_dense(mps_lbm_t* h, int what, double* out, size_t out_len);
 
+/*
+ * Total kinetic energy of domain `domain` (Section 4.2, with the density
+ * normalised so that the total mass is 1 and V_c = (L/N)^3):
+ *   e_kin = (1 / (2 N^3)) sum_x |u_x|^2,  u = j / rho (0 where rho = 0),
+ * in lattice units (multiply by the squared velocity conversion factor for
+ * physical units), from a dense contraction of the state on the device
+ * (Q N^3 elements of the working type, twice, for the call).  The paper's
+ * dissipation -dE_kin/dt is the caller's second-order finite difference of
+ * successive values.  Synchronises the stream.
+ * Errors: EINVAL (NULL handle or e_kin, domain out of range), ENUMERIC,
+ * ENOMEM, EHIP.
+ */
+int mps_lbm_kinetic_energy(mps_lbm_t* h, int domain, double* e_kin);
+
 /* Scalar observables (synchronises the stream). */
 int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
 
@@ -315,12 +335,12 @@ int mps_lbm_domains(const mps_lbm_t* h);
 int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, size_t out_len);
 int mps_lbm_observables_domain(mps_lbm_t* h, int domain, mps_lbm_obs* out);
 
-/* mps_lbm_get_mps: index of the obstacle-mask MPS (0..18 are populations) */
+/* mps_lbm_get_mps: index of the obstacle-mask MPS (0..Q-1 are populations) */
 #define MPS_LBM_MPS_MASK 19
 
 /*
  * Copy one MPS of the state to the host (synchronises the stream).
- * which = 0..18 selects population i (D3Q19 order above), MPS_LBM_MPS_MASK
+ * which = 0..Q-1 selects population i (order above), MPS_LBM_MPS_MASK
  * the obstacle mask m_O (Section 3.2.1, objects equation).  bonds receives
  * n + 1 ints: r_0 = 1, r_1, ..., r_n = 1.  When out is non-NULL it receives
  * the cores one after another, core k (k = 0..n-1) as a C-order FP64 array

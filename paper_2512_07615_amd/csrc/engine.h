@@ -21,13 +21,36 @@
 
 namespace mpslbm {
 
-// D3Q19 velocity set (rest, 6 axis, 12 edge velocities as opposite pairs)
-static const int kC[19][3] = {
-    {0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0}, {0, 0, 1},   {0, 0, -1},
-    {1, 1, 0},  {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1},  {-1, 0, -1}, {1, 0, -1},
-    {-1, 0, 1}, {0, 1, 1},   {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
-static const int kOpp[19] = {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17};
-static inline double kW(int i) { return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0); }
+// Velocity sets, opposite velocities stored as neighbours (opp(i) = i +- 1).
+// D3Q19: rest (1/3), 6 axis (1/18), 12 edge velocities (1/36).  D3Q15, the
+// set of the paper's 3D runs (Section 4.1): rest (2/9), 6 axis (1/9), 8
+// corner velocities (1/72).  Both have c_s^2 = 1/3 and the same
+// second-order equilibrium.
+constexpr int QMAX = 19;
+struct LatticeTab {
+  int q;
+  int c[QMAX][3];
+  int opp[QMAX];
+  double w[QMAX];
+};
+static const LatticeTab kD3Q19 = {
+    19,
+    {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+     {1, 1, 0}, {-1, -1, 0}, {1, -1, 0}, {-1, 1, 0}, {1, 0, 1}, {-1, 0, -1}, {1, 0, -1},
+     {-1, 0, 1}, {0, 1, 1}, {0, -1, -1}, {0, 1, -1}, {0, -1, 1}},
+    {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13, 16, 15, 18, 17},
+    {1.0 / 3.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0, 1.0 / 18.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0,
+     1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0, 1.0 / 36.0}};
+static const LatticeTab kD3Q15 = {
+    15,
+    {{0, 0, 0}, {1, 0, 0}, {-1, 0, 0}, {0, 1, 0}, {0, -1, 0}, {0, 0, 1}, {0, 0, -1},
+     {1, 1, 1}, {-1, -1, -1}, {1, 1, -1}, {-1, -1, 1}, {1, -1, 1}, {-1, 1, -1},
+     {-1, 1, 1}, {1, -1, -1}},
+    {0, 2, 1, 4, 3, 6, 5, 8, 7, 10, 9, 12, 11, 14, 13},
+    {2.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0, 1.0 / 9.0,
+     1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0, 1.0 / 72.0,
+     1.0 / 72.0}};
 
 template <typename T>
 struct Mps {
@@ -469,11 +492,12 @@ __global__ void k_copy_plain(const T* src, T* dst, long count) {
 }
 
 template <typename T>
-__global__ void k_moments_dense(const T* f, double* out, long N3, int what, const int* cvec) {
+__global__ void k_moments_dense(const T* f, double* out, long N3, int what, const int* cvec,
+                                int q) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
        e += (long)gridDim.x * blockDim.x) {
     double rho = 0, jx = 0, jy = 0, jz = 0;
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < q; ++i) {
       double v = (double)f[i * N3 + e];
       rho += v;
       jx += cvec[3 * i] * v;
@@ -490,6 +514,29 @@ __global__ void k_moments_dense(const T* f, double* out, long N3, int what, cons
       out[2 * N3 + e] = jz * s;
     }
   }
+}
+
+// sum over cells of |j / rho|^2 (0 where rho = 0) of the dense
+// populations, added into *out
+template <typename T>
+__global__ __launch_bounds__(256) void k_u2_sum(const T* f, long N3, const int* cvec, int q,
+                                                double* out) {
+  __shared__ double red[4];
+  double acc = 0.0;
+  for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
+       e += (long)gridDim.x * blockDim.x) {
+    double rho = 0, jx = 0, jy = 0, jz = 0;
+    for (int i = 0; i < q; ++i) {
+      const double v = (double)f[i * N3 + e];
+      rho += v;
+      jx += cvec[3 * i] * v;
+      jy += cvec[3 * i + 1] * v;
+      jz += cvec[3 * i + 2] * v;
+    }
+    if (rho != 0.0) acc += (jx * jx + jy * jy + jz * jz) / (rho * rho);
+  }
+  acc = block_sum(acc, red);
+  if (threadIdx.x == 0) atomicAdd(out, acc);
 }
 
 // fill kernel (used instead of memset nodes in code that may be captured)
@@ -1919,7 +1966,7 @@ class Engine {
   // axes in x, y, z order, each shift followed by rounding.  Level L of the
   // batch holds the L-th shift of every item, so each item sees the same
   // sequence of operations as in an axis-by-axis schedule, in as many levels
-  // as an item has nonzero components (two for D3Q19).  The pair sums, if
+  // as an item has nonzero components (two for D3Q19, three for D3Q15).  The pair sums, if
   // any, are assembled and rounded together with the first level; their
   // results go to *pair_out.  Returns fresh objects.
   std::vector<int> stream(const std::vector<int>& src, const std::vector<const int*>& cvec,

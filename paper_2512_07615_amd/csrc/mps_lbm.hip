@@ -1,7 +1,7 @@
 // C ABI and step schedule of the MI355X MPS lattice Boltzmann library.
 //
-// One D3Q19 BGK step on MPS populations (Section 3.2 of the paper), in this
-// order:
+// One BGK step on the MPS populations of a D3Q19 or D3Q15 velocity set
+// (Section 3.2 of the paper), in this order:
 //  1. rho = sum_i f_i and j_a = sum_i c_ia f_i (sums, rounded pairwise);
 //  2. rho_0 = <1, rho> / N_fluid;
 //  3. r ~ 1/rho: Taylor-2 about rho_0, r = (1/rho_0)(1 - e + e (.) e) with
@@ -16,7 +16,8 @@
 // rounded after each addition; the CPU oracle follows the same schedule.
 // Roundings that do not depend on each other share one batch: the j_eq sums
 // run with the first sums of step 3, each population's streaming shifts are
-// batched by their order (two levels for D3Q19), and the first pair of the
+// batched by their order (two levels for D3Q19 edges, three for D3Q15
+// corners), and the first pair of the
 // obstacle sum runs with the first shift level of the reflected part.  This
 // changes which launch carries an operation, never the operations applied to
 // one MPS or their order.
@@ -53,6 +54,8 @@ struct Sim {
   virtual void kstats(mps_lbm_kstats* o) = 0;
   virtual int get_mps(int d, int which, double* out, size_t out_len, int* bonds) = 0;
   virtual long cells() const = 0;
+  virtual int velocities() const = 0;
+  virtual double kinetic_energy(int d) = 0;
   virtual void capture() = 0;
   virtual float train_predictor(int epochs, float lr) = 0;
   virtual int autotune() = 0;
@@ -239,6 +242,8 @@ struct SimT : Sim {
   int one64 = -1;
   hipStream_t st;
   int n, N, D;
+  const LatticeTab* lat = &kD3Q19;  // velocity set of every domain
+  int Q = 19;
   long N3;
   std::vector<Domain> dom;
   int one = -1;
@@ -262,6 +267,8 @@ struct SimT : Sim {
     n = c.n;
     N = 1 << n;
     N3 = 1L << (3 * n);
+    lat = c.lattice == MPS_LBM_D3Q15 ? &kD3Q15 : &kD3Q19;
+    Q = lat->q;
     dom.resize(D);
     for (int d = 0; d < D; ++d) {
       dom[d].cfg = cfgs[d];
@@ -269,7 +276,7 @@ struct SimT : Sim {
     }
     E.sweeps = c.sweeps;
     E.bf16_products = c.precision == MPS_LBM_BF16 ? 1 : c.precision == MPS_LBM_BF16X3 ? 2 : 0;
-    E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, 19 * D));
+    E.setup(n, c.chi_max, c.tol, s, 96 + 160 * D, std::min(MAXB, Q * D));
     if (sizeof(T) == 4) {
       // FP64 island of the reduced-precision policies: the inverse density
       // (its sums and products) runs in an FP64 engine on the same stream
@@ -300,11 +307,11 @@ struct SimT : Sim {
     HIP_OK(hipMemcpy(fprof, hprof.data(), sizeof(FaceProf) * 6 * D, hipMemcpyHostToDevice));
     nfl = (double*)E.dalloc(8 * (D + 8));
     sbuf = (double*)E.dalloc(8 * (19 * D + 64));
-    int cvec[57];
-    double w[19];
-    for (int i = 0; i < 19; ++i) {
-      for (int a = 0; a < 3; ++a) cvec[3 * i + a] = kC[i][a];
-      w[i] = kW(i);
+    int cvec[3 * QMAX];
+    double w[QMAX];
+    for (int i = 0; i < Q; ++i) {
+      for (int a = 0; a < 3; ++a) cvec[3 * i + a] = lat->c[i][a];
+      w[i] = lat->w[i];
     }
     cvec_dev = (int*)E.dalloc(sizeof(cvec));
     w_dev = (double*)E.dalloc(sizeof(w));
@@ -315,6 +322,7 @@ struct SimT : Sim {
   }
 
   int domains() const override { return D; }
+  int velocities() const override { return Q; }
   long cells() const override { return N3; }
 
   int dense_chunks(long count) const {
@@ -449,8 +457,8 @@ struct SimT : Sim {
       staged.push_back(p);
       return p;
     };
-    double* dd = (double*)stage(8 * N3 * 19);
-    T* W = (T*)stage(sizeof(T) * N3 * 19);
+    double* dd = (double*)stage(8 * N3 * Q);
+    T* W = (T*)stage(sizeof(T) * N3 * Q);
     uint8_t* dsolid = nullptr;
     if (solid) {
       dsolid = (uint8_t*)stage(N3);
@@ -523,7 +531,7 @@ struct SimT : Sim {
     }
     // initial populations
     if (fin) {
-      HIP_OK(hipMemcpy(dd, fin, 8 * N3 * 19, hipMemcpyHostToDevice));
+      HIP_OK(hipMemcpy(dd, fin, 8 * N3 * Q, hipMemcpyHostToDevice));
     } else {
       double* drho = (double*)stage(8 * N3);
       double* du = (double*)stage(8 * N3 * 3);
@@ -531,13 +539,13 @@ struct SimT : Sim {
       HIP_OK(hipMemcpy(du, u, 8 * N3 * 3, hipMemcpyHostToDevice));
       hipLaunchKernelGGL(k_feq_dense, dim3(dense_chunks(N3)), dim3(256), 0, st,
                          (const double*)drho, (const double*)du, (const uint8_t*)dsolid, dd, N3,
-                         (const int*)cvec_dev, (const double*)w_dev);
+                         (const int*)cvec_dev, (const double*)w_dev, Q);
     }
-    hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(19 * N3)), dim3(256), 0,
-                       st, (const double*)dd, W, n, 19, 1);
-    std::vector<int> objs(19);
-    for (int i = 0; i < 19; ++i) objs[i] = dm.f[i] = E.acquire();
-    dense_to_mps(dd, W, 19, objs, cfg.chi_max, cfg.tol);
+    hipLaunchKernelGGL((k_scale_permute<double, T>), dim3(dense_chunks(Q * N3)), dim3(256), 0,
+                       st, (const double*)dd, W, n, Q, 1);
+    std::vector<int> objs(Q);
+    for (int i = 0; i < Q; ++i) objs[i] = dm.f[i] = E.acquire();
+    dense_to_mps(dd, W, Q, objs, cfg.chi_max, cfg.tol);
     HIP_OK(hipStreamSynchronize(st));
     for (void* p : staged) E.free_alloc(p);
   }
@@ -645,10 +653,10 @@ struct SimT : Sim {
     // 1. moments rho, j_a (4 sums per domain)
     std::vector<std::vector<Term>> S(4 * D);
     for (int d = 0; d < D; ++d) {
-      for (int i = 0; i < 19; ++i) S[4 * d].push_back({Coef{1.0, 0, d}, dom[d].f[i]});
+      for (int i = 0; i < Q; ++i) S[4 * d].push_back({Coef{1.0, 0, d}, dom[d].f[i]});
       for (int a = 0; a < 3; ++a)
-        for (int i = 0; i < 19; ++i)
-          if (kC[i][a]) S[4 * d + 1 + a].push_back({Coef{(double)kC[i][a], 0, d}, dom[d].f[i]});
+        for (int i = 0; i < Q; ++i)
+          if (lat->c[i][a]) S[4 * d + 1 + a].push_back({Coef{(double)lat->c[i][a], 0, d}, dom[d].f[i]});
     }
     std::vector<int> mom = E.sums(S, rho0);
     std::vector<int> rho(D), j(3 * D);
@@ -713,26 +721,26 @@ struct SimT : Sim {
                {Coef{-1.5, 0, d}, Pi[6 * d + 1]}, {Coef{-1.5, 0, d}, Pi[6 * d + 2]}};
     std::vector<int> S0 = E.sums(SS, rho0);
     // 5. BGK relaxation
-    std::vector<std::vector<Term>> SB(19 * D);
+    std::vector<std::vector<Term>> SB(Q * D);
     for (int d = 0; d < D; ++d) {
       const double om = 1.0 / dom[d].cfg.tau;
-      for (int i = 0; i < 19; ++i) {
-        const double wi = kW(i);
-        std::vector<Term>& t = SB[19 * d + i];
+      for (int i = 0; i < Q; ++i) {
+        const double wi = lat->w[i];
+        std::vector<Term>& t = SB[Q * d + i];
         t.push_back({Coef{1.0 - om, 0, d}, dom[d].f[i]});
         t.push_back({Coef{om * wi, 0, d}, S0[d]});
         for (int a = 0; a < 3; ++a)
-          if (kC[i][a]) t.push_back({Coef{3.0 * om * wi * kC[i][a], 0, d}, jeq[3 * d + a]});
+          if (lat->c[i][a]) t.push_back({Coef{3.0 * om * wi * lat->c[i][a], 0, d}, jeq[3 * d + a]});
         for (int q = 0; q < 6; ++q) {
           const int a = PI[q][0], b = PI[q][1];
-          const int coef = kC[i][a] * kC[i][b] * (a == b ? 1 : 2);
+          const int coef = lat->c[i][a] * lat->c[i][b] * (a == b ? 1 : 2);
           if (coef) t.push_back({Coef{4.5 * om * wi * coef, 0, d}, Pi[6 * d + q]});
         }
       }
     }
-    std::vector<int> fpost = E.sums(SB, rho0);  // fpost[19 d + i]
+    std::vector<int> fpost = E.sums(SB, rho0);  // fpost[Q d + i]
     for (int d = 0; d < D; ++d) {
-      for (int i = 0; i < 19; ++i) E.release(dom[d].f[i]);
+      for (int i = 0; i < Q; ++i) E.release(dom[d].f[i]);
       E.release(rho[d]);
       E.release(r[d]);
       E.release(S0[d]);
@@ -740,7 +748,7 @@ struct SimT : Sim {
       for (int a = 0; a < 3; ++a) E.release(jeq[3 * d + a]);
     }
     // 7a. open-face boundary terms (post-collision f_ihat and u)
-    std::vector<std::vector<Term>> bterms(19 * D);
+    std::vector<std::vector<Term>> bterms(Q * D);
     std::vector<int> btemp;
     {
       struct Face { int d, ax, side, typ, idx; };
@@ -778,12 +786,12 @@ struct SimT : Sim {
       for (size_t q = 0; q < faces.size(); ++q) {
         const Face& F = faces[q];
         const int entering = F.side == 0 ? 1 : -1;
-        for (int i = 0; i < 19; ++i)
-          if (kC[i][F.ax] == entering) {
-            src.push_back(fpost[19 * F.d + kOpp[i]]);
+        for (int i = 0; i < Q; ++i)
+          if (lat->c[i][F.ax] == entering) {
+            src.push_back(fpost[Q * F.d + lat->opp[i]]);
             axs.push_back(F.ax);
             ids.push_back(F.idx);
-            fent.push_back((int)q * 19 + i);
+            fent.push_back((int)q * Q + i);
           }
       }
       std::vector<int> fo = src.empty() ? std::vector<int>() : E.slice(src, axs, ids);
@@ -793,23 +801,23 @@ struct SimT : Sim {
       for (size_t q = 0; q < faces.size(); ++q)
         if (faces[q].typ == MPS_LBM_BC_PRESSURE) pidx[q] = pface++;
       for (size_t t = 0; t < fent.size(); ++t) {
-        const int q = fent[t] / 19, i = fent[t] % 19;
+        const int q = fent[t] / Q, i = fent[t] % Q;
         const Face& F = faces[q];
         const Domain& dm = dom[F.d];
         const int face = 2 * F.ax + F.side;
         const int fp = dm.fplane[face];
-        const double c[3] = {(double)kC[i][0], (double)kC[i][1], (double)kC[i][2]};
-        std::vector<Term>& bt = bterms[19 * F.d + i];
+        const double c[3] = {(double)lat->c[i][0], (double)lat->c[i][1], (double)lat->c[i][2]};
+        std::vector<Term>& bt = bterms[Q * F.d + i];
         if (F.typ == MPS_LBM_BC_VELOCITY) {
           const double* ub = dm.cfg.face_val[face];
           const double cu = c[0] * ub[0] + c[1] * ub[1] + c[2] * ub[2];
           bt.push_back({Coef{1.0, 0, F.d}, fo[t]});
           // u_b(t) = u_b phi(t): phi is the face's per-step scale
-          bt.push_back({Coef{6.0 * kW(i) * cu, cu == 0.0 ? 0 : 1, F.d, fs_off() + 6 * F.d + face},
+          bt.push_back({Coef{6.0 * lat->w[i] * cu, cu == 0.0 ? 0 : 1, F.d, fs_off() + 6 * F.d + face},
                         fp});
         } else {
           const double rb = dm.cfg.face_val[face][0];
-          const double kk = 2.0 * kW(i) * rb;
+          const double kk = 2.0 * lat->w[i] * rb;
           bt.push_back({Coef{-1.0, 0, F.d}, fo[t]});
           bt.push_back({Coef{kk, 0, F.d}, fp});
           for (int p = 0; p < 6; ++p) {
@@ -824,24 +832,24 @@ struct SimT : Sim {
     std::vector<int> src;
     std::vector<const int*> cv, ao;
     for (int d = 0; d < D; ++d)
-      for (int i = 1; i < 19; ++i) {
-        src.push_back(fpost[19 * d + i]);
-        cv.push_back(kC[i]);
+      for (int i = 1; i < Q; ++i) {
+        src.push_back(fpost[Q * d + i]);
+        cv.push_back(lat->c[i]);
         ao.push_back(dom[d].cfg.axis_open);
       }
     std::vector<int> fs1 = E.stream(src, cv, ao);
-    std::vector<int> fs(19 * D);
+    std::vector<int> fs(Q * D);
     for (int d = 0; d < D; ++d) {
-      fs[19 * d] = fpost[19 * d];
-      for (int i = 1; i < 19; ++i) fs[19 * d + i] = fs1[18 * d + i - 1];
+      fs[Q * d] = fpost[Q * d];
+      for (int i = 1; i < Q; ++i) fs[Q * d + i] = fs1[(Q - 1) * d + i - 1];
     }
     // 7b. add the boundary terms
     {
       std::vector<std::vector<Term>> SBC;
       std::vector<int> which;
-      for (int q = 0; q < 19 * D; ++q) {
+      for (int q = 0; q < Q * D; ++q) {
         if (bterms[q].empty()) continue;
-        std::vector<Term> t{{Coef{1.0, 0, q / 19}, fs[q]}};
+        std::vector<Term> t{{Coef{1.0, 0, q / Q}, fs[q]}};
         t.insert(t.end(), bterms[q].begin(), bterms[q].end());
         SBC.push_back(t);
         which.push_back(q);
@@ -856,7 +864,7 @@ struct SimT : Sim {
     }
     for (int o : btemp) E.release(o);
     for (int d = 0; d < D; ++d) {
-      for (int i = 1; i < 19; ++i) E.release(fpost[19 * d + i]);
+      for (int i = 1; i < Q; ++i) E.release(fpost[Q * d + i]);
       for (int a = 0; a < 3; ++a) E.release(u[3 * d + a]);
     }
     // 8. obstacle bounce-back
@@ -867,15 +875,15 @@ struct SimT : Sim {
       if (!dd.empty()) {
         std::vector<std::pair<int, int>> pm;
         for (int d : dd)
-          for (int i = 1; i < 19; ++i) pm.push_back({fs[19 * d + i], dom[d].mask});
+          for (int i = 1; i < Q; ++i) pm.push_back({fs[Q * d + i], dom[d].mask});
         // candidate = the population (its bonds are those the result keeps)
         std::vector<int> g1 = E.prods(pm, mcp);  // g1[18 k + i - 1]
         std::vector<int> hs;
         std::vector<const int*> hc, ha;
         for (size_t k = 0; k < dd.size(); ++k)
-          for (int i = 1; i < 19; ++i) {
-            hs.push_back(g1[18 * k + kOpp[i] - 1]);
-            hc.push_back(kC[i]);
+          for (int i = 1; i < Q; ++i) {
+            hs.push_back(g1[(Q - 1) * k + lat->opp[i] - 1]);
+            hc.push_back(lat->c[i]);
             ha.push_back(dom[dd[k]].cfg.axis_open);
           }
         // the sum f_i - g1_i + h_i is a pairwise tree: its first pair
@@ -883,33 +891,33 @@ struct SimT : Sim {
         std::vector<PairSum> pre;
         for (size_t k = 0; k < dd.size(); ++k) {
           const int d = dd[k];
-          for (int i = 1; i < 19; ++i)
-            pre.push_back({Coef{1.0, 0, d}, fs[19 * d + i], Coef{-1.0, 0, d}, g1[18 * k + i - 1]});
+          for (int i = 1; i < Q; ++i)
+            pre.push_back({Coef{1.0, 0, d}, fs[Q * d + i], Coef{-1.0, 0, d}, g1[(Q - 1) * k + i - 1]});
         }
         std::vector<int> fg;
         std::vector<int> h = E.stream(hs, hc, ha, rho0, pre, &fg);
         std::vector<std::vector<Term>> SO;
         for (size_t k = 0; k < dd.size(); ++k) {
           const int d = dd[k];
-          for (int i = 1; i < 19; ++i)
-            SO.push_back({{Coef{1.0, 0, d}, fg[18 * k + i - 1]},
-                          {Coef{1.0, 0, d}, h[18 * k + i - 1]}});
+          for (int i = 1; i < Q; ++i)
+            SO.push_back({{Coef{1.0, 0, d}, fg[(Q - 1) * k + i - 1]},
+                          {Coef{1.0, 0, d}, h[(Q - 1) * k + i - 1]}});
         }
         std::vector<int> o = E.sums(SO, rho0);
         for (size_t k = 0; k < dd.size(); ++k) {
           const int d = dd[k];
-          for (int i = 1; i < 19; ++i) {
-            E.release(fs[19 * d + i]);
-            E.release(g1[18 * k + i - 1]);
-            E.release(h[18 * k + i - 1]);
-            E.release(fg[18 * k + i - 1]);
-            fs[19 * d + i] = o[18 * k + i - 1];
+          for (int i = 1; i < Q; ++i) {
+            E.release(fs[Q * d + i]);
+            E.release(g1[(Q - 1) * k + i - 1]);
+            E.release(h[(Q - 1) * k + i - 1]);
+            E.release(fg[(Q - 1) * k + i - 1]);
+            fs[Q * d + i] = o[(Q - 1) * k + i - 1];
           }
         }
       }
     }
     for (int d = 0; d < D; ++d)
-      for (int i = 0; i < 19; ++i) dom[d].f[i] = fs[19 * d + i];
+      for (int i = 0; i < Q; ++i) dom[d].f[i] = fs[Q * d + i];
     last_roundings = E.roundings + (X ? X->roundings : 0);
     last_products = E.products + (X ? X->products : 0);
   }
@@ -941,20 +949,20 @@ struct SimT : Sim {
     HIP_OK(hipStreamSynchronize(st));
     std::vector<std::array<int, 19>> home(D);
     for (int d = 0; d < D; ++d)
-      for (int i = 0; i < 19; ++i) home[d][i] = dom[d].f[i];
+      for (int i = 0; i < Q; ++i) home[d][i] = dom[d].f[i];
     // the step releases its input populations half-way; during recording
     // their slots are pinned so that no result or temporary lands in them
     // and the final copies cannot overwrite a source still to be copied
     E.pinned.assign(E.pool.size(), 0);
     for (int d = 0; d < D; ++d)
-      for (int i = 0; i < 19; ++i) E.pinned[home[d][i]] = 1;
+      for (int i = 0; i < Q; ++i) E.pinned[home[d][i]] = 1;
     const int tk = E.tkind;
     E.tkind = 0;
     HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
       step_once();
       for (int d = 0; d < D; ++d)
-        for (int i = 0; i < 19; ++i) {
+        for (int i = 0; i < Q; ++i) {
           const int now = dom[d].f[i], h = home[d][i];
           const long tot = E.pool[now].total;
           hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(tot)), dim3(256), 0, st,
@@ -990,26 +998,50 @@ struct SimT : Sim {
       tmp.push_back(q);
       return q;
     };
-    size_t bytes = sizeof(T) * N3 * 19;
+    size_t bytes = sizeof(T) * N3 * Q;
     T* buf = (T*)tdalloc(bytes);
     T* work = (T*)tdalloc(bytes);
-    std::vector<int> objs(dom[d].f, dom[d].f + 19);
+    std::vector<int> objs(dom[d].f, dom[d].f + Q);
     E.to_dense(objs, buf, work);
-    long nout = (what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3);
+    long nout = (what == MPS_LBM_POPS) ? Q * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3);
     double* res = (double*)tdalloc(8 * nout);
     if (what == MPS_LBM_POPS) {
-      hipLaunchKernelGGL((k_scale_permute<T, double>), dim3(dense_chunks(19 * N3)), dim3(256), 0,
-                         st, (const T*)buf, res, n, 19, 0);
+      hipLaunchKernelGGL((k_scale_permute<T, double>), dim3(dense_chunks(Q * N3)), dim3(256), 0,
+                         st, (const T*)buf, res, n, Q, 0);
     } else {
       double* mom = (double*)tdalloc(8 * nout);
       hipLaunchKernelGGL(k_moments_dense<T>, dim3(dense_chunks(N3)), dim3(256), 0, st,
-                         (const T*)buf, mom, N3, what, (const int*)cvec_dev);
+                         (const T*)buf, mom, N3, what, (const int*)cvec_dev, Q);
       hipLaunchKernelGGL((k_scale_permute<double, double>), dim3(dense_chunks(nout)), dim3(256), 0,
                          st, (const double*)mom, res, n, (int)(nout / N3), 0);
     }
     HIP_OK(hipMemcpyAsync(out, res, 8 * nout, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     for (void* q : tmp) E.free_alloc(q);
+  }
+
+  // Kinetic energy (Section 4.2): (1 / (2 N^3)) sum_x |u_x|^2 with
+  // u = j / rho of the dense contraction of the state (0 where rho = 0).
+  double kinetic_energy(int d) override {
+    std::vector<void*> tmp;
+    auto tdalloc = [&](size_t b) {
+      void* q = E.dalloc(b);
+      tmp.push_back(q);
+      return q;
+    };
+    T* buf = (T*)tdalloc(sizeof(T) * N3 * Q);
+    T* work = (T*)tdalloc(sizeof(T) * N3 * Q);
+    double* acc = (double*)tdalloc(8);
+    std::vector<int> objs(dom[d].f, dom[d].f + Q);
+    E.to_dense(objs, buf, work);
+    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, acc, 0.0, 1L);
+    hipLaunchKernelGGL(k_u2_sum<T>, dim3(std::min(1024, dense_chunks(N3))), dim3(256), 0, st,
+                       (const T*)buf, N3, (const int*)cvec_dev, Q, acc);
+    double s = 0.0;
+    HIP_OK(hipMemcpyAsync(&s, acc, 8, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipStreamSynchronize(st));
+    for (void* q : tmp) E.free_alloc(q);
+    return 0.5 * s / (double)N3;
   }
 
   // Numerical health after a synchronisation: a non-finite value seen in
@@ -1055,7 +1087,9 @@ struct SimT : Sim {
   }
 
   int get_mps(int d, int which, double* out, size_t out_len, int* bonds) override {
-    int idx = which < 19 ? dom[d].f[which] : dom[d].mask;
+    if (which >= Q && which != MPS_LBM_MPS_MASK)
+      return fail(MPS_LBM_EINVAL, "population index beyond the lattice's velocities");
+    int idx = which < Q ? dom[d].f[which] : dom[d].mask;
     if (idx < 0) return fail(MPS_LBM_EINVAL, "no obstacle mask in this simulation");
     MpsDev<T> md;
     HIP_OK(hipMemcpyAsync(&md, E.D(idx), sizeof(md), hipMemcpyDeviceToHost, st));
@@ -1196,32 +1230,32 @@ struct SimT : Sim {
   void observables(int d, mps_lbm_obs* o) override {
     memset(o, 0, sizeof(*o));
     const Domain& dm = dom[d];
-    std::vector<int> objs(dm.f, dm.f + 19);
+    std::vector<int> objs(dm.f, dm.f + Q);
     E.inner_ones(objs, sbuf);
     double s[19];
     double stat[2] = {0, 0};
     int ist[7] = {0, 0, 0, 0, 0, 0, 0};
-    HIP_OK(hipMemcpyAsync(s, sbuf, 8 * 19, hipMemcpyDeviceToHost, st));
+    HIP_OK(hipMemcpyAsync(s, sbuf, 8 * Q, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(stat, E.stats, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipMemcpyAsync(ist, E.istats, 28, hipMemcpyDeviceToHost, st));
     double r0 = 0.0;
     HIP_OK(hipMemcpyAsync(&r0, rho0 + d, 8, hipMemcpyDeviceToHost, st));
-    std::vector<MpsDev<T>> descs(19);
-    for (int i = 0; i < 19; ++i)
+    std::vector<MpsDev<T>> descs(Q);
+    for (int i = 0; i < Q; ++i)
       HIP_OK(hipMemcpyAsync(&descs[i], E.D(dm.f[i]), sizeof(MpsDev<T>), hipMemcpyDeviceToHost, st));
     MpsDev<T> md;
     if (dm.mask >= 0) HIP_OK(hipMemcpyAsync(&md, E.D(dm.mask), sizeof(md), hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
     o->step = steps;
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
       o->mass += s[i];
-      for (int a = 0; a < 3; ++a) o->momentum[a] += kC[i][a] * s[i];
+      for (int a = 0; a < 3; ++a) o->momentum[a] += lat->c[i][a] * s[i];
     }
     o->rho0 = r0;
     o->n_fluid = dm.n_fluid;
     double nv = 0.0;
     int mb = 1;
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < Q; ++i) {
       for (int k = 1; k < n; ++k) {
         o->bonds[i][k - 1] = descs[i].r[k];
         mb = std::max(mb, descs[i].r[k]);
@@ -1230,7 +1264,7 @@ struct SimT : Sim {
     }
     o->max_bond = mb;
     o->nvps = nv;
-    o->compression = nv > 0 ? 19.0 * (double)N3 / nv : 0.0;
+    o->compression = nv > 0 ? (double)Q * (double)N3 / nv : 0.0;
     o->max_discarded = stat[0];
     int mk = 1;
     if (dm.mask >= 0)
@@ -1256,7 +1290,7 @@ struct SimT : Sim {
       // Delta p / p_0 = <m_D, rho> / (rho_ref |D|) - 1 with
       // <m_D, rho> = sum_i <m_D, f_i> (Section 4.2)
       double ip = 0.0;
-      for (int i = 0; i < 19; ++i) {
+      for (int i = 0; i < Q; ++i) {
         E.inner_pair(dm.f[i], dm.region, sbuf);
         double v = 0.0;
         HIP_OK(hipMemcpy(&v, sbuf, 8, hipMemcpyDeviceToHost));
@@ -1357,7 +1391,8 @@ int mps_lbm_set_allocator(void* (*alloc)(size_t, void*, void*), void (*free_)(vo
 static int validate(const mps_lbm_config* c) {
   if (!c) return fail(MPS_LBM_EINVAL, "config is NULL");
   if (c->n < 2 || c->n > MPS_LBM_MAX_SITES) return fail(MPS_LBM_EINVAL, "n out of range");
-  if (c->lattice != MPS_LBM_D3Q19) return fail(MPS_LBM_EINVAL, "unknown lattice");
+  if (c->lattice != MPS_LBM_D3Q19 && c->lattice != MPS_LBM_D3Q15)
+    return fail(MPS_LBM_EINVAL, "unknown lattice");
   if (c->chi_max < 1) return fail(MPS_LBM_EINVAL, "chi_max < 1");
   if (c->chi_max > 512) return fail(MPS_LBM_EUNSUPPORTED, "chi_max > 512");
   if (!(c->tau > 0.5)) return fail(MPS_LBM_EINVAL, "tau must exceed 1/2");
@@ -1462,12 +1497,13 @@ int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* cons
     const mps_lbm_config& a = cfgs[0];
     const mps_lbm_config& b = cfgs[d];
     if (a.n != b.n || a.chi_max != b.chi_max || a.precision != b.precision ||
-        a.tol != b.tol || a.sweeps != b.sweeps || a.inv_rho_mode != b.inv_rho_mode ||
+        a.lattice != b.lattice || a.tol != b.tol || a.sweeps != b.sweeps ||
+        a.inv_rho_mode != b.inv_rho_mode ||
         a.inv_rho_iters != b.inv_rho_iters || a.rank_predictor != b.rank_predictor ||
         a.rank_oversample != b.rank_oversample || a.chi_mask_max != b.chi_mask_max)
       return fail(MPS_LBM_EINVAL,
-                  "batched domains must share n, chi_max, chi_mask_max, precision, tol, sweeps "
-                  "and the inverse-density mode");
+                  "batched domains must share n, lattice, chi_max, chi_mask_max, precision, tol, "
+                  "sweeps and the inverse-density mode");
   }
   return create(cfgs, count, rho, u, nullptr, solid, hip_stream, out);
 }
@@ -1502,12 +1538,25 @@ int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, siz
   if (what < MPS_LBM_POPS || what > MPS_LBM_VEL) return fail(MPS_LBM_EINVAL, "bad what");
   if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
   const long N3 = h->sim->cells();
-  size_t need = (size_t)((what == MPS_LBM_POPS) ? 19 * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3));
+  const long Q = h->sim->velocities();
+  size_t need = (size_t)((what == MPS_LBM_POPS) ? Q * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3));
   if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
   return guarded([&]() -> int {
     const int ns = h->sim->numeric_status();
     if (ns) return ns;
     h->sim->to_dense(domain, what, out);
+    return MPS_LBM_OK;
+  });
+}
+
+int mps_lbm_kinetic_energy(mps_lbm_t* h, int domain, double* e_kin) {
+  if (!h || !h->sim) return fail(MPS_LBM_EINVAL, "handle is NULL");
+  if (!e_kin) return fail(MPS_LBM_EINVAL, "e_kin is NULL");
+  if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
+  return guarded([&]() -> int {
+    const int ns = h->sim->numeric_status();
+    if (ns) return ns;
+    *e_kin = h->sim->kinetic_energy(domain);
     return MPS_LBM_OK;
   });
 }

@@ -343,13 +343,13 @@ __global__ void k_scale_permute(const TI* in, TO* out, int n, int nfields, int t
 
 // Initial equilibrium populations f_i = (1 - m) w_i rho (1 + 3 c.u + 4.5 (c.u)^2 - 1.5 u.u)
 __global__ void k_feq_dense(const double* rho, const double* u, const uint8_t* solid,
-                            double* f, long N3, const int* cvec, const double* w) {
+                            double* f, long N3, const int* cvec, const double* w, int q) {
   for (long e = blockIdx.x * (long)blockDim.x + threadIdx.x; e < N3;
        e += (long)gridDim.x * blockDim.x) {
     double r = rho[e], ux = u[e], uy = u[N3 + e], uz = u[2 * N3 + e];
     double fl = solid ? (solid[e] ? 0.0 : 1.0) : 1.0;
     double uu = ux * ux + uy * uy + uz * uz;
-    for (int i = 0; i < 19; ++i) {
+    for (int i = 0; i < q; ++i) {
       double cu = cvec[3 * i] * ux + cvec[3 * i + 1] * uy + cvec[3 * i + 2] * uz;
       f[i * N3 + e] = fl * w[i] * r * (1.0 + 3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
     }

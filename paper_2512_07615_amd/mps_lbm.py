@@ -20,6 +20,7 @@ MAX_SITES = 10
 
 OK, EINVAL, ENOMEM, EHIP, ENUMERIC, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 D3Q19 = 19
+D3Q15 = 15
 FP64, FP32, BF16, BF16X3 = 0, 1, 2, 3
 INV_TAYLOR2, INV_NEWTON = 0, 1
 BC_NONE, BC_VELOCITY, BC_PRESSURE = 0, 1, 2
@@ -39,7 +40,7 @@ EXPORTED = sorted(["mps_lbm_default_config", "mps_lbm_init_from_field", "mps_lbm
                    "mps_lbm_load_rank_model", "mps_lbm_get_rank_model",
                    "mps_lbm_debug_raise_flags", "mps_lbm_mlp_gradient_device",
                    "mps_lbm_init_tensor_mask", "mps_lbm_set_face_profile",
-                   "mps_lbm_set_region"])
+                   "mps_lbm_set_region", "mps_lbm_kinetic_energy"])
 
 
 class Config(C.Structure):
@@ -117,6 +118,8 @@ def load(path: str = LIB_PATH):
     lib.mps_lbm_set_region.argtypes = [P, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                                        C.c_double]
     lib.mps_lbm_set_region.restype = C.c_int
+    lib.mps_lbm_kinetic_energy.argtypes = [P, C.c_int, DP]
+    lib.mps_lbm_kinetic_energy.restype = C.c_int
     lib.mps_lbm_step.argtypes = [P, C.c_int]
     lib.mps_lbm_step.restype = C.c_int
     lib.mps_lbm_to_dense.argtypes = [P, C.c_int, DP, C.c_size_t]
@@ -253,6 +256,13 @@ def mps_lbm_set_region(h, lo, hi, rho_ref: float, domain: int = 0):
     _check(load().mps_lbm_set_region(h, int(domain), a, b, float(rho_ref)))
 
 
+def mps_lbm_kinetic_energy(h, domain: int = 0) -> float:
+    """(1 / (2 N^3)) sum_x |j / rho|^2 of the state, lattice units."""
+    e = C.c_double()
+    _check(load().mps_lbm_kinetic_energy(h, int(domain), C.byref(e)))
+    return e.value
+
+
 def mps_lbm_train_rank_predictor(h, epochs: int, lr: float) -> float:
     loss = C.c_double()
     _check(load().mps_lbm_train_rank_predictor(h, int(epochs), float(lr), C.byref(loss)))
@@ -344,8 +354,8 @@ def mps_lbm_step(h, nsteps: int = 1):
     _check(load().mps_lbm_step(h, int(nsteps)))
 
 
-def mps_lbm_to_dense(h, what: int, N: int) -> np.ndarray:
-    shape = {POPS: (19, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
+def mps_lbm_to_dense(h, what: int, N: int, q: int = D3Q19) -> np.ndarray:
+    shape = {POPS: (q, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
     out = np.empty(shape, dtype=np.float64)
     _check(load().mps_lbm_to_dense(h, int(what), _dp(out), out.size))
     return out
@@ -407,8 +417,8 @@ def mps_lbm_domains(h) -> int:
     return v
 
 
-def mps_lbm_to_dense_domain(h, domain: int, what: int, N: int) -> np.ndarray:
-    shape = {POPS: (19, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
+def mps_lbm_to_dense_domain(h, domain: int, what: int, N: int, q: int = D3Q19) -> np.ndarray:
+    shape = {POPS: (q, N, N, N), RHO: (N, N, N), J: (3, N, N, N), VEL: (3, N, N, N)}[what]
     out = np.empty(shape, dtype=np.float64)
     _check(load().mps_lbm_to_dense_domain(h, int(domain), int(what), _dp(out), out.size))
     return out
@@ -447,6 +457,7 @@ def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_
     """Config from a workloads.Case."""
     c = mps_lbm_default_config()
     c.n = case.n
+    c.lattice = int(getattr(case, "lattice", D3Q19))
     c.chi_max = int(case.chi)
     c.chi_mask_max = int(case.chi_mask or 0)
     c.tol = float(case.tol)
@@ -485,7 +496,8 @@ class BatchSimulation:
         mps_lbm_step(self.h, n)
 
     def dense(self, domain, what=POPS):
-        return mps_lbm_to_dense_domain(self.h, domain, what, self.cases[domain].N)
+        return mps_lbm_to_dense_domain(self.h, domain, what, self.cases[domain].N,
+                                       self.cfgs[0].lattice)
 
     def observables(self, domain=0):
         return mps_lbm_observables_domain(self.h, domain)
@@ -555,11 +567,14 @@ class Simulation:
     def set_region(self, lo, hi, rho_ref):
         mps_lbm_set_region(self.h, lo, hi, rho_ref)
 
+    def kinetic_energy(self):
+        return mps_lbm_kinetic_energy(self.h)
+
     def step(self, n=1):
         mps_lbm_step(self.h, n)
 
     def dense(self, what=POPS):
-        return mps_lbm_to_dense(self.h, what, self.case.N)
+        return mps_lbm_to_dense(self.h, what, self.case.N, self.cfg.lattice)
 
     def observables(self):
         return mps_lbm_observables(self.h)
