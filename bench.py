@@ -7,8 +7,10 @@ products, BGK sums, streaming, open faces, bounce-back, all roundings) on
 the synthetic workload, inputs resident in HBM.  The default workload is
 the 128^3 branching-tube configuration at chi = 128 with BF16X3
 contractions (the largest configuration of the target that one GPU runs
-whole); the 64^3 porous medium at chi = 64 (FP32) is timed as an extra
-field.  Prints one JSON line.
+whole); the 64^3 porous medium at chi = 64 (FP32), the 256^3 Taylor-Green
+vortex on D3Q15 at chi = 128 and the 128^3 pin array (tensor-product mask,
+ramped inlet, Delta p / p_0 over the inflow region) at chi = 128 are timed
+as extra fields.  Prints one JSON line.
 """
 import argparse
 import re
@@ -37,6 +39,18 @@ def make_case(name):
         return WL.case_porous(n=5, chi=32, tau=0.6, tol=1e-8, precision="fp32")
     if name == "channel16":
         return WL.case_channel()
+    if name == "tgv256":
+        # Taylor-Green vortex of Sections 4.1 / 5.1: 256^3, Re 800,
+        # Ma = 0.1 / c_s, D3Q15, chi = 128, BF16X3 contractions
+        return WL.case_tgv(n=8, chi=128, re=800.0, tol=1e-8, precision="bf16x3")
+    if name == "pinfin128":
+        # pin array (8^3 layout of 16^3 pins, mask as their tensor product),
+        # inlet ramped as u_0 (1 - e^(-1.5 t)) with t in flow-through times
+        # L / u_0 = 128 / 0.02 steps, chi = 128, BF16X3
+        c = WL.case_pinfin(n=7, l=3, chi=128, tau=0.56, u_in=0.02, tol=1e-8,
+                           precision="bf16x3")
+        c.face_profile = {0: ((0.0, 1.0, 1.5, 0.0, 0.0, 0.0), 0.02 / 128.0)}
+        return c
     if name == "vascular128":
         # 128^3 branching tube tree, velocity inlet 0.02 / pressure outlet,
         # chi = 128, contractions on BF16 MFMA with three-term operand
@@ -160,8 +174,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="vascular128")
-    ap.add_argument("--extra-workload", default="porous64",
-                    help="also time this workload's step (empty = skip)")
+    ap.add_argument("--extra-workload", default="porous64,tgv256,pinfin128",
+                    help="also time these workloads' steps (comma-separated; empty = skip)")
     ap.add_argument("--extra-steps", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--fp64-steps", type=int, default=1)
@@ -277,7 +291,7 @@ def main():
             rm = out["roofline_mfma"]
             rm["mfma_products_per_useful"] = 6
             rm["matrix_core_frac"] = 6 * rm["frac"]
-    if not args.no_graph:
+    if not args.no_graph and args.graph_steps > 0:
         # the same step recorded once as a HIP graph and replayed (the timed
         # region above issues it kernel by kernel, with per-launch events)
         sim.kernel_timing(L.K_NONE)
@@ -331,9 +345,17 @@ def main():
         progress(f"FP64 policy: {ms64:.1f} ms/step")
     if args.batch > 0:
         out["config"]["batched"] = batched_rate(case, args.batch, stream, args.batch_steps)
-    if args.extra_workload and args.extra_workload != args.workload and args.extra_steps > 0:
-        xc = make_case(args.extra_workload)
+    extras = [w for w in (args.extra_workload or "").split(",") if w and w != args.workload]
+    if extras and args.extra_steps > 0:
+        out["config"]["extra"] = []
+    for wname in (extras if args.extra_steps > 0 else []):
+        xc = make_case(wname)
+        progress(f"{xc.name}: init")
         xs = L.Simulation(xc, hip_stream=stream.cuda_stream)
+        if wname == "pinfin128":
+            # Delta p / p_0 over the inflow region of Section 4.2 (x < 2 L / 256,
+            # y, z < L / 2)
+            xs.set_region((0, 0, 0), (1, 64, 64), 1.0)
         xs.step(1)
         torch.cuda.synchronize()
         e0.record(stream)
@@ -343,12 +365,17 @@ def main():
         torch.cuda.synchronize()
         xms = e0.elapsed_time(e1) / args.extra_steps
         xo = xs.observables()
+        rec = {"workload": xc.name, "precision": xc.precision, "lattice": f"D3Q{xc.lattice}",
+               "chi": xc.chi, "steps_per_s": 1000.0 / xms, "ms_per_step": xms,
+               "equiv_mlups": xc.N ** 3 * 1000.0 / xms / 1e6,
+               "mask_bond": xo.mask_bond, "max_bond": xo.max_bond,
+               "compression": xo.compression, "steps_taken": int(xo.step)}
+        if wname == "tgv256":
+            rec["e_kin"] = xs.kinetic_energy()
+        if wname == "pinfin128":
+            rec["dp_p0_inflow"] = xo.dp_p0
         xs.close()
-        out["config"]["extra"] = {"workload": xc.name, "precision": xc.precision,
-                                  "chi": xc.chi, "steps_per_s": 1000.0 / xms,
-                                  "ms_per_step": xms,
-                                  "equiv_mlups": xc.N ** 3 * 1000.0 / xms / 1e6,
-                                  "mask_bond": xo.mask_bond, "max_bond": xo.max_bond}
+        out["config"]["extra"].append(rec)
         progress(f"{xc.name}: {xms:.1f} ms/step")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(case, obs.roundings, obs.products)
