@@ -488,6 +488,7 @@ class BatchSimulation:
     def __init__(self, cases, precision=None, hip_stream=None, **kw):
         self.cases = list(cases)
         cfgs = [config_from_case(c, precision, **kw) for c in self.cases]
+        self.cfgs = cfgs
         self.h = mps_lbm_init_batch(cfgs, [c.rho0_field() for c in self.cases],
                                     [c.u0_field() for c in self.cases],
                                     [c.solid for c in self.cases], hip_stream=hip_stream)
