@@ -128,6 +128,39 @@ def batched_rate(case, count, stream, steps):
             "equiv_mlups": count * case.N ** 3 * 1000.0 / ms / 1e6}
 
 
+def c4_rate(stream, steps, progress):
+    """48 seeded domains of mixed size (32^3 to 128^3), bond dimension (32 to
+    128) and policy (FP32, BF16X3) in one handle: the groups of equal shape
+    run as batched engines on streams of their own, and the whole step is
+    replayed as one HIP graph.  Returns domain-steps/s and the groups."""
+    import torch
+    import workloads as WL
+    from paper_2512_07615_amd import mps_lbm as L
+    cases = WL.c4_cases()
+    t0 = time.time()
+    b = L.BatchSimulation(cases, hip_stream=stream.cuda_stream)
+    torch.cuda.synchronize()
+    init_s = time.time() - t0
+    progress(f"c4: 48 domains initialised in {init_s:.1f} s")
+    b.capture()            # one eager step, then the next one recorded
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    b.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / steps
+    nonfinite = sum(b.observables(d).nonfinite for d in range(len(cases)))
+    b.close()
+    groups = sorted({(c.n, c.chi, c.precision) for c in cases})
+    cells = sum(c.N ** 3 for c in cases)
+    return {"domains": len(cases), "groups": len(groups), "steps": steps, "ms_per_step": ms,
+            "domain_steps_per_s": len(cases) * 1000.0 / ms,
+            "equiv_mlups": cells * 1000.0 / ms / 1e6, "init_s": init_s,
+            "hip_graph": True, "nonfinite": nonfinite}
+
+
 def stored_traffic(kind, workload):
     """HBM bytes per launch of the roofline kernel from the committed
     rocprofv3 counter summary (profiles/<workload>_<kind>_hbm_traffic.md),
@@ -185,6 +218,8 @@ def main():
                     help="also time this many domains of the workload advanced together "
                          "(0 = skip)")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--c4-steps", type=int, default=2,
+                    help="graph-replayed steps of the 48 mixed domains (0 = skip)")
     ap.add_argument("--mfma-steps", type=int, default=2,
                     help="steps timed for the MFMA utilisation of the product GEMMs")
     ap.add_argument("--no-graph", action="store_true",
@@ -345,6 +380,9 @@ def main():
         progress(f"FP64 policy: {ms64:.1f} ms/step")
     if args.batch > 0:
         out["config"]["batched"] = batched_rate(case, args.batch, stream, args.batch_steps)
+    if args.c4_steps > 0:
+        out["config"]["c4_mixed_domains"] = c4_rate(stream, args.c4_steps, progress)
+        progress(f"c4: {out['config']['c4_mixed_domains']['ms_per_step']:.0f} ms per step")
     extras = [w for w in (args.extra_workload or "").split(",") if w and w != args.workload]
     if extras and args.extra_steps > 0:
         out["config"]["extra"] = []

@@ -299,15 +299,21 @@ int mps_lbm_observables(mps_lbm_t* h, mps_lbm_obs* out);
 
 /*
  * Batched domains: count independent simulations (each the problem of
- * Section 3.2 with its own geometry, tau, g, faces and initial fields) held
- * by one handle and advanced together by mps_lbm_step, every operation of
- * the step being issued once for the MPS of all domains.  The domains must
- * share n, chi_max, precision, tol, sweeps and the inverse-density mode;
- * rho[d], u[d] and solid[d] are as in mps_lbm_init_from_field (solid, or
- * an entry of it, may be NULL for no obstacles).  The handle's plain entry
- * points address domain 0; the per-domain forms below address any.
- * Errors: EINVAL (count < 1, an invalid configuration, configurations that
- * differ in a shared field, NULL fields), ENOMEM, EHIP.
+ * Section 3.2 with its own configuration, geometry and initial fields) held
+ * by one handle and advanced together by mps_lbm_step.  Domains that share
+ * n, the velocity set, chi_max, chi_mask_max, precision, tol, sweeps, the
+ * inverse-density mode and the rank-predictor settings form a group: every
+ * operation of the step is issued once for the MPS of all domains of the
+ * group.  Domains of different sizes or policies form several groups, which
+ * run one after another on the handle's stream (and are recorded into one
+ * graph by mps_lbm_capture_step).  rho[d], u[d] and solid[d] are as in
+ * mps_lbm_init_from_field (solid, or an entry of it, may be NULL for no
+ * obstacles).  The handle's plain entry points address domain 0; the
+ * per-domain forms below address any.  The rank-predictor entry points and
+ * mps_lbm_debug_raise_flags address the group of domain 0;
+ * mps_lbm_kernel_stats and mps_lbm_autotune cover every group.
+ * Errors: EINVAL (count < 1, an invalid configuration, NULL fields),
+ * ENOMEM, EHIP.
  */
 int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* const* rho,
                        const double* const* u, const uint8_t* const* solid, void* hip_stream,

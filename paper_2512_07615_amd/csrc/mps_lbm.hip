@@ -53,8 +53,8 @@ struct Sim {
   virtual void set_timing(int kind) = 0;
   virtual void kstats(mps_lbm_kstats* o) = 0;
   virtual int get_mps(int d, int which, double* out, size_t out_len, int* bonds) = 0;
-  virtual long cells() const = 0;
-  virtual int velocities() const = 0;
+  virtual long cells(int d) const = 0;
+  virtual int velocities(int d) const = 0;
   virtual double kinetic_energy(int d) = 0;
   virtual void capture() = 0;
   virtual float train_predictor(int epochs, float lr) = 0;
@@ -66,6 +66,11 @@ struct Sim {
   virtual void rank_model(float* w, int load) = 0;
   virtual void set_face_profile(int d, int face, const double* coef, double dt) = 0;
   virtual void set_region(int d, const int* lo, const int* hi, double rho_ref) = 0;
+  // pieces of capture() for a handle whose domains form several groups
+  virtual void capture_prepare() {}
+  virtual void capture_record() {}
+  virtual void capture_finish() {}
+  virtual void count_step() {}
 };
 
 // Copy MPS i of S into MPS i of D (same capacity profile), converting the
@@ -322,8 +327,8 @@ struct SimT : Sim {
   }
 
   int domains() const override { return D; }
-  int velocities() const override { return Q; }
-  long cells() const override { return N3; }
+  int velocities(int) const override { return Q; }
+  long cells(int) const override { return N3; }
 
   int dense_chunks(long count) const {
     return (int)std::max<long>(1, std::min<long>(2048, (count + 255) / 256));
@@ -942,12 +947,16 @@ struct SimT : Sim {
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
 
-  void capture() override {
-    if (gexec) return;
-    if (!st) throw Error(-1, "graph capture needs a non-default stream");
+  // capture in three pieces, so that a handle of several groups can record
+  // all of them into one graph: prepare (one eager step, pin the slots the
+  // populations live in), record (inside an open capture: the step and the
+  // copies back into those slots), finish (unpin)
+  std::vector<std::array<int, 19>> home;
+  int saved_tkind = 0;
+  void capture_prepare() override {
     step(1);
     HIP_OK(hipStreamSynchronize(st));
-    std::vector<std::array<int, 19>> home(D);
+    home.assign(D, std::array<int, 19>{});
     for (int d = 0; d < D; ++d)
       for (int i = 0; i < Q; ++i) home[d][i] = dom[d].f[i];
     // the step releases its input populations half-way; during recording
@@ -956,33 +965,48 @@ struct SimT : Sim {
     E.pinned.assign(E.pool.size(), 0);
     for (int d = 0; d < D; ++d)
       for (int i = 0; i < Q; ++i) E.pinned[home[d][i]] = 1;
-    const int tk = E.tkind;
+    saved_tkind = E.tkind;
     E.tkind = 0;
+  }
+  void capture_record() override {
+    step_once();
+    for (int d = 0; d < D; ++d)
+      for (int i = 0; i < Q; ++i) {
+        const int now = dom[d].f[i], h = home[d][i];
+        const long tot = E.pool[now].total;
+        hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(tot)), dim3(256), 0, st,
+                           (const T*)E.pool[now].data, E.pool[h].data, tot);
+        hipLaunchKernelGGL(k_copy_ranks<T>, dim3(1), dim3(64), 0, st, E.D(h),
+                           (const MpsDev<T>*)E.D(now));
+        E.release(now);
+        dom[d].f[i] = h;
+      }
+  }
+  void capture_finish() override {
+    E.tkind = saved_tkind;
+    E.pinned.clear();
+  }
+  void count_step() override {
+    ++steps;
+    E.step_count = steps;
+  }
+
+  void capture() override {
+    if (gexec) return;
+    if (!st) throw Error(-1, "graph capture needs a non-default stream");
+    capture_prepare();
     HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     try {
-      step_once();
-      for (int d = 0; d < D; ++d)
-        for (int i = 0; i < Q; ++i) {
-          const int now = dom[d].f[i], h = home[d][i];
-          const long tot = E.pool[now].total;
-          hipLaunchKernelGGL(k_copy_plain<T>, dim3(dense_chunks(tot)), dim3(256), 0, st,
-                             (const T*)E.pool[now].data, E.pool[h].data, tot);
-          hipLaunchKernelGGL(k_copy_ranks<T>, dim3(1), dim3(64), 0, st, E.D(h),
-                             (const MpsDev<T>*)E.D(now));
-          E.release(now);
-          dom[d].f[i] = h;
-        }
+      capture_record();
     } catch (...) {
       hipGraph_t g = nullptr;
       (void)hipStreamEndCapture(st, &g);
       if (g) (void)hipGraphDestroy(g);
-      E.tkind = tk;
-      E.pinned.clear();
+      capture_finish();
       throw;
     }
     HIP_OK(hipStreamEndCapture(st, &graph));
-    E.tkind = tk;
-    E.pinned.clear();
+    capture_finish();
     HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
   }
 
@@ -1303,6 +1327,168 @@ struct SimT : Sim {
   }
 };
 
+// Domains of different shapes or policies in one handle: each group of
+// domains that share n, the velocity set, chi_max, chi_mask_max, precision,
+// tol, sweeps, the inverse-density mode and the rank-predictor settings is
+// one batched SimT with a stream of its own (default priority).  A step
+// forks from the handle's stream to the group streams and joins back
+// through events, so that the groups' launches (most of them latency-bound
+// and far from filling the chip) overlap; the graph mode records the same
+// fork and join, one graph with a branch per group.
+struct MultiSim : Sim {
+  std::vector<std::pair<int, int>> where;  // domain -> (group, index in it)
+  hipStream_t st = nullptr;                // the handle's stream
+  std::vector<hipStream_t> gs;             // one per group
+  hipEvent_t fork_ev = nullptr;
+  std::vector<hipEvent_t> join_ev;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<std::unique_ptr<Sim>> g;
+
+  void make_streams(int ngroups) {
+    HIP_OK(hipEventCreateWithFlags(&fork_ev, hipEventDisableTiming));
+    for (int i = 0; i < ngroups; ++i) {
+      hipStream_t s = nullptr;
+      HIP_OK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+      gs.push_back(s);
+      hipEvent_t e = nullptr;
+      HIP_OK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+      join_ev.push_back(e);
+    }
+  }
+  ~MultiSim() {
+    (void)hipStreamSynchronize(st);
+    for (hipStream_t s : gs) (void)hipStreamSynchronize(s);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    g.clear();  // the groups free their memory on their streams
+    for (hipEvent_t e : join_ev) (void)hipEventDestroy(e);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    for (hipStream_t s : gs) (void)hipStreamDestroy(s);
+  }
+  Sim& of(int d) const { return *g[where[d].first]; }
+  int loc(int d) const { return where[d].second; }
+  // work already on the handle's stream precedes a group call
+  Sim& synced(int d) const {
+    HIP_OK(hipStreamSynchronize(st));
+    return of(d);
+  }
+  void fork() {
+    HIP_OK(hipEventRecord(fork_ev, st));
+    for (hipStream_t s : gs) HIP_OK(hipStreamWaitEvent(s, fork_ev, 0));
+  }
+  void join() {
+    for (size_t i = 0; i < gs.size(); ++i) {
+      HIP_OK(hipEventRecord(join_ev[i], gs[i]));
+      HIP_OK(hipStreamWaitEvent(st, join_ev[i], 0));
+    }
+  }
+
+  int domains() const override { return (int)where.size(); }
+  void step(int nsteps) override {
+    for (int s = 0; s < nsteps; ++s) {
+      if (gexec) {
+        HIP_OK(hipGraphLaunch(gexec, st));
+        for (auto& x : g) x->count_step();
+      } else {
+        fork();
+        for (auto& x : g) x->step(1);
+        join();
+      }
+    }
+    HIP_OK(hipGetLastError());
+  }
+  void to_dense(int d, int what, double* out) override {
+    synced(d).to_dense(loc(d), what, out);
+  }
+  void observables(int d, mps_lbm_obs* o) override { synced(d).observables(loc(d), o); }
+  void set_timing(int kind) override {
+    for (auto& x : g) x->set_timing(kind);
+  }
+  void kstats(mps_lbm_kstats* o) override {
+    mps_lbm_kstats sum{0, 0.0, 0.0};
+    for (auto& x : g) {
+      mps_lbm_kstats k{0, 0.0, 0.0};
+      x->kstats(&k);
+      sum.launches += k.launches;
+      sum.total_ms += k.total_ms;
+      sum.flops += k.flops;
+    }
+    *o = sum;
+  }
+  int get_mps(int d, int which, double* out, size_t out_len, int* bonds) override {
+    return synced(d).get_mps(loc(d), which, out, out_len, bonds);
+  }
+  long cells(int d) const override { return of(d).cells(loc(d)); }
+  int velocities(int d) const override { return of(d).velocities(loc(d)); }
+  double kinetic_energy(int d) override { return synced(d).kinetic_energy(loc(d)); }
+  void capture() override {
+    if (gexec) return;
+    if (!st) throw Error(-1, "graph capture needs a non-default stream");
+    HIP_OK(hipStreamSynchronize(st));
+    for (auto& x : g) x->capture_prepare();
+    HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    try {
+      fork();
+      for (auto& x : g) x->capture_record();
+      join();
+    } catch (...) {
+      hipGraph_t gg = nullptr;
+      (void)hipStreamEndCapture(st, &gg);
+      if (gg) (void)hipGraphDestroy(gg);
+      for (auto& x : g) x->capture_finish();
+      throw;
+    }
+    HIP_OK(hipStreamEndCapture(st, &graph));
+    for (auto& x : g) x->capture_finish();
+    HIP_OK(hipGraphInstantiate(&gexec, graph, nullptr, nullptr, 0));
+  }
+  // the rank predictor and the numerical-failure hook address the first group
+  float train_predictor(int epochs, float lr) override {
+    HIP_OK(hipStreamSynchronize(st));
+    return g[0]->train_predictor(epochs, lr);
+  }
+  int autotune() override {
+    HIP_OK(hipStreamSynchronize(st));
+    int n = 0;
+    for (auto& x : g) n += x->autotune();
+    return n;
+  }
+  void predictor_info(mps_lbm_predictor_info* o) override { synced(0).predictor_info(o); }
+  int numeric_status() override {
+    HIP_OK(hipStreamSynchronize(st));
+    for (auto& x : g) {
+      const int r = x->numeric_status();
+      if (r) return r;
+    }
+    return MPS_LBM_OK;
+  }
+  bool fatal_seen() const override {
+    for (auto& x : g)
+      if (x->fatal_seen()) return true;
+    return false;
+  }
+  void raise_flags(int nonfinite, int sweep_limit) override {
+    synced(0).raise_flags(nonfinite, sweep_limit);
+  }
+  void rank_model(float* w, int load) override { synced(0).rank_model(w, load); }
+  void set_face_profile(int d, int face, const double* coef, double dt) override {
+    synced(d).set_face_profile(loc(d), face, coef, dt);
+  }
+  void set_region(int d, const int* lo, const int* hi, double rho_ref) override {
+    synced(d).set_region(loc(d), lo, hi, rho_ref);
+  }
+};
+
+// the fields that domains advanced by one batched engine must share
+static bool same_group(const mps_lbm_config& a, const mps_lbm_config& b) {
+  return a.n == b.n && a.lattice == b.lattice && a.chi_max == b.chi_max &&
+         a.chi_mask_max == b.chi_mask_max && a.precision == b.precision && a.tol == b.tol &&
+         a.sweeps == b.sweeps && a.inv_rho_mode == b.inv_rho_mode &&
+         a.inv_rho_iters == b.inv_rho_iters && a.rank_predictor == b.rank_predictor &&
+         a.rank_oversample == b.rank_oversample;
+}
+
 }  // namespace
 
 struct mps_lbm {
@@ -1424,6 +1610,28 @@ static int validate(const mps_lbm_config* c) {
   return MPS_LBM_OK;
 }
 
+// One batched engine for the domains idx of cfgs (equal group fields).
+static std::unique_ptr<Sim> make_group(const mps_lbm_config* cfgs, const std::vector<int>& idx,
+                                       const double* const* rho, const double* const* u,
+                                       const double* const* f, const uint8_t* const* solid,
+                                       hipStream_t st, const MaskParts* mp) {
+  std::vector<mps_lbm_config> gc;
+  for (int d : idx) gc.push_back(cfgs[d]);
+  auto build = [&](auto* s) {
+    std::unique_ptr<Sim> keep(s);
+    for (size_t j = 0; j < idx.size(); ++j) {
+      const int d = idx[j];
+      s->init_domain((int)j, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
+                     solid ? solid[d] : nullptr, mp);
+    }
+    s->finish_init();
+    return keep;
+  };
+  if (gc[0].precision == MPS_LBM_FP64)
+    return build(new SimT<double>(gc.data(), (int)gc.size(), st, g_alloc));
+  return build(new SimT<float>(gc.data(), (int)gc.size(), st, g_alloc));
+}
+
 static int create(const mps_lbm_config* cfgs, int count, const double* const* rho,
                   const double* const* u, const double* const* f, const uint8_t* const* solid,
                   void* hip_stream, mps_lbm_t** out, const MaskParts* mp = nullptr) {
@@ -1435,20 +1643,27 @@ static int create(const mps_lbm_config* cfgs, int count, const double* const* rh
     }
     std::unique_ptr<mps_lbm> h(new mps_lbm());
     hipStream_t st = (hipStream_t)hip_stream;
-    if (cfgs[0].precision == MPS_LBM_FP64) {
-      auto* s = new SimT<double>(cfgs, count, st, g_alloc);
-      h->sim.reset(s);
-      for (int d = 0; d < count; ++d)
-        s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
-                       solid ? solid[d] : nullptr, mp);
-      s->finish_init();
+    // group the domains by the fields a batched engine needs equal, in the
+    // order of their first appearance
+    std::vector<std::vector<int>> groups;
+    std::vector<std::pair<int, int>> where(count);
+    for (int d = 0; d < count; ++d) {
+      size_t gi = 0;
+      while (gi < groups.size() && !same_group(cfgs[groups[gi][0]], cfgs[d])) ++gi;
+      if (gi == groups.size()) groups.emplace_back();
+      where[d] = {(int)gi, (int)groups[gi].size()};
+      groups[gi].push_back(d);
+    }
+    if (groups.size() == 1) {
+      h->sim = make_group(cfgs, groups[0], rho, u, f, solid, st, mp);
     } else {
-      auto* s = new SimT<float>(cfgs, count, st, g_alloc);
-      h->sim.reset(s);
-      for (int d = 0; d < count; ++d)
-        s->init_domain(d, rho ? rho[d] : nullptr, u ? u[d] : nullptr, f ? f[d] : nullptr,
-                       solid ? solid[d] : nullptr, mp);
-      s->finish_init();
+      std::unique_ptr<MultiSim> ms(new MultiSim());
+      ms->st = st;
+      ms->where = where;
+      ms->make_streams((int)groups.size());
+      for (size_t i = 0; i < groups.size(); ++i)
+        ms->g.push_back(make_group(cfgs, groups[i], rho, u, f, solid, ms->gs[i], mp));
+      h->sim = std::move(ms);
     }
     *out = h.release();
     g_last_error.clear();
@@ -1494,16 +1709,6 @@ int mps_lbm_init_batch(const mps_lbm_config* cfgs, int count, const double* cons
     int v = validate(cfgs + d);
     if (v) return v;
     if (!rho[d] || !u[d]) return fail(MPS_LBM_EINVAL, "rho[d] or u[d] is NULL");
-    const mps_lbm_config& a = cfgs[0];
-    const mps_lbm_config& b = cfgs[d];
-    if (a.n != b.n || a.chi_max != b.chi_max || a.precision != b.precision ||
-        a.lattice != b.lattice || a.tol != b.tol || a.sweeps != b.sweeps ||
-        a.inv_rho_mode != b.inv_rho_mode ||
-        a.inv_rho_iters != b.inv_rho_iters || a.rank_predictor != b.rank_predictor ||
-        a.rank_oversample != b.rank_oversample || a.chi_mask_max != b.chi_mask_max)
-      return fail(MPS_LBM_EINVAL,
-                  "batched domains must share n, lattice, chi_max, chi_mask_max, precision, tol, "
-                  "sweeps and the inverse-density mode");
   }
   return create(cfgs, count, rho, u, nullptr, solid, hip_stream, out);
 }
@@ -1537,8 +1742,8 @@ int mps_lbm_to_dense_domain(mps_lbm_t* h, int domain, int what, double* out, siz
   if (!out) return fail(MPS_LBM_EINVAL, "out is NULL");
   if (what < MPS_LBM_POPS || what > MPS_LBM_VEL) return fail(MPS_LBM_EINVAL, "bad what");
   if (domain < 0 || domain >= h->sim->domains()) return fail(MPS_LBM_EINVAL, "bad domain");
-  const long N3 = h->sim->cells();
-  const long Q = h->sim->velocities();
+  const long N3 = h->sim->cells(domain);
+  const long Q = h->sim->velocities(domain);
   size_t need = (size_t)((what == MPS_LBM_POPS) ? Q * N3 : (what == MPS_LBM_RHO ? N3 : 3 * N3));
   if (out_len < need) return fail(MPS_LBM_EINVAL, "out_len too small");
   return guarded([&]() -> int {

@@ -482,8 +482,8 @@ def config_from_case(case, precision=None, sweeps: int = 2, inv_mode: int = INV_
 
 
 class BatchSimulation:
-    """Several domains (workloads.Case, equal n / chi / precision / tol)
-    advanced together by one handle."""
+    """Several domains (workloads.Case) advanced together by one handle;
+    domains of equal n / chi / precision / tol share batched launches."""
 
     def __init__(self, cases, precision=None, hip_stream=None, **kw):
         self.cases = list(cases)
@@ -498,7 +498,7 @@ class BatchSimulation:
 
     def dense(self, domain, what=POPS):
         return mps_lbm_to_dense_domain(self.h, domain, what, self.cases[domain].N,
-                                       self.cfgs[0].lattice)
+                                       self.cfgs[domain].lattice)
 
     def observables(self, domain=0):
         return mps_lbm_observables_domain(self.h, domain)

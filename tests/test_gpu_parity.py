@@ -958,3 +958,52 @@ def test_tgv32_kinetic_energy_decay_vs_dense():
     # measured: 8.2e-12 and 1.0e-10
     assert eg[-1] < 0.9 * eg[0]
     assert dev < 1e-10 and ddev < 1e-8
+
+
+def test_uneven_domains_in_one_handle():
+    """Domains of different sizes, bond dimensions, velocity sets and
+    precisions in one handle (four groups of batched engines): after two
+    steps each domain equals its own single-domain handle bitwise; a graph
+    recording all groups replays bitwise like the eager handle; the FP64
+    domains match the CPU MPS oracle."""
+    L = lib()
+    cases = [
+        _case_with_flow(WL.case_porous(n=4, chi=16, tau=0.6, tol=1e-8, precision="fp64"), seed=1),
+        _case_with_flow(WL.case_channel(n=5, chi=16, tau=0.7, tol=1e-8, precision="fp64"), seed=2),
+        _case_with_flow(WL.case_porous(n=5, chi=8, tau=0.65, tol=1e-6, precision="fp32"), seed=3),
+        _case_with_flow(WL.case_porous(n=4, chi=16, tau=0.8, tol=1e-8, precision="fp64"), seed=4),
+        WL.case_tgv(n=4, chi=16, re=100.0, tol=1e-8, precision="fp32"),
+    ]
+    print("uneven batch of 5 (4 groups)", flush=True)
+    b = L.BatchSimulation(cases)
+    b.step(2)
+    multi = [b.dense(d) for d in range(len(cases))]
+    b.close()
+    for d, c in enumerate(cases):
+        s = L.Simulation(c)
+        s.step(2)
+        single = s.dense(L.POPS)
+        s.close()
+        print("domain", d, c.name, "max |multi - single|", float(np.abs(multi[d] - single).max()),
+              flush=True)
+        assert np.array_equal(multi[d], single)
+    for d in (0, 1, 3):
+        m = MPSLBM(cases[d])
+        for _ in range(2):
+            m.step()
+        err = rel(multi[d], m.dense_populations())
+        print("domain", d, "rel vs MPS oracle", err, flush=True)
+        assert err < 1e-10
+    print("uneven batch: graph", flush=True)
+    g = L.BatchSimulation(cases, hip_stream=_hip_stream())
+    e = L.BatchSimulation(cases)
+    g.capture()
+    e.step(1)
+    for r in range(3):
+        g.step(1)
+        e.step(1)
+        for d in range(len(cases)):
+            assert np.array_equal(g.dense(d), e.dense(d)), (r, d)
+    assert g.observables(2).step == 4
+    g.close()
+    e.close()

@@ -304,6 +304,30 @@ def case_tgv(n: int = 5, chi: int = 32, re: float = 800.0, u_lat: float = 0.1,
                                        "steps_per_T0": 2.0 * np.pi * N / (2.0 * np.pi * u_lat)})
 
 
+def c4_cases(count: int = 48, seed: int = 2512 + 4) -> List[Case]:
+    """Many independent domains of mixed size and bond dimension (seeded):
+    N in {32, 64, 128}, chi in {32, 64, 128} capped at the full bond of the
+    grid, tau ~ U[0.55, 0.9], half body-forced channels, half pressure-driven
+    porous media (the porous geometry seeded per case); FP32 storage with
+    BF16X3 contractions at chi 128, FP32 otherwise."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        n = int(rng.choice([5, 6, 7]))
+        full = max(min(8 ** k, 8 ** (n - k)) for k in range(1, n))
+        chi = min(int(rng.choice([32, 64, 128])), full)
+        tau = float(rng.uniform(0.55, 0.9))
+        prec = "bf16x3" if chi == 128 else "fp32"
+        if rng.uniform() < 0.5:
+            c = case_channel(n=n, chi=chi, tau=tau, tol=1e-8, precision=prec)
+        else:
+            c = case_porous(n=n, chi=chi, tau=tau, tol=1e-8, precision=prec,
+                            seed=int(rng.integers(1 << 30)))
+        c.name = f"c4_{i}_{c.name}_chi{chi}"
+        out.append(c)
+    return out
+
+
 def random_flow_state(n: int, seed: int, amp: float = 0.02,
                       drho: float = 0.01, modes: int = 2) -> Tuple[np.ndarray, np.ndarray]:
     """Smooth seeded density/velocity fields (a few random Fourier modes):
