@@ -17,7 +17,8 @@ paper's definition of the operation:
   equation);
 * the variational compressed Hadamard product (Section 2.3, minimization
   equation), single-site, candidate = first factor, sweeping 1 -> n -> 1
-  twice with QR centre shifts;
+  twice with QR centre shifts; the zip-up product, the alternative that
+  Section 2.3 names;
 * the cyclic / non-cyclic shift MPOs assembled from the 2x2 matrices
   I, J, J', P and the rank core product (Section 2.5), padded with
   identities to act on one spatial bit of each site.
@@ -302,6 +303,53 @@ def hadamard_variational(b, c, sweeps: int = 2):
 
 def max_bond(a) -> int:
     return max([x.shape[2] for x in a[:-1]] + [1])
+
+
+def right_canonical(a):
+    """The same tensor with cores 2..n right-orthonormal (sum over the
+    physical index and right bond of A A^T = I), by QR of the transposed
+    unfoldings from the right; the norm ends in the first core."""
+    out = [x.copy() for x in a]
+    for k in range(len(out) - 1, 0, -1):
+        rl, d, rr = out[k].shape
+        Q, R = np.linalg.qr(out[k].reshape(rl, d * rr).T)
+        out[k] = Q.T.reshape(Q.shape[1], d, rr)
+        out[k - 1] = np.einsum("asb,cb->asc", out[k - 1], R)
+    return out
+
+
+def hadamard_zipup(b, c, chi: int, tol: float):
+    """Zip-up product, the alternative to the variational product that
+    Section 2.3 names (after Stoudenmire and White).  From the left, the
+    carried factor L (r x r_b r_c) meets the next pair of cores,
+    Z[a, s, b', c'] = sum_{b,c} L[a, (b, c)] b_k[b, s, b'] c_k[c, s, c'],
+    and a truncated SVD of Z as an (8 r) x (r_b' r_c') matrix gives the
+    output core U (orthonormal columns) and the next carry S V^T; the rank at
+    each cut is the rounding rule with delta^2 = tol^2 ||Z||_F^2 / (n - 1),
+    capped at chi.  The last site keeps Z.  The matrices factored have at most
+    8 chi rows; the exact product (bond r_b r_c) is never formed.  Both
+    factors are first brought to right-canonical form (QR from the right),
+    so that each local SVD sees an orthonormal right part of each factor."""
+    n = len(b)
+    b, c = right_canonical(b), right_canonical(c)
+    L = np.ones((1, 1))
+    out = []
+    for k in range(n):
+        x, y = b[k], c[k]
+        rb, rb1 = x.shape[0], x.shape[2]
+        rc, rc1 = y.shape[0], y.shape[2]
+        r = L.shape[0]
+        Z = np.einsum("abc,bsd,cse->asde", L.reshape(r, rb, rc), x, y)
+        Z = Z.reshape(r * D, rb1 * rc1)
+        if k == n - 1:
+            out.append(Z.reshape(r, D, 1))
+            break
+        U, S, Vt = np.linalg.svd(Z, full_matrices=False)
+        delta2 = tol * tol * float(np.sum(S ** 2)) / (n - 1)
+        rk = rank_rule(S, delta2, chi)
+        out.append(U[:, :rk].reshape(r, D, rk))
+        L = S[:rk, None] * Vt[:rk]
+    return out
 
 
 def product(x, y, sweeps: int = 2):

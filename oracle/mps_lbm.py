@@ -50,7 +50,7 @@ class MPSLBM:
     """CPU MPS-LBM state.  `case` is a workloads.Case."""
 
     def __init__(self, case, inv_mode=INV_TAYLOR2, inv_iters=2, sweeps=2,
-                 f_init=None):
+                 f_init=None, product="variational"):
         self.case = case
         self.lat = get_lattice(int(case.lattice))
         self.n = case.n
@@ -63,6 +63,9 @@ class MPSLBM:
         self.inv_mode = inv_mode
         self.inv_iters = inv_iters
         self.sweeps = sweeps
+        # "variational" (Section 2.3, the method) or "zipup" (the named
+        # alternative, truncated at chi and the rounding tolerance)
+        self.product = product
         self.axis_open = tuple(case.axis_open)
         self.cnt = Counters()
         n = self.n
@@ -156,11 +159,16 @@ class MPSLBM:
 
     def prod(self, x, y):
         self.cnt.products += 1
+        if self.product == "zipup":
+            return M.hadamard_zipup(x, y, self.chi, self.tol)
         return M.product(x, y, self.sweeps)
 
     def prod_first(self, x, y):
-        """Variational product with the first factor as the candidate."""
+        """Variational product with the first factor as the candidate (the
+        zip-up product when chosen)."""
         self.cnt.products += 1
+        if self.product == "zipup":
+            return M.hadamard_zipup(x, y, self.chi, self.tol)
         return M.hadamard_variational(x, y, self.sweeps)
 
     def stream(self, x, c):
