@@ -237,7 +237,7 @@ def main():
                     choices=["jacobi", "householder", "prodgemm", "cholesky"])
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (N=1); "
+        print("bench.py: measures one GPU only (N=1); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import torch
