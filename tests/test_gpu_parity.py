@@ -1007,3 +1007,54 @@ def test_uneven_domains_in_one_handle():
     assert g.observables(2).step == 4
     g.close()
     e.close()
+
+
+def test_per_domain_entry_points_of_an_uneven_handle():
+    """In a handle of several groups, the per-domain calls reach the right
+    domain: a velocity-face profile, a pressure region and the kinetic
+    energy of domains in the second and third groups equal those of their
+    single-domain handles; a constant profile (phi = 1) changes nothing."""
+    L = lib()
+    ramp = (0.0, 1.0, 1.5, 0.0, 0.0, 0.0)
+    cases = [
+        _case_with_flow(WL.case_porous(n=4, chi=16, tau=0.6, tol=1e-8, precision="fp64"), seed=1),
+        _case_with_flow(WL.case_vascular(n=5, chi=16, tau=0.6, tol=1e-8, precision="fp64"), seed=2),
+        _case_with_flow(WL.case_porous(n=5, chi=8, tau=0.65, tol=1e-6, precision="fp32"), seed=3),
+    ]
+    lo, hi = (0, 4, 4), (6, 20, 20)
+    b = L.BatchSimulation(cases)
+    L.mps_lbm_set_face_profile(b.h, 0, ramp, 0.3, domain=1)
+    L.mps_lbm_set_region(b.h, lo, hi, 1.0, domain=2)
+    b.step(3)
+    got = [b.dense(d) for d in range(3)]
+    e1 = L.mps_lbm_kinetic_energy(b.h, 1)
+    o2 = b.observables(2)
+    b.close()
+    s1 = L.Simulation(cases[1])
+    s1.set_face_profile(0, ramp, 0.3)
+    s1.step(3)
+    assert np.array_equal(got[1], s1.dense(L.POPS))
+    assert e1 == s1.kinetic_energy()
+    s1.close()
+    s2 = L.Simulation(cases[2])
+    s2.set_region(lo, hi, 1.0)
+    s2.step(3)
+    o = s2.observables()
+    assert np.array_equal(got[2], s2.dense(L.POPS))
+    assert o2.dp_p0 == o.dp_p0 and o2.region_cells == o.region_cells
+    s2.close()
+    # phi = 1 is the constant face, bitwise
+    c = cases[1]
+    a = L.Simulation(c)
+    a.set_face_profile(0, (1.0, 0.0, 0.0, 0.0, 0.0, 0.0), 0.5)
+    z = L.Simulation(c)
+    a.step(2)
+    z.step(2)
+    assert np.array_equal(a.dense(L.POPS), z.dense(L.POPS))
+    # clearing the profile restores the constant face from the next step on
+    a.set_face_profile(0, None)
+    z.step(1)
+    a.step(1)
+    assert np.array_equal(a.dense(L.POPS), z.dense(L.POPS))
+    a.close()
+    z.close()
