@@ -536,7 +536,16 @@ __global__ __launch_bounds__(256) void k_u2_sum(const T* f, long N3, const int* 
     if (rho != 0.0) acc += (jx * jx + jy * jy + jz * jz) / (rho * rho);
   }
   acc = block_sum(acc, red);
-  if (threadIdx.x == 0) atomicAdd(out, acc);
+  if (threadIdx.x == 0) out[blockIdx.x] = acc;
+}
+
+// out[0] = sum of the n partial sums in index order (one thread: the same
+// order, hence the same bits, on every call)
+__global__ void k_sum_in_order(const double* part, int n, double* out) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < n; ++i) s += part[i];
+  out[0] = s;
 }
 
 // fill kernel (used instead of memset nodes in code that may be captured)
@@ -1089,14 +1098,13 @@ class Engine {
     HIP_OK(hipGetLastError());
   }
   // Truncation eigendecompositions of the cnt problems in ep whose factors
-  // may have 129-256 rows: rows split over JS_PARTS workgroups per problem
-  // (k_jacobi_eig_split), at most JS_LAUNCH problems per launch so that the
-  // workgroups of a launch fit the GPU together.
+  // may have 129-256 rows: column blocks spread over JS_PARTS workgroups per
+  // problem (k_jacobi_eig_split), at most JS_LAUNCH problems per launch so
+  // that the workgroups of a launch fit the GPU together.
   static constexpr int JS_LAUNCH = 32;
   JsSync js{};
   void eig_split(int cnt) {
-    if (!js.part) {
-      js.part = (double*)dalloc(8 * JS_PART_SLOT * JS_LAUNCH);
+    if (!js.nrm) {
       js.nrm = (double*)dalloc(8 * JS_NRM_SLOT * JS_LAUNCH);
       js.count = (unsigned*)dalloc(4 * JS_LAUNCH);
     }

@@ -1802,29 +1802,37 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig(const EigProb* ep, int lds_
 }
 
 // ---------------------------------------------------------------------------
-// The truncation eigendecomposition of a factor of 129 to 256 rows with its
-// rows split over JS_PARTS workgroups, so that every part (64 rows of all c
-// columns) fits LDS.  The round-robin sweeps run in lockstep: in a round
-// each workgroup sums (al, be, ga) of every pair over its rows, publishes
-// them, and after an inter-workgroup barrier adds the JS_PARTS partial sums
-// in a fixed order, so that every part takes the same rotation decisions and
-// angles and rotates its own rows.  Column norms are summed the same way
-// before the shared rank rule; each part writes its rows of U S and
-// Sigma^-1 U^T.  The barrier is a counter per problem (zeroed before the
-// launch) with release / acquire at device scope and a bounded wait: a wait
-// that runs out (workgroups of a problem not resident together) counts as a
-// non-finite result and stops further waiting, so every workgroup exits.
+// The truncation eigendecomposition of a factor of 129 to 256 rows and at
+// most 256 columns, spread over JS_PARTS workgroups per problem.  The
+// columns are cut into JS_BLOCKS blocks of bs = ceil(c / JS_BLOCKS); every
+// workgroup holds two whole blocks (all rows) in LDS.  A sweep is a
+// round-robin tournament of the blocks: in each of its JS_BLOCKS - 1 block
+// rounds every workgroup rotates all column pairs that join its two blocks
+// (in the first block round also the pairs inside each block), in rounds of
+// bs disjoint pairs separated by workgroup barriers only; then the blocks go
+// back to the factor in global memory and, after an inter-workgroup
+// barrier, every workgroup loads its next two blocks.  Every column pair is
+// met once per sweep, as in the cyclic sweep of the single-workgroup kernel.
+// The largest relative off-diagonal of a sweep and the column norms are
+// gathered in the same way, so that every workgroup takes the same decision
+// to stop and the same rank; each workgroup then writes its quarter of the
+// rows of U S and Sigma^-1 U^T.  The barrier is a counter per problem
+// (zeroed before the launch) with release / acquire at device scope and a
+// bounded wait: a wait that runs out (workgroups of a problem not resident
+// together) counts as a non-finite result and stops further waiting, so
+// every workgroup exits.  The factor (p.A) is overwritten.
 constexpr int JS_PARTS = 4;
-constexpr int JS_ROWS = 64;          // rows per part: factors of at most 256 rows
-constexpr int JS_PAIRS = 128;        // pairs per round: at most 256 columns
+constexpr int JS_BLOCKS = 2 * JS_PARTS;
+constexpr int JS_BS = 32;            // columns per block: at most 256 columns
+constexpr int JS_ROWS = 256;         // rows at most
+constexpr int JS_LANES = 32;         // lanes per column pair
 constexpr long JS_SPIN = 1L << 21;   // polls of a barrier wait before it gives up
-constexpr long JS_PART_SLOT = 2L * JS_PARTS * JS_PAIRS * 3;  // per problem
-constexpr long JS_NRM_SLOT = (long)JS_PARTS * 256 + JS_PARTS;  // per problem
+constexpr long JS_NRM_SLOT = 256 + 2 * JS_PARTS;  // per problem
 
 struct JsSync {
-  double* part;       // [problem][2 rounds][JS_PARTS][JS_PAIRS][3]
-  double* nrm;        // [problem]: [JS_PARTS][256] squared column norms of a
-                      // part, then [JS_PARTS] squared Frobenius norms
+  double* nrm;        // [problem]: [256] squared column norms, then
+                      // [JS_PARTS] squared Frobenius norms of the parts'
+                      // first blocks and [JS_PARTS] sweep maxima
   unsigned* count;    // [problem] barrier arrivals
 };
 
@@ -1840,9 +1848,10 @@ __device__ inline double js_load(double* p) {
 }
 
 // every thread calls it; returns false once a wait of this workgroup ran out.
-// Every wave first waits until its own stores (device-scope atomic stores,
-// written through to the device's coherence point) have completed, so that
-// the arrival counted by thread 0 follows all stores of the workgroup.
+// Every wave first waits until its own stores have completed, so that the
+// arrival counted by thread 0 (a release at device scope) follows all
+// stores of the workgroup; the acquire of the last poll makes the other
+// workgroups' stores visible to the whole workgroup.
 __device__ inline bool js_barrier(unsigned* cnt, unsigned target, int* broken) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
@@ -1863,6 +1872,45 @@ __device__ inline bool js_barrier(unsigned* cnt, unsigned target, int* broken) {
   return !*broken;
 }
 
+// the two blocks workgroup w plays in block round t of the tournament of
+// JS_BLOCKS blocks (the circle method: block JS_BLOCKS - 1 stays, the others
+// turn one place per round; every pair of blocks meets once in
+// JS_BLOCKS - 1 rounds)
+__device__ inline void js_match(int t, int w, int& x, int& y) {
+  constexpr int M = JS_BLOCKS - 1;
+  if (w == 0) {
+    x = M;
+    y = t;
+  } else {
+    x = (t + w) % M;
+    y = (t - w + M) % M;
+  }
+}
+
+// Jacobi rotation (cs, sn) that makes the pair with Gram entries al, be, ga
+// orthogonal (the smaller angle), with refined hardware reciprocals
+__device__ inline void js_rotation(double al, double be, double ga, double& cs, double& sn) {
+  const double g2 = 2.0 * ga;
+  double ig = __builtin_amdgcn_rcp(g2);
+  ig = ig * (2.0 - g2 * ig);
+  ig = ig * (2.0 - g2 * ig);
+  const double zeta = (be - al) * ig;
+  const double q1 = 1.0 + zeta * zeta;
+  double rq = __builtin_amdgcn_rsq(q1);
+  rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+  rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+  const double den = fabs(zeta) + q1 * rq;
+  double id = __builtin_amdgcn_rcp(den);
+  id = id * (2.0 - den * id);
+  id = id * (2.0 - den * id);
+  const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+  const double q2 = 1.0 + tt * tt;
+  cs = __builtin_amdgcn_rsq(q2);
+  cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+  cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+  sn = cs * tt;
+}
+
 __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, int nprob,
                                                            JsSync js, int lds_elems,
                                                            int max_sweeps, double* flops,
@@ -1881,8 +1929,8 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   EigProb p = ep[pr];
   if (!p.valid) return;
   const int s = p.s, c = p.c, tid = threadIdx.x;
-  if (s <= 128 || s > JS_PARTS * JS_ROWS || c > 2 * JS_PAIRS || (long)s * c <= lds_elems ||
-      (long)JS_ROWS * c > lds_elems) {
+  if (s <= 128 || s > JS_ROWS || c > JS_BLOCKS * JS_BS || (long)s * c <= lds_elems ||
+      (long)2 * JS_BS * JS_ROWS > lds_elems) {
     // the single-workgroup kernel's cases: the first part does it
     if (part != 0) return;
     if (c > 1024) {
@@ -1899,23 +1947,38 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
     }
     return;
   }
-  double* const jp = js.part + pr * JS_PART_SLOT;
   double* const jn = js.nrm + pr * JS_NRM_SLOT;
+  double* const jf = jn + 256;              // Frobenius norms of the parts
+  double* const jm = jf + JS_PARTS;         // sweep maxima of the parts
   unsigned* const cnt = js.count + pr;
   unsigned gen = 0;
   if (tid == 0) broken = 0;
-  // this part's rows [r0, r0 + nr) of every column, column-major, ld JS_ROWS
-  const int r0 = part * JS_ROWS;
-  const int nr = s - r0 < 0 ? 0 : (s - r0 < JS_ROWS ? s - r0 : JS_ROWS);
-  for (long e = tid; e < (long)JS_ROWS * c; e += blockDim.x) {
-    const int col = (int)(e / JS_ROWS), rr = (int)(e % JS_ROWS);
-    sh[e] = rr < nr ? p.A[(long)col * s + r0 + rr] : 0.0;
-  }
-  // Frobenius norm of the whole factor (for the zero-column test)
+  const int bs = (c + JS_BLOCKS - 1) / JS_BLOCKS;
+  double* const A = p.A;  // column-major, ld s
+  // LDS: local column j (0 <= j < 2 bs) at sh + j * JS_ROWS; the first bs
+  // are block x, the others block y
+  auto gcol = [&](int j, int x, int y) { return j < bs ? x * bs + j : y * bs + (j - bs); };
+  auto load_blocks = [&](int x, int y) {
+    for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) {
+      const int j = e / JS_ROWS, row = e % JS_ROWS, col = gcol(j, x, y);
+      sh[e] = (row < s && col < c) ? A[(long)col * s + row] : 0.0;
+    }
+  };
+  auto store_blocks = [&](int x, int y) {
+    for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) {
+      const int j = e / JS_ROWS, row = e % JS_ROWS, col = gcol(j, x, y);
+      if (row < s && col < c) A[(long)col * s + row] = sh[e];
+    }
+  };
+  int x, y;
+  js_match(0, part, x, y);
+  load_blocks(x, y);
+  __syncthreads();
+  // Frobenius norm of the whole factor (for the zero-column test): the
+  // parts' first blocks cover every column once
   double fro2 = 0.0;
-  for (long e = tid; e < (long)JS_ROWS * c; e += blockDim.x) fro2 += sh[e] * sh[e];
+  for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) fro2 += sh[e] * sh[e];
   fro2 = block_sum(fro2, red);
-  double* const jf = jn + (long)JS_PARTS * 256;
   if (tid == 0) js_store(jf + part, fro2);
   js_barrier(cnt, JS_PARTS * (++gen), &broken);
   fro2 = 0.0;
@@ -1923,117 +1986,122 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   const double eps = 2.220446049250313e-16;
   const double small2 = eps * eps * fro2;
   const double tol = orth_tol > 0.0 ? orth_tol : eps * sqrt((double)s);
-  constexpr int G = 8, RPL = JS_ROWS / G;
-  const int lane = tid & 63, wv = tid >> 6, gl = lane % G;
-  const int k = wv * (64 / G) + lane / G;  // this group's pair of a round
-  const int P = (c % 2) ? c + 1 : c;
+  constexpr int RPL = JS_ROWS / JS_LANES;
+  const int gl = tid % JS_LANES;
+  const int k = tid / JS_LANES;  // this group's pair of a round
   double work = 0.0;
   int sweep = 0;
+  bool loaded = true;  // the blocks of block round 0 are in LDS
   for (; sweep < max_sweeps && c > 1; ++sweep) {
     if (tid == 0) flag = 0;
     __syncthreads();
     float mx = 0.0f;
-    for (int t = 0; t < P - 1; ++t) {
-      int i1 = c, i2 = c;
-      if (k < P / 2) {
-        if (k == 0) {
-          i1 = t; i2 = P - 1;
-        } else {
-          i1 = t + k;
-          if (i1 >= P - 1) i1 -= P - 1;
-          i2 = t - k;
-          if (i2 < 0) i2 += P - 1;
+    for (int br = 0; br < JS_BLOCKS - 1; ++br) {
+      js_match(br, part, x, y);
+      if (!loaded) {
+        load_blocks(x, y);
+        __syncthreads();
+      }
+      loaded = false;
+      // block round 0: the circle method over all 2 bs local columns;
+      // later rounds: pair i joins x_i and y_((i + t) mod bs)
+      const int P = 2 * bs;
+      const int nr = br == 0 ? P - 1 : bs;
+      for (int t = 0; t < nr; ++t) {
+        int i1 = P, i2 = P;
+        if (k < bs) {
+          if (br == 0) {
+            if (k == 0) {
+              i1 = t; i2 = P - 1;
+            } else {
+              i1 = t + k;
+              if (i1 >= P - 1) i1 -= P - 1;
+              i2 = t - k;
+              if (i2 < 0) i2 += P - 1;
+            }
+          } else {
+            i1 = k;
+            i2 = bs + (k + t) % bs;
+          }
         }
-      }
-      const bool act = i1 < c && i2 < c;
-      const int a = act ? (i1 < i2 ? i1 : i2) : 0, bb = act ? (i1 < i2 ? i2 : i1) : 0;
-      double* ca = sh + (long)a * JS_ROWS;
-      double* cb = sh + (long)bb * JS_ROWS;
-      double xr[RPL], yr[RPL];
-      double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-      for (int q = 0; q < RPL; ++q) {
-        xr[q] = act ? ca[gl + q * G] : 0.0;
-        yr[q] = act ? cb[gl + q * G] : 0.0;
-        al += xr[q] * xr[q];
-        be += yr[q] * yr[q];
-        ga += xr[q] * yr[q];
-      }
-      al = group_sum(al, G); be = group_sum(be, G); ga = group_sum(ga, G);
-      double* slot = jp + (long)(gen & 1) * JS_PARTS * JS_PAIRS * 3;
-      if (act && gl == 0) {
-        double* o = slot + ((long)part * JS_PAIRS + k) * 3;
-        js_store(o, al);
-        js_store(o + 1, be);
-        js_store(o + 2, ga);
-      }
-      js_barrier(cnt, JS_PARTS * (++gen), &broken);
-      if (act) {
-        al = 0.0; be = 0.0; ga = 0.0;
-        for (int q = 0; q < JS_PARTS; ++q) {
-          double* o = slot + ((long)q * JS_PAIRS + k) * 3;
-          al += js_load(o);
-          be += js_load(o + 1);
-          ga += js_load(o + 2);
-        }
-        if (gl == 0) work += 6.0 * s;
-        const bool rotate = ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 &&
-                            be > small2;
-        if (rotate) {
-          mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
-          const double g2 = 2.0 * ga;
-          double ig = __builtin_amdgcn_rcp(g2);
-          ig = ig * (2.0 - g2 * ig);
-          ig = ig * (2.0 - g2 * ig);
-          const double zeta = (be - al) * ig;
-          const double q1 = 1.0 + zeta * zeta;
-          double rq = __builtin_amdgcn_rsq(q1);
-          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
-          rq = rq * (1.5 - 0.5 * q1 * rq * rq);
-          const double den = fabs(zeta) + q1 * rq;
-          double id = __builtin_amdgcn_rcp(den);
-          id = id * (2.0 - den * id);
-          id = id * (2.0 - den * id);
-          const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
-          const double q2 = 1.0 + tt * tt;
-          double cs = __builtin_amdgcn_rsq(q2);
-          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
-          cs = cs * (1.5 - 0.5 * q2 * cs * cs);
-          const double sn = cs * tt;
+        const bool act = i1 < P && i2 < P && gcol(i1, x, y) < c && gcol(i2, x, y) < c;
+        if (act) {
+          // the pair in global column order, as in the cyclic sweep
+          int a = i1, bb = i2;
+          if (gcol(a, x, y) > gcol(bb, x, y)) {
+            a = i2;
+            bb = i1;
+          }
+          double* ca = sh + (long)a * JS_ROWS;
+          double* cb = sh + (long)bb * JS_ROWS;
+          double xr[RPL], yr[RPL];
+          double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
           for (int q = 0; q < RPL; ++q) {
-            ca[gl + q * G] = cs * xr[q] - sn * yr[q];
-            cb[gl + q * G] = sn * xr[q] + cs * yr[q];
+            xr[q] = ca[gl + q * JS_LANES];
+            yr[q] = cb[gl + q * JS_LANES];
+            al += xr[q] * xr[q];
+            be += yr[q] * yr[q];
+            ga += xr[q] * yr[q];
           }
+          al = group_sum(al, JS_LANES);
+          be = group_sum(be, JS_LANES);
+          ga = group_sum(ga, JS_LANES);
           if (gl == 0) work += 6.0 * s;
+          const bool rotate = ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 &&
+                              be > small2;
+          if (rotate) {
+            mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
+            double cs, sn;
+            js_rotation(al, be, ga, cs, sn);
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) {
+              ca[gl + q * JS_LANES] = cs * xr[q] - sn * yr[q];
+              cb[gl + q * JS_LANES] = sn * xr[q] + cs * yr[q];
+            }
+            if (gl == 0) work += 6.0 * s;
+          }
         }
+        __syncthreads();
       }
-      __syncthreads();
+      store_blocks(x, y);
+      if (br == JS_BLOCKS - 2) {
+        // this sweep's largest relative off-diagonal, gathered with the blocks
+        if (mx > 0.0f) atomicMax(&flag, __float_as_int(mx));
+        __syncthreads();
+        if (tid == 0) js_store(jm + part, (double)__int_as_float(flag));
+      }
+      js_barrier(cnt, JS_PARTS * (++gen), &broken);
     }
-    // the same pairs and sums in every part: the same decisions
-    if (mx > 0.0f) atomicMax(&flag, __float_as_int(mx));
-    __syncthreads();
-    const int any = flag;
-    __syncthreads();
-    if (!any) break;
-    if (__int_as_float(any) < (float)(0.1 * sqrt(tol))) {
+    float any = 0.0f;
+    for (int q = 0; q < JS_PARTS; ++q) any = fmaxf(any, (float)js_load(jm + q));
+    if (!(any > 0.0f)) break;
+    if (any < (float)(0.1 * sqrt(tol))) {
       ++sweep;
       break;
     }
   }
-  // column norms: this part's squared sums, then all parts in a fixed order
-  for (int col = wv; col < c; col += (int)(blockDim.x >> 6)) {
-    const double v = sh[(long)col * JS_ROWS + lane];
-    const double acc = wave_sum(v * v);
-    if (lane == 0) js_store(jn + (long)part * 256 + col, acc);
+  // column norms from the factor in global memory (every block went back
+  // before the last barrier): part q sums the columns of its first block
+  // round, each column once
+  js_match(0, part, x, y);
+  const int wv = tid >> 6, lane = tid & 63;
+  for (int j = wv; j < 2 * bs; j += (int)(blockDim.x >> 6)) {
+    const int col = gcol(j, x, y);
+    if (col >= c) continue;
+    double acc = 0.0;
+    for (int row = lane; row < s; row += 64) {
+      const double v = A[(long)col * s + row];
+      acc += v * v;
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) js_store(jn + col, acc);
   }
   const bool ok = js_barrier(cnt, JS_PARTS * (++gen), &broken);
   if (tid == 0) nonfin = ok ? 0 : 1;
   __syncthreads();
   for (int col = tid; col < c; col += blockDim.x) {
-    double acc = 0.0;
-    for (int q = 0; q < JS_PARTS; ++q) acc += js_load(jn + (long)q * 256 + col);
-    double v = sqrt(acc);
+    double v = sqrt(js_load(jn + col));
     if (!(v <= 1.7976931348623157e308)) {
       nonfin = 1;
       v = -1.0;
@@ -2075,7 +2143,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
       atomicAdd(p.fail + 1, 1);
     }
   }
-  if (part == 0 && flops && tid % G == 0 && work > 0.0) atomicAdd(flops, work);
+  if (flops && gl == 0 && work > 0.0) atomicAdd(flops, work);
   __syncthreads();
   const int r = rsel;
   if (part == 0 && p.feat && tid <= 32) {
@@ -2088,11 +2156,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
     }
     p.feat[tid] = f;
   }
-  // this part's rows of U S (s x r) and Sigma^-1 U^T (r x s)
-  for (long e = tid; e < (long)nr * r; e += blockDim.x) {
+  // this part's quarter of the rows of U S (s x r) and Sigma^-1 U^T (r x s)
+  const int rq = (s + JS_PARTS - 1) / JS_PARTS;
+  const int r0 = part * rq;
+  const int nrow = s - r0 < 0 ? 0 : (s - r0 < rq ? s - r0 : rq);
+  for (long e = tid; e < (long)nrow * r; e += blockDim.x) {
     const int rr = (int)(e / r), j = (int)(e % r), row = r0 + rr;
     const double sg = nrm[perm[j]];
-    const double g = sh[(long)perm[j] * JS_ROWS + rr];
+    const double g = A[(long)perm[j] * s + row];
     p.US[(long)row * r + j] = g;
     p.Ut[(long)j * s + row] = sg > 0.0 ? g / (sg * sg) : 0.0;
   }

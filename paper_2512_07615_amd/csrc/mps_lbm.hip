@@ -376,12 +376,18 @@ struct SimT : Sim {
     T* back = (T*)E.dalloc(sizeof(T) * N3);
     T* work = (T*)E.dalloc(sizeof(T) * N3);
     E.to_dense({obj}, back, work);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, sbuf, 0.0, 2L);
-    hipLaunchKernelGGL(k_diff_norm<T>, dim3(std::min(256, dense_chunks(N3))), dim3(256), 0, st,
-                       (const T*)back, Wref, N3, sbuf);
+    // per-block partial sums, then their sums in a fixed order
+    const int nb = std::min(256, dense_chunks(N3));
+    double* part = (double*)E.dalloc(8 * 2 * nb);
+    hipLaunchKernelGGL(k_diff_norm<T>, dim3(nb), dim3(256), 0, st, (const T*)back, Wref, N3,
+                       part);
+    hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, st, (const double*)part, nb, sbuf);
+    hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, st, (const double*)(part + nb), nb,
+                       sbuf + 1);
     double hnorm[2];
     HIP_OK(hipMemcpyAsync(hnorm, sbuf, 16, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));
+    E.free_alloc(part);
     E.free_alloc(work);
     E.free_alloc(back);
     return hnorm[1] > 0 ? std::sqrt(hnorm[0] / hnorm[1]) : 0.0;
@@ -1055,12 +1061,14 @@ struct SimT : Sim {
     };
     T* buf = (T*)tdalloc(sizeof(T) * N3 * Q);
     T* work = (T*)tdalloc(sizeof(T) * N3 * Q);
-    double* acc = (double*)tdalloc(8);
+    const int nb = std::min(1024, dense_chunks(N3));
+    double* acc = (double*)tdalloc(8 * (nb + 1));
     std::vector<int> objs(dom[d].f, dom[d].f + Q);
     E.to_dense(objs, buf, work);
-    hipLaunchKernelGGL(k_fill_f64, dim3(1), dim3(64), 0, st, acc, 0.0, 1L);
-    hipLaunchKernelGGL(k_u2_sum<T>, dim3(std::min(1024, dense_chunks(N3))), dim3(256), 0, st,
-                       (const T*)buf, N3, (const int*)cvec_dev, Q, acc);
+    // per-block partial sums, then their sum in a fixed order
+    hipLaunchKernelGGL(k_u2_sum<T>, dim3(nb), dim3(256), 0, st, (const T*)buf, N3,
+                       (const int*)cvec_dev, Q, acc + 1);
+    hipLaunchKernelGGL(k_sum_in_order, dim3(1), dim3(64), 0, st, (const double*)(acc + 1), nb, acc);
     double s = 0.0;
     HIP_OK(hipMemcpyAsync(&s, acc, 8, hipMemcpyDeviceToHost, st));
     HIP_OK(hipStreamSynchronize(st));

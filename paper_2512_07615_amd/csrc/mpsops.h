@@ -394,7 +394,8 @@ __global__ void k_nonfinite(MpsList<T> src, int* flag) {
 }  // namespace mpslbm
 
 namespace mpslbm {
-// sum over entries of (a - b)^2 and b^2 (FP64) for the mask decomposition error
+// per-block sums over entries of (a - b)^2 (out[block]) and b^2
+// (out[gridDim.x + block]), FP64, for the mask decomposition error
 template <typename T>
 __global__ __launch_bounds__(256) void k_diff_norm(const T* a, const T* b, long count,
                                                    double* out) {
@@ -409,8 +410,8 @@ __global__ __launch_bounds__(256) void k_diff_norm(const T* a, const T* b, long 
   d = block_sum(d, red);
   q = block_sum(q, red);
   if (threadIdx.x == 0) {
-    atomicAdd(out, d);
-    atomicAdd(out + 1, q);
+    out[blockIdx.x] = d;
+    out[gridDim.x + blockIdx.x] = q;
   }
 }
 }  // namespace mpslbm
