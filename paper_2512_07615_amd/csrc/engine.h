@@ -892,6 +892,7 @@ class Engine {
   long estride = 0, tcap = 0;  // product workspaces per problem (largest profile)
   long ws_env = 0, ws_t = 0;     // elements allocated for envL/envR and T1/T2
   int lds_elems = 8000;
+  int js_elems = 8000;  // dynamic LDS (doubles) of k_jacobi_eig_split
   std::vector<Mps<T>> pool;
   std::vector<int> freelist;
   std::vector<void*> allocs;
@@ -1112,8 +1113,8 @@ class Engine {
       const int c = std::min(JS_LAUNCH, cnt - off);
       hipLaunchKernelGGL(k_js_reset, dim3(1), dim3(64), 0, st, js.count, c);
       const int blocks = ((c + 7) / 8) * 8 * JS_PARTS;
-      hipLaunchKernelGGL(k_jacobi_eig_split, dim3(blocks), dim3(1024), (size_t)lds_elems * 8, st,
-                         (const EigProb*)(ep + off), c, js, lds_elems, 40, kf(1), eig_orth_tol);
+      hipLaunchKernelGGL(k_jacobi_eig_split, dim3(blocks), dim3(JS_THREADS), (size_t)js_elems * 8,
+                         st, (const EigProb*)(ep + off), c, js, js_elems, 40, kf(1), eig_orth_tol);
     }
     HIP_OK(hipGetLastError());
   }
@@ -1253,6 +1254,16 @@ class Engine {
       (void)hipGetLastError();
       lds_elems = (65536 - 16384) / 8;
     }
+    // the split eigendecomposition holds two padded column blocks; below
+    // that it runs the single-workgroup body on its first part
+    js_elems = lds_elems;
+    const long js_need = 2L * JS_BS * JS_LD;
+    if (js_need > lds_elems && js_need * 8 + 16384 <= lds &&
+        hipFuncSetAttribute((const void*)k_jacobi_eig_split,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(js_need * 8)) == hipSuccess)
+      js_elems = (int)js_need;
+    (void)hipGetLastError();
     for (int i = 0; i < npool; ++i) pool.push_back(make_mps(capb));
     freelist.clear();
     for (int i = npool - 1; i >= 0; --i) freelist.push_back(i);

@@ -723,26 +723,45 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
       __syncthreads();
       break;
     }
-    // trailing update G -= L L^T of the unpivoted rows and columns, one
-    // 16 x 16 tile per wave at a time on FP64 MFMA (layouts as in
-    // chol_blocked); tiles holding no unpivoted row are skipped
+    // trailing update G -= L L^T of the unpivoted rows and columns, 16 x 16
+    // tiles on FP64 MFMA (layouts as in chol_blocked); a wave first loads
+    // the entries of TU tiles, so that TU global reads are in flight at
+    // once, then updates and stores them
     typedef double dv4 __attribute__((ext_vector_type(4)));
-    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4;
-    for (int t = wv; t < nb * nb; t += nw) {
-      const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
-      const int ar = a0 + l16, bc = b0 + l16;
-      dv4 acc = {0.0, 0.0, 0.0, 0.0};
+    constexpr int TU = 4;
+    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = nb * nb;
+    for (int t0 = wv; t0 < ntile; t0 += nw * TU) {
+      double gv[TU][4];
 #pragma unroll
-      for (int q0 = 0; q0 < CPB; q0 += 4) {
-        const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
-        const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
-      }
-      if (bc < n && posn[bc] == n) {
+      for (int u = 0; u < TU; ++u) {
+        const int t = t0 + u * nw;
+        const int a0 = (t / nb) * 16, bc = (t % nb) * 16 + l16;
+        const bool okc = t < ntile && bc < n && posn[bc] == n;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a = a0 + lq + 4 * v;
-          if (a < n && posn[a] == n) G[(long)a * n + bc] -= acc[v];
+          gv[u][v] = (okc && a < n && posn[a] == n) ? G[(long)a * n + bc] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < TU; ++u) {
+        const int t = t0 + u * nw;  // the same in every lane of the wave
+        if (t >= ntile) break;
+        const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
+        const int ar = a0 + l16, bc = b0 + l16;
+        dv4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int q0 = 0; q0 < CPB; q0 += 4) {
+          const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
+          const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
+        }
+        if (bc < n && posn[bc] == n) {
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int a = a0 + lq + 4 * v;
+            if (a < n && posn[a] == n) G[(long)a * n + bc] = gv[u][v] - acc[v];
+          }
         }
       }
     }
@@ -1825,7 +1844,11 @@ constexpr int JS_PARTS = 4;
 constexpr int JS_BLOCKS = 2 * JS_PARTS;
 constexpr int JS_BS = 32;            // columns per block: at most 256 columns
 constexpr int JS_ROWS = 256;         // rows at most
-constexpr int JS_LANES = 32;         // lanes per column pair
+// LDS stride of a column: 16 doubles (128 bytes) of padding put the columns
+// of neighbouring lane groups on different LDS banks
+constexpr int JS_LD = JS_ROWS + 16;
+constexpr int JS_LANES = 16;         // lanes per column pair
+constexpr int JS_THREADS = JS_BS * JS_LANES;  // one group of lanes per pair
 constexpr long JS_SPIN = 1L << 21;   // polls of a barrier wait before it gives up
 constexpr long JS_NRM_SLOT = 256 + 2 * JS_PARTS;  // per problem
 
@@ -1911,7 +1934,7 @@ __device__ inline void js_rotation(double al, double be, double ga, double& cs, 
   sn = cs * tt;
 }
 
-__global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, int nprob,
+__global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* ep, int nprob,
                                                            JsSync js, int lds_elems,
                                                            int max_sweeps, double* flops,
                                                            double orth_tol) {
@@ -1920,6 +1943,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   __shared__ int perm[1024];
   __shared__ double nrm[1024];
   __shared__ double red[16];
+  __shared__ double tn[2 * JS_BS];  // carried squared norms of the local columns
   // the parts of a problem are 8 workgroups apart (the same XCD when
   // workgroups are dealt round-robin to the 8 XCDs)
   const int b = blockIdx.x;
@@ -1930,7 +1954,7 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   if (!p.valid) return;
   const int s = p.s, c = p.c, tid = threadIdx.x;
   if (s <= 128 || s > JS_ROWS || c > JS_BLOCKS * JS_BS || (long)s * c <= lds_elems ||
-      (long)2 * JS_BS * JS_ROWS > lds_elems) {
+      (long)2 * JS_BS * JS_LD > lds_elems) {
     // the single-workgroup kernel's cases: the first part does it
     if (part != 0) return;
     if (c > 1024) {
@@ -1955,19 +1979,19 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   if (tid == 0) broken = 0;
   const int bs = (c + JS_BLOCKS - 1) / JS_BLOCKS;
   double* const A = p.A;  // column-major, ld s
-  // LDS: local column j (0 <= j < 2 bs) at sh + j * JS_ROWS; the first bs
+  // LDS: local column j (0 <= j < 2 bs) at sh + j * JS_LD; the first bs
   // are block x, the others block y
   auto gcol = [&](int j, int x, int y) { return j < bs ? x * bs + j : y * bs + (j - bs); };
   auto load_blocks = [&](int x, int y) {
     for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) {
       const int j = e / JS_ROWS, row = e % JS_ROWS, col = gcol(j, x, y);
-      sh[e] = (row < s && col < c) ? A[(long)col * s + row] : 0.0;
+      sh[j * JS_LD + row] = (row < s && col < c) ? A[(long)col * s + row] : 0.0;
     }
   };
   auto store_blocks = [&](int x, int y) {
     for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) {
       const int j = e / JS_ROWS, row = e % JS_ROWS, col = gcol(j, x, y);
-      if (row < s && col < c) A[(long)col * s + row] = sh[e];
+      if (row < s && col < c) A[(long)col * s + row] = sh[j * JS_LD + row];
     }
   };
   int x, y;
@@ -1977,7 +2001,10 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   // Frobenius norm of the whole factor (for the zero-column test): the
   // parts' first blocks cover every column once
   double fro2 = 0.0;
-  for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) fro2 += sh[e] * sh[e];
+  for (int e = tid; e < 2 * bs * JS_ROWS; e += blockDim.x) {
+    const double v = sh[(e / JS_ROWS) * JS_LD + e % JS_ROWS];
+    fro2 += v * v;
+  }
   fro2 = block_sum(fro2, red);
   if (tid == 0) js_store(jf + part, fro2);
   js_barrier(cnt, JS_PARTS * (++gen), &broken);
@@ -1988,14 +2015,145 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
   const double tol = orth_tol > 0.0 ? orth_tol : eps * sqrt((double)s);
   constexpr int RPL = JS_ROWS / JS_LANES;
   const int gl = tid % JS_LANES;
-  const int k = tid / JS_LANES;  // this group's pair of a round
+  const int g = tid / JS_LANES;  // this lane's group
   double work = 0.0;
   int sweep = 0;
   bool loaded = true;  // the blocks of block round 0 are in LDS
+  // the intra-block phases run on a virtual layout with each block padded
+  // to bp columns (a power of two): virtual v < bp is x_v, bp <= v < 2 bp is
+  // y_(v - bp); local column or -1 (padding, or beyond the c columns)
+  int bp = 1;
+  while (bp < bs) bp <<= 1;
+  float mx = 0.0f;  // largest relative coupling this thread rotated away
+  // One phase of the recursive-halving ordering (as in the single-workgroup
+  // ring sweeps): group g = j h + u keeps virtual column j S + u in
+  // registers and meets j S + h + (u + t) mod h for t = 0 .. h - 1, which
+  // travel through LDS; squared norms are carried through the rotations
+  // (tn, from an exact sum where a phase first meets a column), with an
+  // exact sum where an update cancels digits.
+  auto phase = [&](int S, int h, int V, bool intra) {
+    auto lmap = [&](int v) {
+      int l = v;
+      if (intra) {
+        const int blk = v / bp, o = v % bp;
+        l = o < bs ? blk * bs + o : -1;
+      }
+      return (l >= 0 && l < 2 * bs && gcol(l, x, y) < c) ? l : -1;
+    };
+    const int j = g / h, u = g % h;
+    const bool live = (j + 1) * S <= V;
+    const int ri = live ? lmap(j * S + u) : -1;
+    double xr[RPL];
+    double al = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      xr[q] = ri >= 0 ? sh[ri * JS_LD + gl + q * JS_LANES] : 0.0;
+      al += xr[q] * xr[q];
+    }
+    al = group_sum(al, JS_LANES);
+    for (int t = 0; t < h; ++t) {
+      int v = u + t;
+      if (v >= h) v -= h;
+      const int ti = live ? lmap(j * S + h + v) : -1;
+      const bool act = ri >= 0 && ti >= 0;
+      double yr[RPL];
+      double ga = 0.0, ga2 = 0.0, be = 0.0;
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) {
+        yr[q] = ti >= 0 ? sh[ti * JS_LD + gl + q * JS_LANES] : 0.0;
+        if (q & 1)
+          ga2 += xr[q] * yr[q];
+        else
+          ga += xr[q] * yr[q];
+      }
+      if (t == 0) {
+        // the first meeting of this traveller in the phase: its exact norm
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) be += yr[q] * yr[q];
+        be = group_sum(be, JS_LANES);
+        if (ti >= 0 && gl == 0) {
+          tn[ti] = be;
+          work += 2.0 * s;
+        }
+      } else {
+        be = ti >= 0 ? tn[ti] : 0.0;
+      }
+      ga = group_sum(ga + ga2, JS_LANES);
+      if (act && gl == 0) work += 2.0 * s;
+      if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
+        mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
+        // the pair in global column order, as in the cyclic sweep
+        const bool rfirst = gcol(ri, x, y) < gcol(ti, x, y);
+        const double aa = rfirst ? al : be, bb = rfirst ? be : al;
+        // one Newton-Raphson step on each hardware estimate (relative error
+        // about 5e-8 on gfx950) leaves the angle within 5e-15; the cosine
+        // gets two, so that the rotation stays orthogonal to FP64 rounding
+        const double g2 = 2.0 * ga;
+        double ig = __builtin_amdgcn_rcp(g2);
+        ig = ig * (2.0 - g2 * ig);
+        const double zeta = (bb - aa) * ig;
+        const double q1 = 1.0 + zeta * zeta;
+        double rq = __builtin_amdgcn_rsq(q1);
+        rq = rq * (1.5 - 0.5 * q1 * rq * rq);
+        const double den = fabs(zeta) + q1 * rq;
+        double id = __builtin_amdgcn_rcp(den);
+        id = id * (2.0 - den * id);
+        const double tt = (zeta >= 0 ? 1.0 : -1.0) * id;
+        const double q2 = 1.0 + tt * tt;
+        double cs = __builtin_amdgcn_rsq(q2);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        cs = cs * (1.5 - 0.5 * q2 * cs * cs);
+        const double sn = cs * tt;
+        // first' = cs first - sn second, second' = sn first + cs second
+        const double sx = rfirst ? -sn : sn;  // resident' = cs x + sx y
+        const double sy = rfirst ? sn : -sn;  // traveller' = sy x + cs y
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+          const double xo = xr[q], yo = yr[q];
+          xr[q] = cs * xo + sx * yo;
+          yr[q] = sy * xo + cs * yo;
+        }
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) sh[ti * JS_LD + gl + q * JS_LANES] = yr[q];
+        // new squared norms from the 2 x 2 rotation: first' = aa - tt ga,
+        // second' = bb + tt ga; where one drops below 1e-3 of its old value
+        // the update has cancelled digits and the norm is summed again
+        const double na = rfirst ? aa - tt * ga : bb + tt * ga;
+        const double nb = rfirst ? bb + tt * ga : aa - tt * ga;
+        if (!(na >= 1e-3 * al)) {
+          double w = 0.0;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) w += xr[q] * xr[q];
+          al = group_sum(w, JS_LANES);
+          if (gl == 0) work += 2.0 * s;
+        } else {
+          al = na;
+        }
+        double nbe = nb;
+        if (!(nb >= 1e-3 * be)) {
+          double w = 0.0;
+#pragma unroll
+          for (int q = 0; q < RPL; ++q) w += yr[q] * yr[q];
+          nbe = group_sum(w, JS_LANES);
+          if (gl == 0) work += 2.0 * s;
+        }
+        if (gl == 0) {
+          tn[ti] = nbe;
+          work += 6.0 * s;
+        }
+      }
+      __syncthreads();
+    }
+    if (ri >= 0) {
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) sh[ri * JS_LD + gl + q * JS_LANES] = xr[q];
+    }
+    __syncthreads();
+  };
   for (; sweep < max_sweeps && c > 1; ++sweep) {
     if (tid == 0) flag = 0;
     __syncthreads();
-    float mx = 0.0f;
+    mx = 0.0f;
     for (int br = 0; br < JS_BLOCKS - 1; ++br) {
       js_match(br, part, x, y);
       if (!loaded) {
@@ -2003,70 +2161,14 @@ __global__ __launch_bounds__(1024) void k_jacobi_eig_split(const EigProb* ep, in
         __syncthreads();
       }
       loaded = false;
-      // block round 0: the circle method over all 2 bs local columns;
-      // later rounds: pair i joins x_i and y_((i + t) mod bs)
-      const int P = 2 * bs;
-      const int nr = br == 0 ? P - 1 : bs;
-      for (int t = 0; t < nr; ++t) {
-        int i1 = P, i2 = P;
-        if (k < bs) {
-          if (br == 0) {
-            if (k == 0) {
-              i1 = t; i2 = P - 1;
-            } else {
-              i1 = t + k;
-              if (i1 >= P - 1) i1 -= P - 1;
-              i2 = t - k;
-              if (i2 < 0) i2 += P - 1;
-            }
-          } else {
-            i1 = k;
-            i2 = bs + (k + t) % bs;
-          }
-        }
-        const bool act = i1 < P && i2 < P && gcol(i1, x, y) < c && gcol(i2, x, y) < c;
-        if (act) {
-          // the pair in global column order, as in the cyclic sweep
-          int a = i1, bb = i2;
-          if (gcol(a, x, y) > gcol(bb, x, y)) {
-            a = i2;
-            bb = i1;
-          }
-          double* ca = sh + (long)a * JS_ROWS;
-          double* cb = sh + (long)bb * JS_ROWS;
-          double xr[RPL], yr[RPL];
-          double al = 0.0, be = 0.0, ga = 0.0;
-#pragma unroll
-          for (int q = 0; q < RPL; ++q) {
-            xr[q] = ca[gl + q * JS_LANES];
-            yr[q] = cb[gl + q * JS_LANES];
-            al += xr[q] * xr[q];
-            be += yr[q] * yr[q];
-            ga += xr[q] * yr[q];
-          }
-          al = group_sum(al, JS_LANES);
-          be = group_sum(be, JS_LANES);
-          ga = group_sum(ga, JS_LANES);
-          if (gl == 0) work += 6.0 * s;
-          const bool rotate = ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 &&
-                              be > small2;
-          if (rotate) {
-            mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
-            double cs, sn;
-            js_rotation(al, be, ga, cs, sn);
-#pragma unroll
-            for (int q = 0; q < RPL; ++q) {
-              ca[gl + q * JS_LANES] = cs * xr[q] - sn * yr[q];
-              cb[gl + q * JS_LANES] = sn * xr[q] + cs * yr[q];
-            }
-            if (gl == 0) work += 6.0 * s;
-          }
-        }
-        __syncthreads();
-      }
+      // every pair of an x column and a y column; in the first block round
+      // of a sweep also the pairs inside each block
+      phase(2 * bs, bs, 2 * bs, false);
+      if (br == 0)
+        for (int S = bp; S >= 2; S >>= 1) phase(S, S / 2, 2 * bp, true);
       store_blocks(x, y);
       if (br == JS_BLOCKS - 2) {
-        // this sweep's largest relative off-diagonal, gathered with the blocks
+        // this sweep's largest relative coupling, gathered with the blocks
         if (mx > 0.0f) atomicMax(&flag, __float_as_int(mx));
         __syncthreads();
         if (tid == 0) js_store(jm + part, (double)__int_as_float(flag));
