@@ -67,12 +67,9 @@ template <> struct MfmaT<float> {
 constexpr int GT = 64;   // tile edge
 constexpr int GK = 64;   // K slice staged through LDS per step
 
-// Round to nearest even BF16 (bit pattern) and back.
-__device__ inline short bf16_bits(float f) {
-  unsigned u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
-  return (short)(u >> 16);
-}
+// Round to nearest even BF16 (bit pattern: gfx950's v_cvt_pk_bf16_f32)
+// and back.
+__device__ inline short bf16_bits(float f) { return __builtin_bit_cast(short, (__bf16)f); }
 __device__ inline float bf16_value(short b) {
   return __uint_as_float(((unsigned)(unsigned short)b) << 16);
 }
@@ -162,45 +159,82 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   // is paid once per GK = 64 columns of K rather than per instruction.
   constexpr int LQ = GT * GK / 256;  // elements of each operand per thread
   Tacc ra[LQ], rb[LQ];
+  // Element q of this thread's share of a slice.  FP32/FP64 (MODE 0): one
+  // element per 256 threads, the contiguous index fastest.  BF16 modes:
+  // four runs of four consecutive K values of one row of A or column of B
+  // (q = 4 i + j), so that the converted terms go to LDS as 8-byte writes;
+  // lanes still walk the contiguous index of the operand.
+  auto a_pos = [&](int q, int& mm, int& kk) {
+    if constexpr (MODE == 0) {
+      const int e = tid + 256 * q;
+      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
+    } else {
+      const int i = q >> 2, j = q & 3;
+      if (a_k_contig) { mm = (tid >> 4) + 16 * i; kk = 4 * (tid & 15) + j; }
+      else { mm = tid & 63; kk = 4 * (tid >> 6) + 16 * i + j; }
+    }
+  };
+  auto b_pos = [&](int q, int& nn, int& kb) {
+    if constexpr (MODE == 0) {
+      const int e = tid + 256 * q;
+      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
+    } else {
+      const int i = q >> 2, j = q & 3;
+      if (b_n_contig) { nn = tid & 63; kb = 4 * (tid >> 6) + 16 * i + j; }
+      else { nn = (tid >> 4) + 16 * i; kb = 4 * (tid & 15) + j; }
+    }
+  };
   auto fetch = [&](int k0) {
 #pragma unroll
     for (int q = 0; q < LQ; ++q) {
-      const int e = tid + 256 * q;
       int mm, kk;
-      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
+      a_pos(q, mm, kk);
       const int gm = m0 + mm, gk = k0 + kk;
       ra[q] = (gm < d.M && gk < ke) ? (Tacc)A[gm * d.sAm + gk * d.sAk] : (Tacc)0;
       int nn, kb;
-      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
+      b_pos(q, nn, kb);
       const int gn = n0 + nn, gk2 = k0 + kb;
       rb[q] = (gn < d.N && gk2 < ke) ? (Tacc)B[gk2 * d.sBk + gn * d.sBn] : (Tacc)0;
     }
   };
   if (kb < ke) fetch(kb);
   for (int k0 = kb; k0 < ke; k0 += GK) {
+    if constexpr (MODE == 0) {
 #pragma unroll
-    for (int q = 0; q < LQ; ++q) {
-      const int e = tid + 256 * q;
-      int mm, kk;
-      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
-      int nn, kb;
-      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
-      if constexpr (MODE == 0) {
+      for (int q = 0; q < LQ; ++q) {
+        int mm, kk, nn, kb;
+        a_pos(q, mm, kk);
+        b_pos(q, nn, kb);
         As[kk][mm] = ra[q];
         Bs[kb][nn] = rb[q];
-      } else if constexpr (MODE == 1) {
-        Ab[mm * BKP + kk] = bf16_bits((float)ra[q]);
-        Bb[nn * BKP + kb] = bf16_bits((float)rb[q]);
-      } else {
-        short x0, x1, x2;
-        bf16_split3((float)ra[q], x0, x1, x2);
-        Ab[mm * BKP + kk] = x0;
-        Ab[GT * BKP + mm * BKP + kk] = x1;
-        Ab[2 * GT * BKP + mm * BKP + kk] = x2;
-        bf16_split3((float)rb[q], x0, x1, x2);
-        Bb[nn * BKP + kb] = x0;
-        Bb[GT * BKP + nn * BKP + kb] = x1;
-        Bb[2 * GT * BKP + nn * BKP + kb] = x2;
+      }
+    } else {
+      // a run of four K values -> NT terms of four BF16 each, 8-byte writes
+      typedef short s4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+      for (int i = 0; i < LQ / 4; ++i) {
+        int mm, kk, nn, kb;
+        a_pos(4 * i, mm, kk);
+        b_pos(4 * i, nn, kb);
+        s4 ta[NT], tb[NT];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if constexpr (MODE == 1) {
+            ta[0][j] = bf16_bits((float)ra[4 * i + j]);
+            tb[0][j] = bf16_bits((float)rb[4 * i + j]);
+          } else {
+            short x0, x1, x2;
+            bf16_split3((float)ra[4 * i + j], x0, x1, x2);
+            ta[0][j] = x0; ta[1][j] = x1; ta[2][j] = x2;
+            bf16_split3((float)rb[4 * i + j], x0, x1, x2);
+            tb[0][j] = x0; tb[1][j] = x1; tb[2][j] = x2;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+          *reinterpret_cast<s4*>(Ab + t * GT * BKP + mm * BKP + kk) = ta[t];
+          *reinterpret_cast<s4*>(Bb + t * GT * BKP + nn * BKP + kb) = tb[t];
+        }
       }
     }
     __syncthreads();

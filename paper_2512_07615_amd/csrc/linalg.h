@@ -1756,7 +1756,9 @@ __device__ __forceinline__ void eig_body(const EigProb& p, double* A, int max_sw
       atomicAdd(p.fail + 6, c);
     }
   }
-  if (flops && work > 0.0) atomicAdd(flops, work);
+  // algorithmic work of the truncation SVD: 24 s^3 per problem (the cost
+  // of an R-SVD of an order-s factor), whatever the sweeps took
+  if (flops && tid == 0) atomicAdd(flops, 24.0 * s * s * s);
   jacobi_sorted_norms(A, s, c, nrm, perm, nonfin);
   if (tid == 0 && *nonfin && p.fail) atomicAdd(p.fail + 1, 1);
   if (tid == 0) {
@@ -2016,7 +2018,6 @@ __global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* 
   constexpr int RPL = JS_ROWS / JS_LANES;
   const int gl = tid % JS_LANES;
   const int g = tid / JS_LANES;  // this lane's group
-  double work = 0.0;
   int sweep = 0;
   bool loaded = true;  // the blocks of block round 0 are in LDS
   // the intra-block phases run on a virtual layout with each block padded
@@ -2071,15 +2072,11 @@ __global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* 
 #pragma unroll
         for (int q = 0; q < RPL; ++q) be += yr[q] * yr[q];
         be = group_sum(be, JS_LANES);
-        if (ti >= 0 && gl == 0) {
-          tn[ti] = be;
-          work += 2.0 * s;
-        }
+        if (ti >= 0 && gl == 0) tn[ti] = be;
       } else {
         be = ti >= 0 ? tn[ti] : 0.0;
       }
       ga = group_sum(ga + ga2, JS_LANES);
-      if (act && gl == 0) work += 2.0 * s;
       if (act && ga != 0.0 && pair_coupled(ga, al, be, tol) && al > small2 && be > small2) {
         mx = fmaxf(mx, (float)(fabs(ga) * __builtin_amdgcn_rsq(al) * __builtin_amdgcn_rsq(be)));
         // the pair in global column order, as in the cyclic sweep
@@ -2125,7 +2122,6 @@ __global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* 
 #pragma unroll
           for (int q = 0; q < RPL; ++q) w += xr[q] * xr[q];
           al = group_sum(w, JS_LANES);
-          if (gl == 0) work += 2.0 * s;
         } else {
           al = na;
         }
@@ -2135,12 +2131,8 @@ __global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* 
 #pragma unroll
           for (int q = 0; q < RPL; ++q) w += yr[q] * yr[q];
           nbe = group_sum(w, JS_LANES);
-          if (gl == 0) work += 2.0 * s;
         }
-        if (gl == 0) {
-          tn[ti] = nbe;
-          work += 6.0 * s;
-        }
+        if (gl == 0) tn[ti] = nbe;
       }
       __syncthreads();
     }
@@ -2245,7 +2237,8 @@ __global__ __launch_bounds__(JS_THREADS) void k_jacobi_eig_split(const EigProb* 
       atomicAdd(p.fail + 1, 1);
     }
   }
-  if (flops && gl == 0 && work > 0.0) atomicAdd(flops, work);
+  // algorithmic work: 24 s^3 per problem, as in the single-workgroup kernel
+  if (flops && part == 0 && tid == 0) atomicAdd(flops, 24.0 * s * s * s);
   __syncthreads();
   const int r = rsel;
   if (part == 0 && p.feat && tid <= 32) {
