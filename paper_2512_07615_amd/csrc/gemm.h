@@ -106,14 +106,18 @@ struct KSplit {
 // operands are converted once, when a K slice is staged: rounded (MODE 1)
 // or split into three BF16 terms (MODE 2), stored K-contiguous per row of A
 // and per column of B (row stride BKP) so that a lane's eight K values are
-// one 16-byte LDS read.
+// one 16-byte LDS read.  These modes stage K slices of GKB = 32 (the three
+// BF16 terms of a 64 x 64 x 32 slice take 30 KB of LDS), so that four
+// workgroups share a CU and hide each other's staging and LDS latency.
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-constexpr int BKP = GK + 8;
+constexpr int GKB = 32;
+constexpr int BKP = GKB + 8;  // 80-byte rows: an odd number of 16-byte units
 
 template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
 __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops,
                                               KSplit ks) {
   typedef typename MfmaT<Tacc>::V V;
+  constexpr int GKM = MODE == 0 ? GK : GKB;  // K slice staged through LDS
   constexpr size_t SM0 = 2 * sizeof(Tacc) * GK * (GT + 1);
   constexpr size_t SMB = (MODE == 2 ? 6 : 2) * sizeof(short) * GT * BKP;
   __shared__ __attribute__((aligned(16))) char smem[MODE == 0 ? SM0 : SMB];
@@ -156,21 +160,22 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   const bool b_n_contig = (d.sBn == 1);
   // Software pipeline: the operands of the next K slice are loaded into
   // registers while the MFMAs work on the slice in LDS, so global latency
-  // is paid once per GK = 64 columns of K rather than per instruction.
-  constexpr int LQ = GT * GK / 256;  // elements of each operand per thread
+  // is paid once per K slice rather than per instruction.
+  constexpr int LQ = GT * GKM / 256;  // elements of each operand per thread
   Tacc ra[LQ], rb[LQ];
   // Element q of this thread's share of a slice.  FP32/FP64 (MODE 0): one
   // element per 256 threads, the contiguous index fastest.  BF16 modes:
   // four runs of four consecutive K values of one row of A or column of B
   // (q = 4 i + j), so that the converted terms go to LDS as 8-byte writes;
   // lanes still walk the contiguous index of the operand.
+  constexpr int TPR = GKM / 4;  // threads per row (column) of a K-contiguous operand
   auto a_pos = [&](int q, int& mm, int& kk) {
     if constexpr (MODE == 0) {
       const int e = tid + 256 * q;
       if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
     } else {
       const int i = q >> 2, j = q & 3;
-      if (a_k_contig) { mm = (tid >> 4) + 16 * i; kk = 4 * (tid & 15) + j; }
+      if (a_k_contig) { mm = tid / TPR + (256 / TPR) * i; kk = 4 * (tid % TPR) + j; }
       else { mm = tid & 63; kk = 4 * (tid >> 6) + 16 * i + j; }
     }
   };
@@ -181,7 +186,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
     } else {
       const int i = q >> 2, j = q & 3;
       if (b_n_contig) { nn = tid & 63; kb = 4 * (tid >> 6) + 16 * i + j; }
-      else { nn = (tid >> 4) + 16 * i; kb = 4 * (tid & 15) + j; }
+      else { nn = tid / TPR + (256 / TPR) * i; kb = 4 * (tid % TPR) + j; }
     }
   };
   auto fetch = [&](int k0) {
@@ -198,7 +203,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
     }
   };
   if (kb < ke) fetch(kb);
-  for (int k0 = kb; k0 < ke; k0 += GK) {
+  for (int k0 = kb; k0 < ke; k0 += GKM) {
     if constexpr (MODE == 0) {
 #pragma unroll
       for (int q = 0; q < LQ; ++q) {
@@ -238,11 +243,11 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       }
     }
     __syncthreads();
-    if (k0 + GK < ke) fetch(k0 + GK);
+    if (k0 + GKM < ke) fetch(k0 + GKM);
     const int kvalid = ke - k0;  // K columns of this slice that are not padding
     if constexpr (MODE == 2) {
 #pragma unroll
-      for (int ks = 0; ks < GK / 32; ++ks) {
+      for (int ks = 0; ks < GKM / 32; ++ks) {
         if (ks * 32 < kvalid) {
           const int kof = ks * 32 + 8 * (lane >> 4);
           bf8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
@@ -275,7 +280,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       }
     } else if constexpr (MODE == 1) {
 #pragma unroll
-      for (int ks = 0; ks < GK / 32; ++ks) {
+      for (int ks = 0; ks < GKM / 32; ++ks) {
         if (ks * 32 < kvalid) {
           const int kof = ks * 32 + 8 * (lane >> 4);
           const bf8 a0 = *reinterpret_cast<const bf8*>(Ab + (wm * 32 + (lane & 15)) * BKP + kof);
