@@ -670,12 +670,16 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
             invr = invr * (1.5 - 0.5 * best * invr * invr);
             invr = invr * (1.5 - 0.5 * best * invr * invr);
             const double r = best * invr;
-            const double* gp = G + (long)p * n;  // row p (G is kept symmetric)
+            // row p of the Schur complement from its lower triangle (the
+            // only part the trailing updates keep): G[p][i] for i < p, the
+            // symmetric G[i][p] for i > p
             double gv[RQ];
 #pragma unroll
             for (int q = 0; q < RQ; ++q) {
               const int i = lane + 64 * q;
-              gv[q] = (d[q] > DONE && i != p) ? gp[i] : 0.0;
+              gv[q] = (d[q] > DONE && i != p)
+                          ? (i < p ? G[(long)p * n + i] : G[(long)i * n + p])
+                          : 0.0;
             }
 #pragma unroll
             for (int q = 0; q < RQ; ++q) {
@@ -723,19 +727,30 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
       __syncthreads();
       break;
     }
-    // trailing update G -= L L^T of the unpivoted rows and columns, 16 x 16
-    // tiles on FP64 MFMA (layouts as in chol_blocked); a wave first loads
-    // the entries of TU tiles, so that TU global reads are in flight at
-    // once, then updates and stores them
+    // trailing update G -= L L^T of the unpivoted rows and columns on the
+    // lower triangle of 16 x 16 tiles (the Schur complement is symmetric),
+    // on FP64 MFMA (layouts as in chol_blocked); a wave first loads the
+    // entries of TU tiles, so that TU global reads are in flight at once,
+    // then updates and stores them
     typedef double dv4 __attribute__((ext_vector_type(4)));
     constexpr int TU = 4;
-    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = nb * nb;
+    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = nb * (nb + 1) / 2;
+    // tile t of the lower triangle: block row tr, block column t - tr (tr + 1) / 2
+    auto tri = [](int t, int& a0, int& b0) {
+      int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
+      while ((r + 1) * (r + 2) / 2 <= t) ++r;
+      while (r * (r + 1) / 2 > t) --r;
+      a0 = 16 * r;
+      b0 = 16 * (t - r * (r + 1) / 2);
+    };
     for (int t0 = wv; t0 < ntile; t0 += nw * TU) {
       double gv[TU][4];
 #pragma unroll
       for (int u = 0; u < TU; ++u) {
         const int t = t0 + u * nw;
-        const int a0 = (t / nb) * 16, bc = (t % nb) * 16 + l16;
+        int a0, b0;
+        tri(t, a0, b0);
+        const int bc = b0 + l16;
         const bool okc = t < ntile && bc < n && posn[bc] == n;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -747,7 +762,8 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
       for (int u = 0; u < TU; ++u) {
         const int t = t0 + u * nw;  // the same in every lane of the wave
         if (t >= ntile) break;
-        const int a0 = (t / nb) * 16, b0 = (t % nb) * 16;
+        int a0, b0;
+        tri(t, a0, b0);
         const int ar = a0 + l16, bc = b0 + l16;
         dv4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
