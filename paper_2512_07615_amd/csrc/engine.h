@@ -1446,14 +1446,21 @@ class Engine {
   void pgemm(const F& f, int nprob, int mcap, int ncap, int bcap, hipStream_t s,
              double* flops = nullptr, int kcap = 0) {
     const int acc = bf16_products == 2 ? 3 : bf16_products == 1 ? 2 : sizeof(Tacc) == 8 ? 0 : 1;
-    const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap, acc);
+    int ts = GT;
+    const KSplit ks = ksplit(nprob, mcap, ncap, bcap, kcap, acc, &ts);
     if constexpr (std::is_same<T, float>::value) {
       if (bf16_products == 1) {
-        launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+        if (ts == 2 * GT)
+          launch_gemm<T, T, T, float, F, 1, 2 * GT>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+        else
+          launch_gemm<T, T, T, float, F, 1>(f, nprob, mcap, ncap, bcap, s, flops, ks);
         return;
       }
       if (bf16_products == 2) {
-        launch_gemm<T, T, T, float, F, 2>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+        if (ts == 2 * GT)
+          launch_gemm<T, T, T, float, F, 2, 2 * GT>(f, nprob, mcap, ncap, bcap, s, flops, ks);
+        else
+          launch_gemm<T, T, T, float, F, 2>(f, nprob, mcap, ncap, bcap, s, flops, ks);
         return;
       }
     }
@@ -1465,29 +1472,41 @@ class Engine {
   // (arithmetic, capacities, problem and batch counts) once it has been
   // tuned, else one share per 256 columns of K, at most 8.  The partial
   // tiles go to a workspace that grows on demand (the first, eager step
-  // reaches its peak before any capture).
+  // reaches its peak before any capture).  The BF16 product contractions
+  // also take their tile edge from the table (64, or 128 where it was
+  // faster; *ts), whatever their K.  A table entry holds the share count
+  // plus TILE128 for the larger tile.
   double* kws = nullptr;
   size_t kws_bytes = 0;
   typedef std::tuple<int, int, int, int, int, int> KClass;  // acc, m, n, k, nprob, batch
-  std::map<KClass, int> ktab;  // tuned share counts
+  std::map<KClass, int> ktab;  // tuned share counts (+ TILE128)
   std::set<KClass> kseen;      // classes met and not tuned yet
-  KSplit ksplit(int nprob, int mcap, int ncap, int bcap, int kcap, int acc = 0) {
-    if (kcap < 512 || nprob <= 0 || mcap <= 0 || ncap <= 0 || bcap <= 0) return KSplit{nullptr, 1};
+  static constexpr int TILE128 = 16;
+  KSplit ksplit(int nprob, int mcap, int ncap, int bcap, int kcap, int acc = 0,
+                int* ts = nullptr) {
+    if (ts) *ts = GT;
+    const bool bf16 = ts && acc >= 2;  // a product contraction on BF16 MFMA
+    if ((kcap < 512 && !bf16) || nprob <= 0 || mcap <= 0 || ncap <= 0 || bcap <= 0)
+      return KSplit{nullptr, 1};
     const KClass key(acc, mcap, ncap, kcap, nprob, bcap);
     int sp;
     auto it = ktab.find(key);
     if (it != ktab.end()) {
       sp = it->second;
+      if (sp & TILE128) {
+        if (ts) *ts = 2 * GT;
+        sp &= ~TILE128;
+      }
     } else {
       kseen.insert(key);
-      sp = std::min(8, kcap / 256);
+      sp = kcap < 512 ? 1 : std::min(8, kcap / 256);
     }
     if (sp < 2) return KSplit{nullptr, 1};
-    return KSplit{kworkspace(nprob, mcap, ncap, bcap, sp), sp};
+    return KSplit{kworkspace(nprob, mcap, ncap, bcap, sp, ts ? *ts : GT), sp};
   }
-  double* kworkspace(int nprob, int mcap, int ncap, int bcap, int sp) {
-    const size_t need = (size_t)nprob * bcap * ceil_div(mcap, GT) * ceil_div(ncap, GT) * sp *
-                        GT * GT * sizeof(double);
+  double* kworkspace(int nprob, int mcap, int ncap, int bcap, int sp, int tsz = GT) {
+    const size_t need = (size_t)nprob * bcap * ceil_div(mcap, tsz) * ceil_div(ncap, tsz) * sp *
+                        tsz * tsz * sizeof(double);
     if (need > kws_bytes) {
       kws = (double*)dalloc(need);
       kws_bytes = need;
@@ -1495,12 +1514,13 @@ class Engine {
     return kws;
   }
 
-  // ---- split-K autotuner ----------------------------------------------------
+  // ---- split-K and tile autotuner -------------------------------------------
   // Every class met since the last tuning is timed at its capacity shape on
   // scratch operands (one shared A and B, a C per problem and batch entry)
-  // for 1, 2, 4 and 8 shares of K (each share at least one slice of GK):
-  // one warm-up launch and three timed ones with HIP events per candidate;
-  // the fastest is kept.  Returns the number of classes tuned.
+  // for 1, 2, 4 and 8 shares of K (each share at least one slice of GK),
+  // and for the BF16 modes with tiles of 64 and of 128: one warm-up launch
+  // and three timed ones with HIP events per candidate; the fastest is kept.
+  // Returns the number of classes tuned.
   template <typename TA, int MODE>
   struct FTune {
     const TA* A; const TA* B; void* C; int M, N, K, nb;
@@ -1514,32 +1534,41 @@ class Engine {
       return d;
     }
   };
-  template <typename TA, typename Tacc, int MODE>
-  int tune_class(const KClass& c, void* A, void* B, void* C) {
+  template <typename TA, typename Tacc, int MODE, int TS>
+  void time_class(const KClass& c, void* A, void* B, void* C, hipEvent_t e0, hipEvent_t e1,
+                  int code, int& best, float& tbest) {
     int acc, m, nn, kk, np, nb;
     std::tie(acc, m, nn, kk, np, nb) = c;
     const FTune<TA, MODE> f{(const TA*)A, (const TA*)B, C, m, nn, kk, nb};
-    hipEvent_t e0, e1;
-    HIP_OK(hipEventCreate(&e0));
-    HIP_OK(hipEventCreate(&e1));
-    int best = 1;
-    float tbest = 1e30f;
     for (int sp = 1; sp <= 8; sp *= 2) {
-      if (sp > 1 && (long)sp * GK > kk) break;
-      const KSplit ks = sp > 1 ? KSplit{kworkspace(np, m, nn, nb, sp), sp} : KSplit{nullptr, 1};
-      launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE>(f, np, m, nn, nb, st, nullptr, ks);
+      if (sp > 1 && ((long)sp * GK > kk || kk < 512)) break;
+      const KSplit ks =
+          sp > 1 ? KSplit{kworkspace(np, m, nn, nb, sp, TS), sp} : KSplit{nullptr, 1};
+      launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE, TS>(f, np, m, nn, nb, st, nullptr, ks);
       HIP_OK(hipEventRecord(e0, st));
       for (int r = 0; r < 3; ++r)
-        launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE>(f, np, m, nn, nb, st, nullptr, ks);
+        launch_gemm<TA, TA, TA, Tacc, FTune<TA, MODE>, MODE, TS>(f, np, m, nn, nb, st, nullptr,
+                                                                 ks);
       HIP_OK(hipEventRecord(e1, st));
       HIP_OK(hipEventSynchronize(e1));
       float ms = 0.0f;
       HIP_OK(hipEventElapsedTime(&ms, e0, e1));
       if (ms < tbest) {
         tbest = ms;
-        best = sp;
+        best = sp | code;
       }
     }
+  }
+  template <typename TA, typename Tacc, int MODE>
+  int tune_class(const KClass& c, void* A, void* B, void* C) {
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    HIP_OK(hipEventCreate(&e1));
+    int best = 1;
+    float tbest = 1e30f;
+    time_class<TA, Tacc, MODE, GT>(c, A, B, C, e0, e1, 0, best, tbest);
+    if constexpr (MODE != 0)
+      time_class<TA, Tacc, MODE, 2 * GT>(c, A, B, C, e0, e1, TILE128, best, tbest);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     return best;

@@ -113,20 +113,25 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int GKB = 32;
 constexpr int BKP = GKB + 8;  // 80-byte rows: an odd number of 16-byte units
 
-template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
+// TS: tile edge, 64 or (BF16 modes) 128; each of the four waves computes
+// one (TS/2) x (TS/2) quarter of the tile.
+template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0,
+          int TS = GT>
 __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap, double* flops,
                                               KSplit ks) {
+  static_assert(TS == GT || (MODE != 0 && TS == 2 * GT), "tile edge");
   typedef typename MfmaT<Tacc>::V V;
   constexpr int GKM = MODE == 0 ? GK : GKB;  // K slice staged through LDS
+  constexpr int WT = TS / 2, NBW = WT / 16;  // a wave's quarter, in 16 x 16 blocks
   constexpr size_t SM0 = 2 * sizeof(Tacc) * GK * (GT + 1);
-  constexpr size_t SMB = (MODE == 2 ? 6 : 2) * sizeof(short) * GT * BKP;
+  constexpr size_t SMB = (MODE == 2 ? 6 : 2) * sizeof(short) * TS * BKP;
   __shared__ __attribute__((aligned(16))) char smem[MODE == 0 ? SM0 : SMB];
   Tacc (*As)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem);
   Tacc (*Bs)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem + sizeof(Tacc) * GK * (GT + 1));
-  // BF16 tiles: A terms [GT rows][BKP], then B terms [GT columns][BKP]
+  // BF16 tiles: A terms [TS rows][BKP], then B terms [TS columns][BKP]
   short* const Ab = reinterpret_cast<short*>(smem);
   constexpr int NT = MODE == 2 ? 3 : 1;
-  short* const Bb = Ab + NT * GT * BKP;
+  short* const Bb = Ab + NT * TS * BKP;
   long wg = blockIdx.x;
   const int kseg = (int)(wg % ks.split);
   wg /= ks.split;
@@ -137,8 +142,8 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   GemmDesc<TA, TB, TC> d = f.get(prob);
   if (!d.valid) return;
   if (b >= d.nb1 * d.nb2) return;
-  int tn = (d.N + GT - 1) / GT;
-  int tm = (d.M + GT - 1) / GT;
+  int tn = (d.N + TS - 1) / TS;
+  int tm = (d.M + TS - 1) / TS;
   if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
   if (flops && tile == 0 && kseg == 0 && threadIdx.x == 0) atomicAdd(flops, 2.0 * d.M * d.N * d.K);
   // share of K: [kb, ke)
@@ -149,19 +154,19 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   const TA* A = d.A + b1 * d.bA1 + b2 * d.bA2;
   const TB* B = d.B + b1 * d.bB1 + b2 * d.bB2;
   TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
-  int m0 = ti * GT, n0 = tj * GT;
+  int m0 = ti * TS, n0 = tj * TS;
   int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   int wm = w >> 1, wn = w & 1;
-  V acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j)
+  V acc[NBW][NBW];
+  for (int i = 0; i < NBW; ++i)
+    for (int j = 0; j < NBW; ++j)
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
   const bool a_k_contig = (d.sAk == 1);
   const bool b_n_contig = (d.sBn == 1);
   // Software pipeline: the operands of the next K slice are loaded into
   // registers while the MFMAs work on the slice in LDS, so global latency
   // is paid once per K slice rather than per instruction.
-  constexpr int LQ = GT * GKM / 256;  // elements of each operand per thread
+  constexpr int LQ = TS * GKM / 256;  // elements of each operand per thread
   Tacc ra[LQ], rb[LQ];
   // Element q of this thread's share of a slice.  FP32/FP64 (MODE 0): one
   // element per 256 threads, the contiguous index fastest.  BF16 modes:
@@ -176,7 +181,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
     } else {
       const int i = q >> 2, j = q & 3;
       if (a_k_contig) { mm = tid / TPR + (256 / TPR) * i; kk = 4 * (tid % TPR) + j; }
-      else { mm = tid & 63; kk = 4 * (tid >> 6) + 16 * i + j; }
+      else { mm = tid % TS; kk = 4 * (tid / TS) + 4 * (256 / TS) * i + j; }
     }
   };
   auto b_pos = [&](int q, int& nn, int& kb) {
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
     } else {
       const int i = q >> 2, j = q & 3;
-      if (b_n_contig) { nn = tid & 63; kb = 4 * (tid >> 6) + 16 * i + j; }
+      if (b_n_contig) { nn = tid % TS; kb = 4 * (tid / TS) + 4 * (256 / TS) * i + j; }
       else { nn = tid / TPR + (256 / TPR) * i; kb = 4 * (tid % TPR) + j; }
     }
   };
@@ -237,8 +242,8 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
         }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-          *reinterpret_cast<s4*>(Ab + t * GT * BKP + mm * BKP + kk) = ta[t];
-          *reinterpret_cast<s4*>(Bb + t * GT * BKP + nn * BKP + kb) = tb[t];
+          *reinterpret_cast<s4*>(Ab + t * TS * BKP + mm * BKP + kk) = ta[t];
+          *reinterpret_cast<s4*>(Bb + t * TS * BKP + nn * BKP + kb) = tb[t];
         }
       }
     }
@@ -250,22 +255,22 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       for (int ks = 0; ks < GKM / 32; ++ks) {
         if (ks * 32 < kvalid) {
           const int kof = ks * 32 + 8 * (lane >> 4);
-          bf8 ah[2], am[2], al[2], bh[2], bm[2], bl[2];
+          bf8 ah[NBW], am[NBW], al[NBW], bh[NBW], bm[NBW], bl[NBW];
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int ra_ = (wm * 32 + 16 * h + (lane & 15)) * BKP + kof;
-            const int cb_ = (wn * 32 + 16 * h + (lane & 15)) * BKP + kof;
+          for (int h = 0; h < NBW; ++h) {
+            const int ra_ = (wm * WT + 16 * h + (lane & 15)) * BKP + kof;
+            const int cb_ = (wn * WT + 16 * h + (lane & 15)) * BKP + kof;
             ah[h] = *reinterpret_cast<const bf8*>(Ab + ra_);
-            am[h] = *reinterpret_cast<const bf8*>(Ab + GT * BKP + ra_);
-            al[h] = *reinterpret_cast<const bf8*>(Ab + 2 * GT * BKP + ra_);
+            am[h] = *reinterpret_cast<const bf8*>(Ab + TS * BKP + ra_);
+            al[h] = *reinterpret_cast<const bf8*>(Ab + 2 * TS * BKP + ra_);
             bh[h] = *reinterpret_cast<const bf8*>(Bb + cb_);
-            bm[h] = *reinterpret_cast<const bf8*>(Bb + GT * BKP + cb_);
-            bl[h] = *reinterpret_cast<const bf8*>(Bb + 2 * GT * BKP + cb_);
+            bm[h] = *reinterpret_cast<const bf8*>(Bb + TS * BKP + cb_);
+            bl[h] = *reinterpret_cast<const bf8*>(Bb + 2 * TS * BKP + cb_);
           }
 #pragma unroll
-          for (int i = 0; i < 2; ++i)
+          for (int i = 0; i < NBW; ++i)
 #pragma unroll
-            for (int jj = 0; jj < 2; ++jj) {
+            for (int jj = 0; jj < NBW; ++jj) {
               // smallest terms first
               V c = acc[i][jj];
               c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[i], bh[jj], c, 0, 0, 0);
@@ -283,16 +288,17 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       for (int ks = 0; ks < GKM / 32; ++ks) {
         if (ks * 32 < kvalid) {
           const int kof = ks * 32 + 8 * (lane >> 4);
-          const bf8 a0 = *reinterpret_cast<const bf8*>(Ab + (wm * 32 + (lane & 15)) * BKP + kof);
-          const bf8 a1 =
-              *reinterpret_cast<const bf8*>(Ab + (wm * 32 + 16 + (lane & 15)) * BKP + kof);
-          const bf8 b0 = *reinterpret_cast<const bf8*>(Bb + (wn * 32 + (lane & 15)) * BKP + kof);
-          const bf8 b1 =
-              *reinterpret_cast<const bf8*>(Bb + (wn * 32 + 16 + (lane & 15)) * BKP + kof);
-          acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-          acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-          acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-          acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+          bf8 av[NBW], bv[NBW];
+#pragma unroll
+          for (int h = 0; h < NBW; ++h) {
+            av[h] = *reinterpret_cast<const bf8*>(Ab + (wm * WT + 16 * h + (lane & 15)) * BKP + kof);
+            bv[h] = *reinterpret_cast<const bf8*>(Bb + (wn * WT + 16 * h + (lane & 15)) * BKP + kof);
+          }
+#pragma unroll
+          for (int i = 0; i < NBW; ++i)
+#pragma unroll
+            for (int jj = 0; jj < NBW; ++jj)
+              acc[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv[jj], acc[i][jj], 0, 0, 0);
         }
       }
     } else {
@@ -315,28 +321,28 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   }
   if (ks.split > 1) {
     double* W = ks.ws + ((((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split + kseg) *
-                            (GT * GT);
+                            (TS * TS);
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < NBW; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j)
+      for (int j = 0; j < NBW; ++j)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int row = wm * 32 + i * 16 + MfmaT<Tacc>::row(lane, v);
-          const int col = wn * 32 + j * 16 + (lane & 15);
-          W[row * GT + col] = (double)acc[i][j][v];
+          const int row = wm * WT + i * 16 + MfmaT<Tacc>::row(lane, v);
+          const int col = wn * WT + j * 16 + (lane & 15);
+          W[row * TS + col] = (double)acc[i][j][v];
         }
     return;
   }
   const double alpha = d.alpha, beta = d.beta;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < NBW; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < NBW; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        int row = m0 + wm * 32 + i * 16 + MfmaT<Tacc>::row(lane, v);
-        int col = n0 + wn * 32 + j * 16 + (lane & 15);
+        int row = m0 + wm * WT + i * 16 + MfmaT<Tacc>::row(lane, v);
+        int col = n0 + wn * WT + j * 16 + (lane & 15);
         if (row < d.M && col < d.N) {
           TC* p = C + row * d.sCm + col * d.sCn;
           double val = alpha * (double)acc[i][j][v];
@@ -351,7 +357,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
 // each), so that one pass of loads covers a workgroup's part and the launch
 // spreads over RQ times as many CUs.
 constexpr int RQ = 8;
-template <typename TA, typename TB, typename TC, typename F>
+template <typename TA, typename TB, typename TC, typename F, int TS = GT>
 __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int batch_cap, KSplit ks) {
   long wg = blockIdx.x;
   const int part = (int)(wg % RQ);
@@ -363,16 +369,16 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
   GemmDesc<TA, TB, TC> d = f.get(prob);
   if (!d.valid) return;
   if (b >= d.nb1 * d.nb2) return;
-  int tn = (d.N + GT - 1) / GT;
-  int tm = (d.M + GT - 1) / GT;
+  int tn = (d.N + TS - 1) / TS;
+  int tm = (d.M + TS - 1) / TS;
   if (tile >= tm * tn || d.M <= 0 || d.N <= 0) return;
   int ti = tile / tn, tj = tile % tn;
   int b1 = b % d.nb1, b2 = b / d.nb1;
   TC* C = d.C + b1 * d.bC1 + b2 * d.bC2;
-  const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (GT * GT);
+  const double* W = ks.ws + (((long)prob * batch_cap + b) * tiles_cap + tile) * ks.split * (TS * TS);
   // two outputs per thread, the loads of all their shares issued together,
   // then each output summed in share order
-  constexpr int OUT = 2, PART = GT * GT / RQ;
+  constexpr int OUT = 2, PART = TS * TS / RQ;
   const int e_end = (part + 1) * PART;
   for (int e0 = part * PART + threadIdx.x; e0 < e_end; e0 += OUT * blockDim.x) {
     double v[OUT][8];
@@ -381,12 +387,12 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
       const int e = e0 + o * blockDim.x;
 #pragma unroll
       for (int q = 0; q < 8; ++q)
-        v[o][q] = (e < e_end && q < ks.split) ? W[(long)q * (GT * GT) + e] : 0.0;
+        v[o][q] = (e < e_end && q < ks.split) ? W[(long)q * (TS * TS) + e] : 0.0;
     }
 #pragma unroll
     for (int o = 0; o < OUT; ++o) {
       const int e = e0 + o * blockDim.x;
-      const int row = ti * GT + e / GT, col = tj * GT + e % GT;
+      const int row = ti * TS + e / TS, col = tj * TS + e % TS;
       if (e >= e_end || row >= d.M || col >= d.N) continue;
       double sum = 0.0;
 #pragma unroll
@@ -402,20 +408,21 @@ __global__ __launch_bounds__(256) void k_gemm_reduce(F f, int tiles_cap, int bat
 
 // Launch helper: grid = nprob * batch_cap * tiles_cap (each host-known caps),
 // times ks.split when K is split (ks.ws then holds
-// nprob * batch_cap * tiles_cap * split tiles of GT x GT doubles).
-template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0>
+// nprob * batch_cap * tiles_cap * split tiles of TS x TS doubles).
+template <typename TA, typename TB, typename TC, typename Tacc, typename F, int MODE = 0,
+          int TS = GT>
 inline void launch_gemm(const F& f, int nprob, int mcap, int ncap, int batch_cap,
                         hipStream_t s, double* flops = nullptr, KSplit ks = KSplit{nullptr, 1}) {
   if (nprob <= 0 || mcap <= 0 || ncap <= 0 || batch_cap <= 0) return;
   if (ks.split < 1 || !ks.ws) ks.split = 1;
-  int tiles = ceil_div(mcap, GT) * ceil_div(ncap, GT);
+  int tiles = ceil_div(mcap, TS) * ceil_div(ncap, TS);
   long grid = (long)nprob * batch_cap * tiles;
   if (grid <= 0) return;
-  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE>), dim3((unsigned)(grid * ks.split)),
+  hipLaunchKernelGGL((k_gemm<TA, TB, TC, Tacc, F, MODE, TS>), dim3((unsigned)(grid * ks.split)),
                      dim3(256), 0, s, f, tiles, batch_cap, flops, ks);
   if (ks.split > 1)
-    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, F>), dim3((unsigned)(grid * RQ)), dim3(256), 0,
-                       s, f, tiles, batch_cap, ks);
+    hipLaunchKernelGGL((k_gemm_reduce<TA, TB, TC, F, TS>), dim3((unsigned)(grid * RQ)), dim3(256),
+                       0, s, f, tiles, batch_cap, ks);
   HIP_OK(hipGetLastError());
 }
 

@@ -506,7 +506,9 @@ def test_vascular128_full_size_velocity_vs_oracle():
     stored at 6000 seeded fluid cells (tests/golden, written by the
     committed script beside it, which calls only the oracle); the relative
     L2 difference over those cells must stay below the 1e-4 asked of the
-    reduced-precision step."""
+    reduced-precision step.  Between the two steps the contraction
+    autotuner runs, as in the benchmark, so that the second step uses the
+    tuned split-K counts and tile edges."""
     import os
     L = lib()
     path = os.path.join(os.path.dirname(__file__), "golden",
@@ -520,7 +522,9 @@ def test_vascular128_full_size_velocity_vs_oracle():
     for prec in ("fp32", "bf16x3"):
         print("vascular128 chi128", prec, "two steps", flush=True)
         s = L.Simulation(case, precision=prec)
-        s.step(2)
+        s.step(1)
+        print("vascular128", prec, "classes tuned", s.autotune(), flush=True)
+        s.step(1)
         vel = s.dense(L.VEL)
         o = s.observables()
         s.close()
