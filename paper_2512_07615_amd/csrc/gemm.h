@@ -121,13 +121,15 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
                                               KSplit ks) {
   static_assert(TS == GT || (MODE != 0 && TS == 2 * GT), "tile edge");
   typedef typename MfmaT<Tacc>::V V;
-  constexpr int GKM = MODE == 0 ? GK : GKB;  // K slice staged through LDS
+  // K slice staged through LDS: 64 for FP32, 32 for FP64 (34 KB of LDS, so
+  // that four workgroups share a CU) and the BF16 modes
+  constexpr int GKM = (MODE == 0 && sizeof(Tacc) == 4) ? GK : GKB;
   constexpr int WT = TS / 2, NBW = WT / 16;  // a wave's quarter, in 16 x 16 blocks
-  constexpr size_t SM0 = 2 * sizeof(Tacc) * GK * (GT + 1);
+  constexpr size_t SM0 = 2 * sizeof(Tacc) * GKM * (GT + 1);
   constexpr size_t SMB = (MODE == 2 ? 6 : 2) * sizeof(short) * TS * BKP;
   __shared__ __attribute__((aligned(16))) char smem[MODE == 0 ? SM0 : SMB];
   Tacc (*As)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem);
-  Tacc (*Bs)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem + sizeof(Tacc) * GK * (GT + 1));
+  Tacc (*Bs)[GT + 1] = reinterpret_cast<Tacc (*)[GT + 1]>(smem + sizeof(Tacc) * GKM * (GT + 1));
   // BF16 tiles: A terms [TS rows][BKP], then B terms [TS columns][BKP]
   short* const Ab = reinterpret_cast<short*>(smem);
   constexpr int NT = MODE == 2 ? 3 : 1;
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   auto a_pos = [&](int q, int& mm, int& kk) {
     if constexpr (MODE == 0) {
       const int e = tid + 256 * q;
-      if (a_k_contig) { mm = e / GK; kk = e % GK; } else { mm = e % GT; kk = e / GT; }
+      if (a_k_contig) { mm = e / GKM; kk = e % GKM; } else { mm = e % GT; kk = e / GT; }
     } else {
       const int i = q >> 2, j = q & 3;
       if (a_k_contig) { mm = tid / TPR + (256 / TPR) * i; kk = 4 * (tid % TPR) + j; }
@@ -187,7 +189,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
   auto b_pos = [&](int q, int& nn, int& kb) {
     if constexpr (MODE == 0) {
       const int e = tid + 256 * q;
-      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GK; kb = e % GK; }
+      if (b_n_contig) { kb = e / GT; nn = e % GT; } else { nn = e / GKM; kb = e % GKM; }
     } else {
       const int i = q >> 2, j = q & 3;
       if (b_n_contig) { nn = tid % TS; kb = 4 * (tid / TS) + 4 * (256 / TS) * i + j; }
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(256) void k_gemm(F f, int tiles_cap, int batch_cap,
       }
     } else {
 #pragma unroll
-      for (int ks = 0; ks < GK / 4; ++ks) {
+      for (int ks = 0; ks < GKM / 4; ++ks) {
         if (ks * 4 < kvalid) {
           int kr = ks * 4 + (lane >> 4);
           Tacc a0 = As[kr][wm * 32 + (lane & 15)];

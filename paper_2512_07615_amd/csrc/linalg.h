@@ -733,7 +733,7 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
     // entries of TU tiles, so that TU global reads are in flight at once,
     // then updates and stores them
     typedef double dv4 __attribute__((ext_vector_type(4)));
-    constexpr int TU = 4;
+    constexpr int TU = 8;
     const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = nb * (nb + 1) / 2;
     // tile t of the lower triangle: block row tr, block column t - tr (tr + 1) / 2
     auto tri = [](int t, int& a0, int& b0) {
