@@ -793,7 +793,8 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
   __syncthreads();
 }
 
-// Body of k_chol_piv for G in LDS or in global memory.
+// Body of k_chol_piv for G in LDS or in global memory (NT threads).
+template <int NT>
 __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, double* Bbase,
                                           double* Rbase, int* rank_out, double eps_rank,
                                           int want_b, int* perm, double* red, int* ired,
@@ -950,49 +951,70 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
     }
   }
   __syncthreads();
-  if (regs) {
-    // Orders up to 128 with 16 waves: each level's two products on FP64 MFMA
-    // (16 x 16 x 4), one wave per 16 x 16 output tile (at most 16 tiles a
-    // level).  Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16] and
-    // holds the results of column l % 16, rows l / 16 + 4 v.  Out-of-range
-    // operands enter as zeros; the triangular factors contribute only their
-    // nonzero K range.
+  // Each level's two products on FP64 MFMA (16 x 16 x 4), one wave per
+  // 16 x 16 output tile: orders up to 128 with 16 waves (at most 16 tiles a
+  // level, one per wave), and in the 512-thread kernel orders up to 256 with
+  // 8 waves (at most 64 tiles a level, MT per wave; R11 usually in global
+  // memory there, where the scalar products below would wait on every load).  Lane l
+  // supplies A[l % 16][l / 16] and B[l / 16][l % 16] and holds the results
+  // of column l % 16, rows l / 16 + 4 v.  Out-of-range operands enter as
+  // zeros; the triangular factors contribute only their nonzero K range.
+  constexpr int MT = NT <= CHOL_WIDE_THREADS ? 8 : 1;
+  const bool mlev = regs || (NT <= CHOL_WIDE_THREADS && nw * MT >= 64);
+  if (mlev) {
     typedef double dv4 __attribute__((ext_vector_type(4)));
     const int l16 = lane & 15, lq = lane >> 4;
     for (int b = IB; b < rho; b *= 2) {
-      int tile = wv, tp = -1, tI = 0, tJ = 0, tbc = 0;
-      for (int p = 0; p + b < rho; p += 2 * b) {
-        const int bc = rho - p - b < b ? rho - p - b : b;
-        const int ncol = (bc + 15) / 16, nt = (b / 16) * ncol;
-        if (tile < nt) {
-          tp = p;
-          tI = (tile / ncol) * 16;
-          tJ = (tile % ncol) * 16;
-          tbc = bc;
-          break;
+      // tile number `tile` of the level: pair at p, block row tI, column tJ
+      auto find = [&](int tile, int& tp, int& tI, int& tJ, int& tbc) {
+        tp = -1;
+        for (int p = 0; p + b < rho; p += 2 * b) {
+          const int bc = rho - p - b < b ? rho - p - b : b;
+          const int ncol = (bc + 15) / 16, nt = (b / 16) * ncol;
+          if (tile < nt) {
+            tp = p;
+            tI = (tile / ncol) * 16;
+            tJ = (tile % ncol) * 16;
+            tbc = bc;
+            return;
+          }
+          tile -= nt;
         }
-        tile -= nt;
-      }
+      };
       // U = X11 R12: X11[i][t] is xd[i] on the diagonal and sits in the
-      // lower slot (t, i) above it; R12[t][c] in the upper slot (t, c)
-      dv4 acc = {0.0, 0.0, 0.0, 0.0};
-      if (tp >= 0) {
-        const int ia = tp + tI + l16, cb = tp + b + tJ + l16;
-        const bool cok = tJ + l16 < tbc;
-        for (int k0 = tI; k0 < b; k0 += 4) {
-          const int t = tp + k0 + lq;
-          const double a = t < ia ? 0.0 : (t == ia ? xd[ia] : G[(long)t * rho + sk(ia + t)]);
-          const double bv = cok ? G[(long)t * rho + sk(cb + t)] : 0.0;
-          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+      // lower slot (t, i) above it; R12[t][c] in the upper slot (t, c).  A
+      // wave keeps its tiles' results until every wave has read R12.
+      dv4 ures[MT];
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        int tp, tI = 0, tJ = 0, tbc = 0;
+        find(wv + q * nw, tp, tI, tJ, tbc);  // the same in every lane of the wave
+        dv4 acc = {0.0, 0.0, 0.0, 0.0};
+        if (tp >= 0) {
+          const int ia = tp + tI + l16, cb = tp + b + tJ + l16;
+          const bool cok = tJ + l16 < tbc;
+#pragma unroll 4
+          for (int k0 = tI; k0 < b; k0 += 4) {
+            const int t = tp + k0 + lq;
+            const double a = t < ia ? 0.0 : (t == ia ? xd[ia] : G[(long)t * rho + sk(ia + t)]);
+            const double bv = cok ? G[(long)t * rho + sk(cb + t)] : 0.0;
+            acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+          }
         }
+        ures[q] = acc;
       }
       __syncthreads();
-      if (tp >= 0 && tJ + l16 < tbc) {
-        const int c = tp + b + tJ + l16;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int ig = tp + tI + lq + 4 * v;
-          G[(long)ig * rho + sk(c + ig)] = acc[v];
+      for (int q = 0; q < MT; ++q) {
+        int tp, tI = 0, tJ = 0, tbc = 0;
+        find(wv + q * nw, tp, tI, tJ, tbc);
+        if (tp >= 0 && tJ + l16 < tbc) {
+          const int c = tp + b + tJ + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            const int ig = tp + tI + lq + 4 * v;
+            G[(long)ig * rho + sk(c + ig)] = ures[q][v];
+          }
         }
       }
       __syncthreads();
@@ -1000,11 +1022,16 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
       // on the diagonal and sits in the lower slot (c, t) above it.  The
       // results go to the lower slots (c, i), which no product of this level
       // reads
-      acc = dv4{0.0, 0.0, 0.0, 0.0};
-      if (tp >= 0) {
+#pragma unroll
+      for (int q = 0; q < MT; ++q) {
+        int tp, tI = 0, tJ = 0, tbc = 0;
+        find(wv + q * nw, tp, tI, tJ, tbc);
+        if (tp < 0) continue;
+        dv4 acc = {0.0, 0.0, 0.0, 0.0};
         const int ia = tp + tI + l16, cb = tp + b + tJ + l16;
         const bool cok = tJ + l16 < tbc;
         const int kend = tJ + 16 < tbc ? tJ + 16 : tbc;
+#pragma unroll 4
         for (int k0 = 0; k0 < kend; k0 += 4) {
           const int kt = k0 + lq, t = tp + b + kt;
           const double a = kt < tbc ? G[(long)ia * rho + sk(t + ia)] : 0.0;
@@ -1024,7 +1051,7 @@ __device__ __forceinline__ void chol_body(double* G, int n, int pr, long sq, dou
       __syncthreads();
     }
   }
-  for (int b = IB; b < rho && !regs; b *= 2) {
+  for (int b = IB; b < rho && !mlev; b *= 2) {
     // U = X11 R12 (rows [p, p+b), columns [p+b, p+b+bc)); at most rho b / 2
     // entries, so at most 4 per thread when staged through registers
     double u[4];
@@ -1157,15 +1184,15 @@ __device__ __forceinline__ void chol_piv_kernel_body(const int* dims, int dim_st
   }
   if ((long)n * n <= lds_elems) {
     block_copy(sh, Gg, (long)n * n);
-    chol_body(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+    chol_body<NT>(sh, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, n <= CPB_MAXN ? Lp : nullptr, &kdone, rank_stride);
   } else if (NT <= CHOL_WIDE_THREADS && n <= CHOL_WIDE_MAXN &&
              (long)n * LPS <= lds_elems) {
     // the panel of L in the (otherwise unused) dynamic LDS
-    chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+    chol_body<NT>(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, sh, &kdone, rank_stride, true);
   } else {
-    chol_body(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
+    chol_body<NT>(Gg, n, pr, sq, Bbase, Rbase, rank_out, eps_rank, want_b, perm, red, ired, &rho_s,
               &dmax0, &dpiv, xd, nullptr, &kdone, rank_stride);
   }
   if (dims_next && threadIdx.x == 0) dims_next[pr] = rank_out[(long)pr * rank_stride];
