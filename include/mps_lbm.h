@@ -386,12 +386,16 @@ int mps_lbm_kernel_timing(mps_lbm_t* h, int kind);
    stream).  Errors: EINVAL (NULL handle or out), EHIP. */
 int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out);
 
-/* Autotune the split of K of the long contractions (K capacity above
-   512): every contraction class met in the steps taken so far (arithmetic,
-   capacities M, N, K, problem and batch counts) is timed on scratch
-   operands of its capacity shape for 1, 2, 4 and 8 shares of K, and later
-   steps use the fastest (untuned classes use one share per 256 columns of
-   K).  Allocates and frees scratch memory; synchronises the stream.
+/* Autotune the contractions: the split of K of the long ones (K capacity
+   above 512) and, for the product contractions on BF16 matrix cores, the
+   tile edge (64 or 128).  Every contraction class met in the steps taken
+   so far (arithmetic, capacities M, N, K, problem and batch counts) is
+   timed on scratch operands of its capacity shape for 1, 2, 4 and 8 shares
+   of K (and both tile edges where they apply), and later steps use the
+   fastest (untuned classes use one share per 256 columns of K and tiles of
+   64).  The tile edge changes no result bit; the share count changes the
+   summation order.  Allocates and frees scratch memory; synchronises the
+   stream.
    *classes_tuned (may be NULL) receives the number of classes tuned.
    Errors: EINVAL (NULL handle, no step taken), EUNSUPPORTED (after graph
    capture), ENOMEM, EHIP. */
