@@ -393,8 +393,8 @@ int mps_lbm_kernel_stats(mps_lbm_t* h, mps_lbm_kstats* out);
    timed on scratch operands of its capacity shape for 1, 2, 4 and 8 shares
    of K (and both tile edges where they apply), and later steps use the
    fastest (untuned classes use one share per 256 columns of K and tiles of
-   64).  The tile edge changes no result bit; the share count changes the
-   summation order.  Allocates and frees scratch memory; synchronises the
+   64).  The tile edge keeps each output's summation order; the share
+   count changes it.  Allocates and frees scratch memory; synchronises the
    stream.
    *classes_tuned (may be NULL) receives the number of classes tuned.
    Errors: EINVAL (NULL handle, no step taken), EUNSUPPORTED (after graph
