@@ -727,14 +727,29 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
       __syncthreads();
       break;
     }
-    // trailing update G -= L L^T of the unpivoted rows and columns on the
-    // lower triangle of 16 x 16 tiles (the Schur complement is symmetric),
-    // on FP64 MFMA (layouts as in chol_blocked); a wave first loads the
-    // entries of TU tiles, so that TU global reads are in flight at once,
-    // then updates and stores them
+    // trailing update G -= L L^T of the unpivoted rows and columns, on the
+    // lower triangle of 16 x 16 tiles (the Schur complement is symmetric) of
+    // the unpivoted indices listed in increasing order (up), so that the
+    // tiles shrink with the complement; FP64 MFMA (layouts as in
+    // chol_blocked); a wave first loads the entries of TU tiles, so that TU
+    // global reads are in flight at once, then updates and stores them
+    int* const up = perm + 768;
+    __shared__ int wtot[16];
+    {
+      const bool f = tid < n && posn[tid] == n;
+      const unsigned long long bal = __ballot(f);
+      if (lane == 0) wtot[wv] = __popcll(bal);
+      __syncthreads();
+      int off = 0;
+      for (int w = 0; w < wv; ++w) off += wtot[w];
+      if (f) up[off + __popcll(bal & ((1ull << lane) - 1ull))] = tid;
+      __syncthreads();
+    }
+    int m = 0;
+    for (int w = 0; w < nw; ++w) m += wtot[w];
     typedef double dv4 __attribute__((ext_vector_type(4)));
     constexpr int TU = 8;
-    const int nb = (n + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = nb * (nb + 1) / 2;
+    const int mb = (m + 15) / 16, l16 = lane & 15, lq = lane >> 4, ntile = mb * (mb + 1) / 2;
     // tile t of the lower triangle: block row tr, block column t - tr (tr + 1) / 2
     auto tri = [](int t, int& a0, int& b0) {
       int r = (int)((sqrtf(8.0f * (float)t + 1.0f) - 1.0f) * 0.5f);
@@ -751,11 +766,12 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
         int a0, b0;
         tri(t, a0, b0);
         const int bc = b0 + l16;
-        const bool okc = t < ntile && bc < n && posn[bc] == n;
+        const bool okc = t < ntile && bc < m;
+        const long cg = okc ? up[bc] : 0;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
           const int a = a0 + lq + 4 * v;
-          gv[u][v] = (okc && a < n && posn[a] == n) ? G[(long)a * n + bc] : 0.0;
+          gv[u][v] = (okc && a < m) ? G[(long)up[a] * n + cg] : 0.0;
         }
       }
 #pragma unroll
@@ -765,18 +781,19 @@ __device__ __forceinline__ void chol_blocked_wide(double* G, int n, double thr, 
         int a0, b0;
         tri(t, a0, b0);
         const int ar = a0 + l16, bc = b0 + l16;
+        const int pr = ar < m ? up[ar] : 0, pc = bc < m ? up[bc] : 0;
         dv4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int q0 = 0; q0 < CPB; q0 += 4) {
-          const double x = ar < n ? Lp[ar * LPS + q0 + lq] : 0.0;
-          const double y = bc < n ? Lp[bc * LPS + q0 + lq] : 0.0;
+          const double x = ar < m ? Lp[pr * LPS + q0 + lq] : 0.0;
+          const double y = bc < m ? Lp[pc * LPS + q0 + lq] : 0.0;
           acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, y, acc, 0, 0, 0);
         }
-        if (bc < n && posn[bc] == n) {
+        if (bc < m) {
 #pragma unroll
           for (int v = 0; v < 4; ++v) {
             const int a = a0 + lq + 4 * v;
-            if (a < n && posn[a] == n) G[(long)a * n + bc] = gv[u][v] - acc[v];
+            if (a < m) G[(long)up[a] * n + pc] = gv[u][v] - acc[v];
           }
         }
       }
