@@ -421,14 +421,16 @@ def test_learned_rank_predictor_end_to_end():
     assert d < 50 * case.tol
 
 
-def test_split_autotuner_keeps_the_step():
-    """The split-K autotuner retimes the long contractions met in a step and
-    picks their share counts; the step it then runs differs from the
-    untuned one only by the summation order of those contractions."""
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_split_autotuner_keeps_the_step(prec):
+    """The autotuner retimes the contractions met in a step and picks their
+    share counts of K (and, for the products on BF16 matrix cores, their
+    tile edge); the step it then runs differs from the untuned one only by
+    the summation order of the contractions whose share count changed."""
     L = lib()
     case = _case_with_flow(WL.case_porous(n=5, chi=64, tol=1e-8), seed=4)
-    a = L.Simulation(case, precision="fp32")
-    b = L.Simulation(case, precision="fp32")
+    a = L.Simulation(case, precision=prec)
+    b = L.Simulation(case, precision=prec)
     a.step(1)
     b.step(1)
     tuned = a.autotune()
@@ -439,7 +441,7 @@ def test_split_autotuner_keeps_the_step():
     a.close()
     b.close()
     d = float(np.sqrt(((fa - fb) ** 2).sum() / (fb ** 2).sum()))
-    print("classes tuned", tuned, "rel L2 tuned/untuned", d, flush=True)
+    print(prec, "classes tuned", tuned, "rel L2 tuned/untuned", d, flush=True)
     assert tuned > 0
     assert d < 1e-4
 
